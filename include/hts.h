@@ -1,0 +1,205 @@
+/*
+ * hts.h - C ABI of the MI355X (gfx950) Haar-tSVD denoiser hot path.
+ *
+ * Haar-tSVD (arXiv 2508.10307): for every reference patch of a noisy image,
+ * find its K most similar patches in a local window (Sec. III.A, Eq. 10),
+ * project the stacked group on a global t-SVD patch basis learned from all
+ * reference patches (Sec. III.B.1, Eq. 11-12) combined with a Haar transform
+ * along the group mode (Eq. 17-18), hard-threshold the coefficients (Eq. 19),
+ * invert both transforms (Eq. 20) and average every estimate back into the
+ * image (Eq. 2, Alg. 1 Step 3).  The paper states the problem as: noisy image
+ * Y, patch size ps, group size K, window W and noise level sigma in, the
+ * estimated clean image out (Alg. 1).
+ *
+ * Conventions shared by every entry point
+ *  - Images are planar float32 [C][H][W], contiguous, in device memory.
+ *    C is 1 or 3; ps must be 8.
+ *  - Reference grid: top-left corners 0, s, 2s, ... along each axis plus the
+ *    last valid position H-ps (resp. W-ps); references are numbered
+ *    row-major over that grid (n_ref = n_ref_y * n_ref_x).
+ *  - Match indices are int32 [n_ref][K]; entry = y*W + x of a patch's
+ *    top-left corner.  Slot 0 is the reference itself, slots 1..K-1 the K-1
+ *    closest other candidates of the truncated window ordered by
+ *    (distance, index).  Distances are exact integers on the guide
+ *    q = round_half_even(256*y) clamped to |q| <= 2^20-1; for C = 3 the guide
+ *    of a reference is its green channel when
+ *    gcp_num^2*|qG|^2 >= gcp_den^2*max(|qR|^2,|qB|^2) (Eq. 10 with
+ *    gamma = gcp_num/gcp_den) and R+G+B otherwise.
+ *  - Basis tensors U, V are float32 [C][ps][ps] (frontal slice j = U(:,:,j)).
+ *  - Threshold masks are bit-packed: bit ((g*K + k)*C + ch)*64 + i*8 + j of a
+ *    little-endian uint32 stream is 1 when Haar-t-SVD coefficient (k, ch, i, j)
+ *    of group g survived the hard threshold (k = row of the K x K Haar matrix
+ *    of Eq. 9, i/j = row/column of the projected patch).
+ *  - Ownership: the caller owns every buffer, including the workspace sized
+ *    by hts_workspace_size(); the library never allocates device memory.
+ *  - Every call is asynchronous on `stream` (a hipStream_t; NULL = the null
+ *    stream).  A returned status covers argument validation and launch
+ *    errors; on any error nothing is launched.  Device faults surface at the
+ *    caller's next synchronisation.  No C++ exception crosses this ABI.
+ *  - Non-finite inputs: NaN quantises to 0 and +-inf to the clamp for
+ *    matching; the filter propagates them into the output.
+ */
+#ifndef HTS_H
+#define HTS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HTS_OK = 0,
+  HTS_ERR_INVALID = 1,      /* bad argument (null pointer, sizes, K, window...) */
+  HTS_ERR_UNSUPPORTED = 2,  /* valid per the paper but not built (C not 1/3, ps != 8) */
+  HTS_ERR_WORKSPACE = 3,    /* workspace too small */
+  HTS_ERR_HIP = 4           /* a HIP runtime call or launch failed */
+} hts_status;
+
+typedef enum {
+  HTS_MATCH_BF16 = 0,       /* norm+dot distance tiles on BF16 MFMA (FP32 accumulate) */
+  HTS_MATCH_FP32 = 1        /* plain FP32 SSD tiles on the vector ALUs (no MFMA) */
+} hts_match_mode;
+
+enum {
+  HTS_FLAG_DETERMINISTIC = 1  /* aggregation via ordered tile partials, no float atomics */
+};
+
+typedef struct {
+  int32_t ps;          /* patch size; must be 8                                  */
+  int32_t stride;      /* reference stride s, 1 <= s <= ps                        */
+  int32_t window;      /* odd full search-window width w, 3 <= w <= 63            */
+  int32_t K;           /* group size, power of two, 2 <= K <= 64 (32 for C = 3)   */
+  float tau_mult;      /* lambda: hard threshold tau = lambda * sigma (Eq. 19)    */
+  int32_t gcp_num;     /* gamma = gcp_num / gcp_den (Eq. 10; 6/5 = 1.2), 1..64    */
+  int32_t gcp_den;
+  int32_t match_mode;  /* hts_match_mode                                          */
+  int32_t flags;       /* HTS_FLAG_*                                              */
+  int32_t tune;        /* 0 = autotuned/default launch schedule, else a schedule id */
+} hts_params;
+
+/* Fill *p with the defaults: ps 8, stride 3, window 21, K 16, lambda 2.7,
+ * gamma 6/5, BF16 matching, flags 0, tune 0. */
+void hts_default_params(hts_params* p);
+
+/* Number of references along each axis (reference grid, see above). */
+hts_status hts_ref_grid(int32_t H, int32_t W, const hts_params* p,
+                        int32_t* n_ref_y, int32_t* n_ref_x);
+
+/* Workspace bytes needed by hts_match / hts_basis / hts_filter / hts_denoise
+ * for one C x H x W image. */
+hts_status hts_workspace_size(const hts_params* p, int32_t C, int32_t H, int32_t W,
+                              size_t* bytes);
+
+/* Alg. 1 Step 1 (Sec. III.A, Eq. 10): block matching of every reference.
+ * idx   out, int32 [n_ref][K] (device).
+ * dist  out, nullable, int64 [n_ref][K]: exact guide distances (slot 0 = 0).
+ * green out, nullable, uint8 [n_ref]: 1 when the reference used the green guide.
+ * Distance tiles run in p->match_mode; the shortlist they produce is
+ * certified by an error bound and re-ranked exactly, so idx does not depend
+ * on the mode. */
+hts_status hts_match(const hts_params* p, const float* noisy, int32_t C, int32_t H,
+                     int32_t W, int32_t* idx, int64_t* dist, uint8_t* green,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* Alg. 1 Step 2(1) (Sec. III.B.1, Eq. 11-12): global basis from all
+ * reference patches.  Covariances are accumulated and eigen-decomposed in
+ * FP64 on the device, per frequency of the channel-mode DFT (descending
+ * eigenvalues; each eigenvector scaled by a unit-modulus factor so that its
+ * largest-modulus entry is real positive).
+ * U, V    out, float32 [C][ps][ps] (device).
+ * U64,V64 out, nullable, float64 [C][ps][ps].
+ * eig     out, nullable, float64 [2][C/2+1][ps]: eigenvalues of the row (U)
+ *         and column (V) covariances per frequency, descending. */
+hts_status hts_basis(const hts_params* p, const float* noisy, int32_t C, int32_t H,
+                     int32_t W, float* U, float* V, double* U64, double* V64, double* eig,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* Alg. 1 Step 2(2)-(4) (Eq. 18-20) for references [ref_begin, ref_begin+ref_count):
+ * gather each group, project with U^T * . * V (t-product) and H_K along the
+ * group, keep coefficients with |s| >= tau_mult*sigma, invert.
+ * idx        in, int32 [n_ref][K] (all references of the image).
+ * U, V       in, float32 [C][ps][ps].
+ * num, cnt   in/out, nullable together: estimates are ADDED into
+ *            num float32 [C][H][W] and coverage counts into cnt float32 [H][W]
+ *            (Eq. 2 numerator and denominator); the caller zeroes them first.
+ * group_est  out, nullable, float32 [ref_count][K][C][ps][ps].
+ * masks      out, nullable, bit-packed keep-masks of the ref_count groups
+ *            (ceil(ref_count*K*C*64/32) uint32 words; group index relative
+ *            to ref_begin). */
+hts_status hts_filter(const hts_params* p, const float* noisy, int32_t C, int32_t H,
+                      int32_t W, float sigma, const int32_t* idx, const float* U,
+                      const float* V, int32_t ref_begin, int32_t ref_count, float* num,
+                      float* cnt, float* group_est, uint32_t* masks, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* Alg. 1 Step 3 / Eq. 2 with uniform weights (estimates averaged).
+ * group_est nullable: when given, the estimates of references
+ *           [ref_begin, ref_begin+ref_count) are added into num / cnt at the
+ *           positions idx gives.
+ * out       nullable: when given, out = num / cnt (every pixel has cnt >= 1). */
+hts_status hts_aggregate(const hts_params* p, const float* group_est, const int32_t* idx,
+                         int32_t ref_begin, int32_t ref_count, int32_t C, int32_t H,
+                         int32_t W, float* num, float* cnt, float* out, void* stream);
+
+/* Algorithm 1 end to end: noisy image and sigma in, denoised image out.
+ * idx_out, masks_out, U_out, V_out, cnt_out: nullable copies of the state a
+ * backward pass needs (idx [n_ref][K], masks as in hts_filter for all n_ref
+ * groups, U/V [C][ps][ps], cnt [H][W]). */
+hts_status hts_denoise(const hts_params* p, const float* noisy, int32_t C, int32_t H,
+                       int32_t W, float sigma, float* out, int32_t* idx_out,
+                       uint32_t* masks_out, float* U_out, float* V_out, float* cnt_out,
+                       void* ws, size_t ws_bytes, void* stream);
+
+typedef struct {
+  const float* noisy;  /* device [C][H][W]                */
+  float* out;          /* device [C][H][W]                */
+  int32_t C, H, W;
+  float sigma;
+} hts_image;
+
+/* Workspace bytes for hts_denoise_batch over these n images (host array). */
+hts_status hts_batch_workspace_size(const hts_params* p, const hts_image* imgs, int32_t n,
+                                    size_t* bytes);
+
+/* Algorithm 1 for n independent images of any sizes and noise levels (each
+ * with its own reference grid, basis and sigma).  All images share C and
+ * the method parameters.  The stages run as persistent kernels over a
+ * device work list of (image, tile) items, captured once per parameter set
+ * into a HIP graph and replayed; imgs is a host array. */
+hts_status hts_denoise_batch(const hts_params* p, const hts_image* imgs, int32_t n,
+                             void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint of hts_denoise with the match indices, threshold masks, basis and
+ * coverage count held fixed (the map noisy -> denoised is then linear;
+ * derived from Eq. 18-20 and Eq. 2):
+ *   grad_in = sum_g Gather_g^T Q^T M_g Q Gather_g (grad_out / cnt).
+ * grad_tau_mult (nullable, device float) receives 0: the threshold enters
+ * only through the frozen masks. */
+hts_status hts_denoise_backward(const hts_params* p, const float* grad_out,
+                                const int32_t* idx, const uint32_t* masks, const float* U,
+                                const float* V, const float* cnt, int32_t C, int32_t H,
+                                int32_t W, float* grad_in, float* grad_tau_mult, void* ws,
+                                size_t ws_bytes, void* stream);
+
+/* Autotuner: time the launch schedules of the match and filter stages on
+ * the current device for this parameter set and image shape, remember the
+ * fastest (in memory, and in the cache file `cache_path` when non-null),
+ * and return it in *tune_out (pass it as hts_params.tune).  Uses ws for
+ * scratch; synchronises `stream`. */
+hts_status hts_autotune(const hts_params* p, int32_t C, int32_t H, int32_t W,
+                        const char* cache_path, int32_t* tune_out, void* ws,
+                        size_t ws_bytes, void* stream);
+
+/* Short static description of a status code. */
+const char* hts_status_string(hts_status s);
+
+/* Library version string. */
+const char* hts_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HTS_H */

@@ -1,0 +1,268 @@
+"""Python binding of the C ABI (include/hts.h) for torch tensors.
+
+Only argument marshalling happens here: tensors are checked for device,
+dtype and contiguity, buffers the C calls write are allocated with torch,
+and every step of the method runs in the HIP kernels of libhts.so on the
+caller's current stream.  The function names are those of the C ABI.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import _lib as L
+
+
+@dataclass
+class Params:
+    """Method parameters (hts_params): patch size, reference stride, odd
+    search-window width, group size K (power of two), threshold multiplier
+    lambda (tau = lambda * sigma), GCP gamma = gcp_num / gcp_den, distance
+    tile mode, flags and launch schedule."""
+    ps: int = 8
+    stride: int = 3
+    window: int = 21
+    K: int = 16
+    tau_mult: float = 2.7
+    gcp_num: int = 6
+    gcp_den: int = 5
+    match_mode: int = L.HTS_MATCH_BF16
+    flags: int = 0
+    tune: int = 0
+
+    def c(self) -> L.HtsParams:
+        return L.HtsParams(self.ps, self.stride, self.window, self.K, float(self.tau_mult),
+                           self.gcp_num, self.gcp_den, self.match_mode, self.flags, self.tune)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _img(x: torch.Tensor, name="noisy") -> torch.Tensor:
+    if x.dim() != 3:
+        raise ValueError(f"{name} must be [C, H, W]")
+    if not x.is_cuda or x.dtype != torch.float32:
+        raise ValueError(f"{name} must be a float32 tensor on the GPU")
+    return x.contiguous()
+
+
+def ref_grid(H: int, W: int, p: Params):
+    ny, nx = L.c_i32(), L.c_i32()
+    pc = p.c()
+    L.check("hts_ref_grid", L.load().hts_ref_grid(H, W, ctypes.byref(pc), ctypes.byref(ny),
+                                                  ctypes.byref(nx)))
+    return ny.value, nx.value
+
+
+def workspace_size(p: Params, C: int, H: int, W: int) -> int:
+    n = L.c_sz()
+    pc = p.c()
+    L.check("hts_workspace_size", L.load().hts_workspace_size(ctypes.byref(pc), C, H, W,
+                                                              ctypes.byref(n)))
+    return n.value
+
+
+def workspace(p: Params, C: int, H: int, W: int, device) -> torch.Tensor:
+    return torch.empty(workspace_size(p, C, H, W), dtype=torch.uint8, device=device)
+
+
+def hts_match(noisy: torch.Tensor, p: Params, want_dist=False, want_green=False, ws=None):
+    """Alg. 1 Step 1.  Returns idx int32 [n_ref, K] (and dist int64, green uint8)."""
+    x = _img(noisy)
+    C, H, W = x.shape
+    ny, nx = ref_grid(H, W, p)
+    n_ref = ny * nx
+    idx = torch.empty((n_ref, p.K), dtype=torch.int32, device=x.device)
+    dist = torch.empty((n_ref, p.K), dtype=torch.int64, device=x.device) if want_dist else None
+    green = torch.empty(n_ref, dtype=torch.uint8, device=x.device) if want_green else None
+    ws = workspace(p, C, H, W, x.device) if ws is None else ws
+    pc = p.c()
+    L.check("hts_match", L.load().hts_match(ctypes.byref(pc), _ptr(x), C, H, W, _ptr(idx),
+                                            _ptr(dist), _ptr(green), _ptr(ws), ws.numel(),
+                                            _stream(x.device)))
+    out = (idx,)
+    if want_dist:
+        out += (dist,)
+    if want_green:
+        out += (green,)
+    return out[0] if len(out) == 1 else out
+
+
+def hts_basis(noisy: torch.Tensor, p: Params, want_fp64=False, ws=None):
+    """Alg. 1 Step 2(1).  Returns U, V float32 [C, 8, 8] (+ U64, V64, eig)."""
+    x = _img(noisy)
+    C, H, W = x.shape
+    U = torch.empty((C, 8, 8), dtype=torch.float32, device=x.device)
+    V = torch.empty_like(U)
+    U64 = V64 = eig = None
+    if want_fp64:
+        U64 = torch.empty((C, 8, 8), dtype=torch.float64, device=x.device)
+        V64 = torch.empty_like(U64)
+        eig = torch.empty((2, C // 2 + 1, 8), dtype=torch.float64, device=x.device)
+    ws = workspace(p, C, H, W, x.device) if ws is None else ws
+    pc = p.c()
+    L.check("hts_basis", L.load().hts_basis(ctypes.byref(pc), _ptr(x), C, H, W, _ptr(U), _ptr(V),
+                                            _ptr(U64), _ptr(V64), _ptr(eig), _ptr(ws), ws.numel(),
+                                            _stream(x.device)))
+    return (U, V, U64, V64, eig) if want_fp64 else (U, V)
+
+
+def mask_words(n_groups: int, K: int, C: int) -> int:
+    return (n_groups * K * C * 64 + 31) // 32
+
+
+def hts_filter(noisy, sigma, idx, U, V, p: Params, ref_begin=0, ref_count=None,
+               accumulate=True, want_group_est=False, want_masks=False, ws=None):
+    """Alg. 1 Step 2(2)-(4) for references [ref_begin, ref_begin + ref_count).
+    Returns a dict with num, cnt (when accumulate), group_est, masks."""
+    x = _img(noisy)
+    C, H, W = x.shape
+    n_ref = idx.shape[0]
+    ref_count = n_ref - ref_begin if ref_count is None else ref_count
+    dev = x.device
+    num = torch.zeros((C, H, W), dtype=torch.float32, device=dev) if accumulate else None
+    cnt = torch.zeros((H, W), dtype=torch.float32, device=dev) if accumulate else None
+    est = (torch.empty((ref_count, p.K, C, 8, 8), dtype=torch.float32, device=dev)
+           if want_group_est else None)
+    masks = (torch.zeros(mask_words(ref_count, p.K, C), dtype=torch.int32, device=dev)
+             if want_masks else None)
+    ws = workspace(p, C, H, W, dev) if ws is None else ws
+    pc = p.c()
+    idx = idx.contiguous()
+    L.check("hts_filter", L.load().hts_filter(
+        ctypes.byref(pc), _ptr(x), C, H, W, float(sigma), _ptr(idx), _ptr(U.contiguous()),
+        _ptr(V.contiguous()), ref_begin, ref_count, _ptr(num), _ptr(cnt), _ptr(est), _ptr(masks),
+        _ptr(ws), ws.numel(), _stream(dev)))
+    return {"num": num, "cnt": cnt, "group_est": est, "masks": masks}
+
+
+def hts_aggregate(p: Params, C, H, W, num, cnt, group_est=None, idx=None, ref_begin=0,
+                  ref_count=0, out=None):
+    """Eq. 2: add group estimates into num/cnt and/or finalise out = num / cnt."""
+    pc = p.c()
+    dev = num.device
+    L.check("hts_aggregate", L.load().hts_aggregate(
+        ctypes.byref(pc), _ptr(group_est), _ptr(idx), ref_begin, ref_count, C, H, W, _ptr(num),
+        _ptr(cnt), _ptr(out), _stream(dev)))
+    return out
+
+
+def hts_denoise(noisy, sigma, p: Params, save=False, ws=None):
+    """Algorithm 1 end to end.  With save=True also returns the state the
+    adjoint needs: dict(idx, masks, U, V, cnt)."""
+    x = _img(noisy)
+    C, H, W = x.shape
+    dev = x.device
+    out = torch.empty_like(x)
+    st = None
+    if save:
+        ny, nx = ref_grid(H, W, p)
+        n_ref = ny * nx
+        st = {"idx": torch.empty((n_ref, p.K), dtype=torch.int32, device=dev),
+              "masks": torch.zeros(mask_words(n_ref, p.K, C), dtype=torch.int32, device=dev),
+              "U": torch.empty((C, 8, 8), dtype=torch.float32, device=dev),
+              "V": torch.empty((C, 8, 8), dtype=torch.float32, device=dev),
+              "cnt": torch.empty((H, W), dtype=torch.float32, device=dev)}
+    g = st or {}
+    ws = workspace(p, C, H, W, dev) if ws is None else ws
+    pc = p.c()
+    L.check("hts_denoise", L.load().hts_denoise(
+        ctypes.byref(pc), _ptr(x), C, H, W, float(sigma), _ptr(out), _ptr(g.get("idx")),
+        _ptr(g.get("masks")), _ptr(g.get("U")), _ptr(g.get("V")), _ptr(g.get("cnt")), _ptr(ws),
+        ws.numel(), _stream(dev)))
+    return (out, st) if save else out
+
+
+def hts_denoise_backward(grad_out, st, p: Params, ws=None):
+    """Adjoint with frozen idx / masks / basis / counts.  Returns
+    (grad_noisy, grad_tau_mult) - the latter is identically zero."""
+    g = _img(grad_out, "grad_out")
+    C, H, W = g.shape
+    dev = g.device
+    gin = torch.empty_like(g)
+    gtau = torch.empty(1, dtype=torch.float32, device=dev)
+    ws = workspace(p, C, H, W, dev) if ws is None else ws
+    pc = p.c()
+    L.check("hts_denoise_backward", L.load().hts_denoise_backward(
+        ctypes.byref(pc), _ptr(g), _ptr(st["idx"]), _ptr(st["masks"]), _ptr(st["U"]),
+        _ptr(st["V"]), _ptr(st["cnt"]), C, H, W, _ptr(gin), _ptr(gtau), _ptr(ws), ws.numel(),
+        _stream(dev)))
+    return gin, gtau
+
+
+def _images(noisy: Sequence[torch.Tensor], outs: Sequence[torch.Tensor], sigmas):
+    arr = (L.HtsImage * len(noisy))()
+    for i, (x, o, s) in enumerate(zip(noisy, outs, sigmas)):
+        C, H, W = x.shape
+        arr[i] = L.HtsImage(x.data_ptr(), o.data_ptr(), C, H, W, float(s))
+    return arr
+
+
+def batch_workspace_size(p: Params, noisy, outs, sigmas) -> int:
+    arr = _images(noisy, outs, sigmas)
+    n = L.c_sz()
+    pc = p.c()
+    L.check("hts_batch_workspace_size", L.load().hts_batch_workspace_size(
+        ctypes.byref(pc), arr, len(noisy), ctypes.byref(n)))
+    return n.value
+
+
+def hts_denoise_batch(noisy: List[torch.Tensor], sigmas, p: Params, outs=None, ws=None):
+    """Algorithm 1 for a list of images of any sizes / noise levels (one
+    persistent, graph-captured pipeline).  Returns the list of outputs."""
+    xs = [_img(x) for x in noisy]
+    dev = xs[0].device
+    outs = [torch.empty_like(x) for x in xs] if outs is None else outs
+    if ws is None:
+        ws = torch.empty(batch_workspace_size(p, xs, outs, sigmas), dtype=torch.uint8, device=dev)
+    arr = _images(xs, outs, sigmas)
+    pc = p.c()
+    L.check("hts_denoise_batch", L.load().hts_denoise_batch(
+        ctypes.byref(pc), arr, len(xs), _ptr(ws), ws.numel(), _stream(dev)))
+    return outs
+
+
+def hts_autotune(p: Params, C, H, W, cache_path: Optional[str] = None, device="cuda"):
+    """Time the launch schedules for this shape on the GPU; returns the tune word."""
+    size = workspace_size(p, C, H, W) + 2 * C * H * W * 4 + (H * W) * p.K * 4 + (1 << 20)
+    ws = torch.empty(size, dtype=torch.uint8, device=device)
+    out = L.c_i32()
+    pc = p.c()
+    L.check("hts_autotune", L.load().hts_autotune(
+        ctypes.byref(pc), C, H, W, cache_path.encode() if cache_path else None,
+        ctypes.byref(out), _ptr(ws), ws.numel(), _stream(torch.device(device))))
+    return out.value
+
+
+class HaarTSVD(torch.autograd.Function):
+    """Differentiable Haar-tSVD denoiser: forward = hts_denoise; backward =
+    the hand-written adjoint kernel with match indices, threshold masks,
+    basis and coverage counts frozen at the forward pass.  The gradient with
+    respect to the threshold multiplier is zero (it only moves the frozen
+    masks)."""
+
+    @staticmethod
+    def forward(ctx, noisy, sigma, tau_mult, p: Params):
+        q = Params(**{**p.__dict__, "tau_mult": float(tau_mult)})
+        out, st = hts_denoise(noisy.detach(), float(sigma), q, save=True)
+        ctx.st = st
+        ctx.p = q
+        return out
+
+    @staticmethod
+    def backward(ctx, grad):
+        gin, gtau = hts_denoise_backward(grad.contiguous(), ctx.st, ctx.p)
+        return gin, None, gtau.reshape(()), None
+
+
+def denoise(x: torch.Tensor, sigma: float, **params) -> torch.Tensor:
+    """Convenience: denoise one [C, H, W] float32 GPU image."""
+    return hts_denoise(x, sigma, Params(**params))

@@ -1,0 +1,707 @@
+// Host side of the C ABI (include/hts.h): argument validation, workspace
+// carving, launch sequences, batched persistent launches captured into HIP
+// graphs, and the launch-schedule autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "hts_internal.h"
+
+using namespace hts;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+inline size_t al(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+// Filter tile shapes the schedule may pick (references per tile).
+constexpr FiltShape kShapes[] = {{8, 8}, {8, 4}, {4, 8}, {4, 4}, {4, 2}, {2, 4}, {2, 2}, {2, 1}, {1, 1}};
+constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+constexpr size_t kFilterLdsBudget = 80 * 1024;   // two work groups per CU
+constexpr size_t kLdsMax = 160 * 1024;
+
+struct Geo {
+  int C, H, W, Hp, Wp, nry, nrx, n_ref, n_cov, np;
+  int K;
+};
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+hts_status check_params(const hts_params* p, int C) {
+  if (!p) return HTS_ERR_INVALID;
+  if (p->ps != PS) return HTS_ERR_UNSUPPORTED;
+  if (C != 1 && C != 3) return HTS_ERR_UNSUPPORTED;
+  if (!is_pow2(p->K) || p->K < 2 || p->K > 64) return HTS_ERR_INVALID;
+  if (C == 3 && p->K > 32) return HTS_ERR_UNSUPPORTED;
+  if (p->stride < 1 || p->stride > PS) return HTS_ERR_INVALID;
+  if (p->window < 3 || p->window > MAX_WINDOW || (p->window & 1) == 0) return HTS_ERR_INVALID;
+  if (!(p->tau_mult >= 0.f) || !std::isfinite(p->tau_mult)) return HTS_ERR_INVALID;
+  if (p->gcp_num < 1 || p->gcp_num > 64 || p->gcp_den < 1 || p->gcp_den > 64) return HTS_ERR_INVALID;
+  if (p->match_mode != HTS_MATCH_BF16 && p->match_mode != HTS_MATCH_FP32) return HTS_ERR_INVALID;
+  if ((size_t)match_lds_bytes(p->stride, p->window) > kLdsMax) return HTS_ERR_UNSUPPORTED;
+  if (filter_lds_bytes(C, p->K, p->stride, p->window, 1, 1) > kLdsMax) return HTS_ERR_UNSUPPORTED;
+  return HTS_OK;
+}
+
+hts_status make_geo(const hts_params* p, int C, int H, int W, Geo& g) {
+  hts_status st = check_params(p, C);
+  if (st != HTS_OK) return st;
+  if (H < PS || W < PS) return HTS_ERR_INVALID;
+  if ((long long)C * H * W >= (1LL << 31)) return HTS_ERR_UNSUPPORTED;
+  g.C = C; g.H = H; g.W = W; g.K = p->K;
+  g.Hp = H - PS + 1; g.Wp = W - PS + 1;
+  g.nry = ref_count_axis(g.Hp, p->stride);
+  g.nrx = ref_count_axis(g.Wp, p->stride);
+  g.n_ref = g.nry * g.nrx;
+  g.n_cov = (g.n_ref + COV_REFS - 1) / COV_REFS;
+  g.np = C == 1 ? 1 : 2;
+  const int r = (p->window - 1) / 2;
+  // every reference must have at least K candidates (the corner ones have fewest)
+  if ((long long)std::min(g.Hp, r + 1) * std::min(g.Wp, r + 1) < p->K) return HTS_ERR_INVALID;
+  if ((long long)g.n_ref * p->K >= (1LL << 31)) return HTS_ERR_UNSUPPORTED;
+  return HTS_OK;
+}
+
+// Workspace carve-up for one image.
+struct Carve {
+  size_t gplanes, green, idx, fb_list, fb_count, cov, basis64, basis, fbasis, num, cnt, total;
+};
+
+Carve carve(const Geo& g) {
+  Carve c;
+  size_t o = 0;
+  c.gplanes = o; o += al((size_t)g.np * g.H * g.W * 4);
+  c.green = o; o += al((size_t)g.n_ref);
+  c.idx = o; o += al((size_t)g.n_ref * g.K * 4);
+  c.fb_list = o; o += al((size_t)g.n_ref * 4);
+  c.fb_count = o; o += al(4);
+  c.cov = o; o += al((size_t)g.n_cov * cov_elems(g.C) * 8);
+  c.basis64 = o; o += al((size_t)(2 * g.C * 64 + 2 * (g.C / 2 + 1) * 8) * 8);
+  c.basis = o; o += al((size_t)2 * g.C * 64 * 4);
+  c.fbasis = o; o += al((size_t)FB_SIZE * 4);
+  c.num = o; o += al((size_t)g.C * g.H * g.W * 4);
+  c.cnt = o; o += al((size_t)g.H * g.W * 4);
+  c.total = o;
+  return c;
+}
+
+void fill_counts(const Geo& g, const hts_params* p, int fty, int ftx, ImgDesc& d) {
+  d.wcnt[W_PIX] = (g.H * g.W + PIX_CHUNK - 1) / PIX_CHUNK;
+  d.wcnt[W_REF] = (g.n_ref + 255) / 256;
+  d.wcnt[W_MATCH] = ((g.nry + MATCH_TY - 1) / MATCH_TY) * ((g.nrx + MATCH_TX - 1) / MATCH_TX);
+  d.wcnt[W_COV] = g.n_cov;
+  d.wcnt[W_FILT] = ((g.nry + fty - 1) / fty) * ((g.nrx + ftx - 1) / ftx);
+  for (int k = 0; k < W_NKIND; ++k) d.woff[k] = 0;
+  (void)p;
+}
+
+ImgDesc make_desc(const Geo& g, const hts_params* p, char* ws, const Carve& c, const float* img,
+                  float sigma, int fty, int ftx) {
+  ImgDesc d;
+  std::memset(&d, 0, sizeof(d));
+  d.img = img;
+  d.gplanes = (int32_t*)(ws + c.gplanes);
+  d.green = (uint8_t*)(ws + c.green);
+  d.idx = (int32_t*)(ws + c.idx);
+  d.fb_list = (int32_t*)(ws + c.fb_list);
+  d.fb_count = (int32_t*)(ws + c.fb_count);
+  d.cov_part = (double*)(ws + c.cov);
+  d.basis64 = (double*)(ws + c.basis64);
+  d.basis = (float*)(ws + c.basis);
+  d.fbasis = (float*)(ws + c.fbasis);
+  d.num = (float*)(ws + c.num);
+  d.cnt = (float*)(ws + c.cnt);
+  d.H = g.H; d.W = g.W; d.Hp = g.Hp; d.Wp = g.Wp;
+  d.nry = g.nry; d.nrx = g.nrx; d.n_ref = g.n_ref;
+  d.ref_begin = 0; d.ref_count = g.n_ref;
+  d.sigma = sigma;
+  d.tau = p->tau_mult * sigma;
+  d.n_cov = g.n_cov;
+  fill_counts(g, p, fty, ftx, d);
+  return d;
+}
+
+Launch make_launch(const hts_params* p, int C, const ImgDesc& d, int kind, int fty, int ftx) {
+  Launch L;
+  std::memset(&L, 0, sizeof(L));
+  L.one = d;
+  L.table = nullptr;
+  L.n_img = 1;
+  L.total = kind >= 0 ? d.wcnt[kind] : 1;
+  L.C = C; L.K = p->K; L.stride = p->stride; L.window = p->window;
+  L.tau_mult = p->tau_mult;
+  L.gcp_num = p->gcp_num; L.gcp_den = p->gcp_den;
+  L.flags = p->flags;
+  L.fty = fty; L.ftx = ftx;
+  return L;
+}
+
+// ---- launch schedule (tune word) ----
+// bits 0-3: filter tile shape index + 1 (0 = largest shape within the LDS budget)
+// bits 4-5: BF16 match terms (0 = default 3, 1 = one product, 2 = hi/lo split)
+struct Schedule { int fty, ftx, terms; };
+
+int tuned_word(const hts_params* p, int C);
+
+Schedule schedule_for(const hts_params* p, int C) {
+  Schedule s;
+  const int tune = p->tune ? p->tune : tuned_word(p, C);
+  int si = (tune & 15) - 1;
+  if (si < 0 || si >= kNumShapes ||
+      filter_lds_bytes(C, p->K, p->stride, p->window, kShapes[si].ty, kShapes[si].tx) > kLdsMax) {
+    si = kNumShapes - 1;
+    for (int i = 0; i < kNumShapes; ++i)
+      if (filter_lds_bytes(C, p->K, p->stride, p->window, kShapes[i].ty, kShapes[i].tx) <= kFilterLdsBudget) { si = i; break; }
+  }
+  s.fty = kShapes[si].ty;
+  s.ftx = kShapes[si].tx;
+  const int t = (tune >> 4) & 3;
+  s.terms = t == 1 ? 1 : 3;
+  return s;
+}
+
+#define HIPCHK(x) do { if ((x) != hipSuccess) return HTS_ERR_HIP; } while (0)
+
+hts_status run_match(const hts_params* p, int C, const Schedule& sc, ImgDesc d, hipStream_t s) {
+  HIPCHK(launch_quant(make_launch(p, C, d, W_PIX, sc.fty, sc.ftx), 0, s));
+  HIPCHK(launch_gcp(make_launch(p, C, d, W_REF, sc.fty, sc.ftx), 0, s));
+  HIPCHK(launch_reset_counters(make_launch(p, C, d, -1, sc.fty, sc.ftx), s));
+  HIPCHK(launch_match(make_launch(p, C, d, W_MATCH, sc.fty, sc.ftx), p->match_mode, sc.terms, 0, s));
+  HIPCHK(launch_match_fallback(make_launch(p, C, d, -1, sc.fty, sc.ftx), 256, s));
+  return HTS_OK;
+}
+
+hts_status run_basis(const hts_params* p, int C, const Schedule& sc, ImgDesc d, hipStream_t s) {
+  HIPCHK(launch_cov(make_launch(p, C, d, W_COV, sc.fty, sc.ftx), 0, s));
+  HIPCHK(launch_eig(make_launch(p, C, d, -1, sc.fty, sc.ftx), s));
+  return HTS_OK;
+}
+
+hts_status run_filter(const hts_params* p, int C, const Schedule& sc, ImgDesc d, int adjoint,
+                      hipStream_t s) {
+  HIPCHK(launch_fbasis(make_launch(p, C, d, -1, sc.fty, sc.ftx), s));
+  HIPCHK(launch_filter(make_launch(p, C, d, W_FILT, sc.fty, sc.ftx), sc.fty, sc.ftx, adjoint, 0, s));
+  return HTS_OK;
+}
+
+// ---------------------------------------------------------------- devices
+int device_cus() {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cus[dev]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+    cus[dev] = v;
+  }
+  return cus[dev];
+}
+
+// ---------------------------------------------------------------- autotune cache
+// key: device arch + the parameters a schedule depends on; value: tune word.
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;
+
+std::string arch_name() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "gfx?";
+  std::string a = prop.gcnArchName;
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+std::string tune_key(const hts_params* p, int C) {
+  char buf[160];
+  std::snprintf(buf, sizeof(buf), "%s C=%d s=%d w=%d K=%d mode=%d", arch_name().c_str(), C,
+                p->stride, p->window, p->K, p->match_mode);
+  return buf;
+}
+
+int tuned_word(const hts_params* p, int C) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (g_tune.empty()) return 0;
+  auto it = g_tune.find(tune_key(p, C));
+  return it == g_tune.end() ? 0 : it->second;
+}
+
+void load_cache_file(const char* path) {
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char line[256];
+  while (std::fgets(line, sizeof(line), f)) {
+    char* bar = std::strrchr(line, '|');
+    if (!bar) continue;
+    *bar = 0;
+    const int w = std::atoi(bar + 1);
+    if (w > 0) g_tune[line] = w;     // corrupt or zero entries are ignored
+  }
+  std::fclose(f);
+}
+
+// ---------------------------------------------------------------- batches
+struct BatchPlan {
+  std::vector<ImgDesc> descs;   // n entries
+  int totals[W_NKIND];
+  size_t table_off, bytes;
+  Schedule sc;
+};
+
+hts_status plan_batch(const hts_params* p, const hts_image* imgs, int n, char* base, bool check_ptrs,
+                      BatchPlan& plan) {
+  if (!p || !imgs || n < 1) return HTS_ERR_INVALID;
+  const int C = imgs[0].C;
+  hts_status st = check_params(p, C);
+  if (st != HTS_OK) return st;
+  plan.sc = schedule_for(p, C);
+  plan.descs.assign(n, ImgDesc());
+  for (int k = 0; k < W_NKIND; ++k) plan.totals[k] = 0;
+  size_t off = 0;
+  plan.table_off = off;
+  off += al((size_t)n * sizeof(ImgDesc));
+  for (int i = 0; i < n; ++i) {
+    const hts_image& im = imgs[i];
+    if (im.C != C) return HTS_ERR_INVALID;
+    if (!(im.sigma >= 0.f) || !std::isfinite(im.sigma)) return HTS_ERR_INVALID;
+    if (check_ptrs && (!im.noisy || !im.out)) return HTS_ERR_INVALID;
+    Geo g;
+    st = make_geo(p, C, im.H, im.W, g);
+    if (st != HTS_OK) return st;
+    const Carve c = carve(g);
+    ImgDesc d = make_desc(g, p, base ? base + off : nullptr, c, im.noisy, im.sigma, plan.sc.fty,
+                          plan.sc.ftx);
+    d.out = im.out;
+    for (int k = 0; k < W_NKIND; ++k) {
+      d.woff[k] = plan.totals[k];
+      if ((long long)plan.totals[k] + d.wcnt[k] >= (1LL << 31)) return HTS_ERR_UNSUPPORTED;
+      plan.totals[k] += d.wcnt[k];
+    }
+    plan.descs[i] = d;
+    off += c.total;
+  }
+  plan.bytes = off;
+  return HTS_OK;
+}
+
+Launch batch_launch(const hts_params* p, int C, const ImgDesc* table, int n, int total, const Schedule& sc) {
+  Launch L;
+  std::memset(&L, 0, sizeof(L));
+  L.table = table;
+  L.n_img = n;
+  L.total = total;
+  L.C = C; L.K = p->K; L.stride = p->stride; L.window = p->window;
+  L.tau_mult = p->tau_mult;
+  L.gcp_num = p->gcp_num; L.gcp_den = p->gcp_den;
+  L.flags = p->flags;
+  L.fty = sc.fty; L.ftx = sc.ftx;
+  return L;
+}
+
+// All stages of Algorithm 1 over the batch, as persistent launches sized to
+// the device (work groups loop over the global (image, item) list).
+hts_status enqueue_batch(const hts_params* p, int C, const BatchPlan& plan, const ImgDesc* table,
+                         hipStream_t s) {
+  const int n = (int)plan.descs.size();
+  const int cus = device_cus();
+  const Schedule& sc = plan.sc;
+  auto LK = [&](int kind) { return batch_launch(p, C, table, n, kind >= 0 ? plan.totals[kind] : 0, sc); };
+  HIPCHK(launch_quant(LK(W_PIX), cus * 8, s));
+  HIPCHK(launch_gcp(LK(W_REF), cus * 8, s));
+  HIPCHK(launch_reset_counters(LK(-1), s));
+  HIPCHK(launch_match(LK(W_MATCH), p->match_mode, sc.terms, cus * 2, s));
+  HIPCHK(launch_match_fallback(LK(-1), cus, s));
+  HIPCHK(launch_cov(LK(W_COV), cus * 4, s));
+  HIPCHK(launch_eig(LK(-1), s));
+  HIPCHK(launch_fbasis(LK(-1), s));
+  HIPCHK(launch_zero_accum(LK(W_PIX), cus * 8, s));
+  HIPCHK(launch_filter(LK(W_FILT), sc.fty, sc.ftx, 0, cus * 2, s));
+  HIPCHK(launch_finalize(LK(W_PIX), cus * 8, s));
+  return HTS_OK;
+}
+
+// One captured graph per shape-set (parameters, image shapes, workspace);
+// images' pointers and noise levels live in the device table and may change
+// between replays.
+struct GraphEntry {
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t copied = nullptr;
+  bool used = false;
+  std::vector<ImgDesc> host;     // staging for the table upload
+};
+std::mutex g_graph_mu;
+std::map<std::string, GraphEntry> g_graphs;
+hipStream_t g_capture_stream[64] = {nullptr};
+
+std::string graph_key(const hts_params* p, const hts_image* imgs, int n, const void* ws) {
+  std::string k;
+  char buf[128];
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::snprintf(buf, sizeof(buf), "%d|%d %d %d %d %a %d %d %d %d %d|%p|", dev, p->ps, p->stride,
+                p->window, p->K, (double)p->tau_mult, p->gcp_num, p->gcp_den, p->match_mode,
+                p->flags, p->tune, ws);
+  k = buf;
+  for (int i = 0; i < n; ++i) {
+    std::snprintf(buf, sizeof(buf), "%dx%dx%d;", imgs[i].C, imgs[i].H, imgs[i].W);
+    k += buf;
+  }
+  return k;
+}
+
+}  // namespace
+
+extern "C" {
+
+void hts_default_params(hts_params* p) {
+  if (!p) return;
+  p->ps = 8; p->stride = 3; p->window = 21; p->K = 16; p->tau_mult = 2.7f;
+  p->gcp_num = 6; p->gcp_den = 5; p->match_mode = HTS_MATCH_BF16; p->flags = 0; p->tune = 0;
+}
+
+const char* hts_status_string(hts_status s) {
+  switch (s) {
+    case HTS_OK: return "ok";
+    case HTS_ERR_INVALID: return "invalid argument";
+    case HTS_ERR_UNSUPPORTED: return "unsupported configuration";
+    case HTS_ERR_WORKSPACE: return "workspace too small";
+    case HTS_ERR_HIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+const char* hts_version(void) { return "hts 0.1 (gfx950)"; }
+
+hts_status hts_ref_grid(int32_t H, int32_t W, const hts_params* p, int32_t* ny, int32_t* nx) {
+  if (!p || !ny || !nx) return HTS_ERR_INVALID;
+  if (p->stride < 1 || p->stride > PS || p->ps != PS) return p && p->ps != PS ? HTS_ERR_UNSUPPORTED : HTS_ERR_INVALID;
+  if (H < PS || W < PS) return HTS_ERR_INVALID;
+  *ny = ref_count_axis(H - PS + 1, p->stride);
+  *nx = ref_count_axis(W - PS + 1, p->stride);
+  return HTS_OK;
+}
+
+hts_status hts_workspace_size(const hts_params* p, int32_t C, int32_t H, int32_t W, size_t* bytes) {
+  if (!bytes) return HTS_ERR_INVALID;
+  Geo g;
+  hts_status st = make_geo(p, C, H, W, g);
+  if (st != HTS_OK) return st;
+  *bytes = carve(g).total;
+  return HTS_OK;
+}
+
+hts_status hts_match(const hts_params* p, const float* noisy, int32_t C, int32_t H, int32_t W,
+                     int32_t* idx, int64_t* dist, uint8_t* green, void* ws, size_t ws_bytes,
+                     void* stream) {
+  Geo g;
+  hts_status st = make_geo(p, C, H, W, g);
+  if (st != HTS_OK) return st;
+  if (!noisy || !idx || !ws) return HTS_ERR_INVALID;
+  const Carve c = carve(g);
+  if (ws_bytes < c.total) return HTS_ERR_WORKSPACE;
+  const Schedule sc = schedule_for(p, C);
+  ImgDesc d = make_desc(g, p, (char*)ws, c, noisy, 0.f, sc.fty, sc.ftx);
+  d.idx = idx;
+  d.dist = (long long*)dist;
+  if (green) d.green = green;
+  return run_match(p, C, sc, d, (hipStream_t)stream);
+}
+
+hts_status hts_basis(const hts_params* p, const float* noisy, int32_t C, int32_t H, int32_t W,
+                     float* U, float* V, double* U64, double* V64, double* eig, void* ws,
+                     size_t ws_bytes, void* stream) {
+  Geo g;
+  hts_status st = make_geo(p, C, H, W, g);
+  if (st != HTS_OK) return st;
+  if (!noisy || !U || !V || !ws) return HTS_ERR_INVALID;
+  const Carve c = carve(g);
+  if (ws_bytes < c.total) return HTS_ERR_WORKSPACE;
+  const Schedule sc = schedule_for(p, C);
+  hipStream_t s = (hipStream_t)stream;
+  ImgDesc d = make_desc(g, p, (char*)ws, c, noisy, 0.f, sc.fty, sc.ftx);
+  st = run_basis(p, C, sc, d, s);
+  if (st != HTS_OK) return st;
+  const size_t nb = (size_t)C * 64;
+  HIPCHK(hipMemcpyAsync(U, d.basis, nb * 4, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(V, d.basis + nb, nb * 4, hipMemcpyDeviceToDevice, s));
+  if (U64) HIPCHK(hipMemcpyAsync(U64, d.basis64, nb * 8, hipMemcpyDeviceToDevice, s));
+  if (V64) HIPCHK(hipMemcpyAsync(V64, d.basis64 + nb, nb * 8, hipMemcpyDeviceToDevice, s));
+  if (eig) HIPCHK(hipMemcpyAsync(eig, d.basis64 + 2 * nb, (size_t)2 * (C / 2 + 1) * 8 * 8, hipMemcpyDeviceToDevice, s));
+  return HTS_OK;
+}
+
+hts_status hts_filter(const hts_params* p, const float* noisy, int32_t C, int32_t H, int32_t W,
+                      float sigma, const int32_t* idx, const float* U, const float* V,
+                      int32_t ref_begin, int32_t ref_count, float* num, float* cnt,
+                      float* group_est, uint32_t* masks, void* ws, size_t ws_bytes, void* stream) {
+  Geo g;
+  hts_status st = make_geo(p, C, H, W, g);
+  if (st != HTS_OK) return st;
+  if (!noisy || !idx || !U || !V || !ws) return HTS_ERR_INVALID;
+  if ((num == nullptr) != (cnt == nullptr)) return HTS_ERR_INVALID;
+  if (!(sigma >= 0.f) || !std::isfinite(sigma)) return HTS_ERR_INVALID;
+  if (ref_begin < 0 || ref_count < 0 || (long long)ref_begin + ref_count > g.n_ref) return HTS_ERR_INVALID;
+  const Carve c = carve(g);
+  if (ws_bytes < c.total) return HTS_ERR_WORKSPACE;
+  if (ref_count == 0) return HTS_OK;
+  const Schedule sc = schedule_for(p, C);
+  hipStream_t s = (hipStream_t)stream;
+  ImgDesc d = make_desc(g, p, (char*)ws, c, noisy, sigma, sc.fty, sc.ftx);
+  d.idx = const_cast<int32_t*>(idx);
+  d.ref_begin = ref_begin;
+  d.ref_count = ref_count;
+  d.group_est = group_est;
+  d.masks = masks;
+  if (num) { d.num = num; d.cnt = cnt; }
+  const size_t nb = (size_t)C * 64;
+  HIPCHK(hipMemcpyAsync(d.basis, U, nb * 4, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(d.basis + nb, V, nb * 4, hipMemcpyDeviceToDevice, s));
+  return run_filter(p, C, sc, d, 0, s);
+}
+
+hts_status hts_aggregate(const hts_params* p, const float* group_est, const int32_t* idx,
+                         int32_t ref_begin, int32_t ref_count, int32_t C, int32_t H, int32_t W,
+                         float* num, float* cnt, float* out, void* stream) {
+  Geo g;
+  hts_status st = make_geo(p, C, H, W, g);
+  if (st != HTS_OK) return st;
+  if (!num || !cnt) return HTS_ERR_INVALID;
+  if (group_est && !idx) return HTS_ERR_INVALID;
+  if (ref_begin < 0 || ref_count < 0 || (long long)ref_begin + ref_count > g.n_ref) return HTS_ERR_INVALID;
+  hipStream_t s = (hipStream_t)stream;
+  const Schedule sc = schedule_for(p, C);
+  ImgDesc d;
+  std::memset(&d, 0, sizeof(d));
+  d.H = g.H; d.W = g.W; d.Hp = g.Hp; d.Wp = g.Wp; d.nry = g.nry; d.nrx = g.nrx; d.n_ref = g.n_ref;
+  d.idx = const_cast<int32_t*>(idx);
+  d.num = num; d.cnt = cnt; d.out = out;
+  d.ref_begin = ref_begin; d.ref_count = ref_count;
+  d.group_est = const_cast<float*>(group_est);
+  fill_counts(g, p, sc.fty, sc.ftx, d);
+  if (group_est && ref_count > 0) HIPCHK(launch_scatter_est(make_launch(p, C, d, -1, sc.fty, sc.ftx), s));
+  if (out) HIPCHK(launch_finalize(make_launch(p, C, d, W_PIX, sc.fty, sc.ftx), 0, s));
+  return HTS_OK;
+}
+
+hts_status hts_denoise(const hts_params* p, const float* noisy, int32_t C, int32_t H, int32_t W,
+                       float sigma, float* out, int32_t* idx_out, uint32_t* masks_out,
+                       float* U_out, float* V_out, float* cnt_out, void* ws, size_t ws_bytes,
+                       void* stream) {
+  Geo g;
+  hts_status st = make_geo(p, C, H, W, g);
+  if (st != HTS_OK) return st;
+  if (!noisy || !out || !ws) return HTS_ERR_INVALID;
+  if (!(sigma >= 0.f) || !std::isfinite(sigma)) return HTS_ERR_INVALID;
+  const Carve c = carve(g);
+  if (ws_bytes < c.total) return HTS_ERR_WORKSPACE;
+  const Schedule sc = schedule_for(p, C);
+  hipStream_t s = (hipStream_t)stream;
+  ImgDesc d = make_desc(g, p, (char*)ws, c, noisy, sigma, sc.fty, sc.ftx);
+  if (idx_out) d.idx = idx_out;
+  if (cnt_out) d.cnt = cnt_out;
+  d.masks = masks_out;
+  d.out = out;
+  st = run_match(p, C, sc, d, s);
+  if (st != HTS_OK) return st;
+  st = run_basis(p, C, sc, d, s);
+  if (st != HTS_OK) return st;
+  HIPCHK(launch_zero_accum(make_launch(p, C, d, W_PIX, sc.fty, sc.ftx), 0, s));
+  st = run_filter(p, C, sc, d, 0, s);
+  if (st != HTS_OK) return st;
+  HIPCHK(launch_finalize(make_launch(p, C, d, W_PIX, sc.fty, sc.ftx), 0, s));
+  const size_t nb = (size_t)C * 64;
+  if (U_out) HIPCHK(hipMemcpyAsync(U_out, d.basis, nb * 4, hipMemcpyDeviceToDevice, s));
+  if (V_out) HIPCHK(hipMemcpyAsync(V_out, d.basis + nb, nb * 4, hipMemcpyDeviceToDevice, s));
+  return HTS_OK;
+}
+
+hts_status hts_denoise_backward(const hts_params* p, const float* grad_out, const int32_t* idx,
+                                const uint32_t* masks, const float* U, const float* V,
+                                const float* cnt, int32_t C, int32_t H, int32_t W, float* grad_in,
+                                float* grad_tau_mult, void* ws, size_t ws_bytes, void* stream) {
+  Geo g;
+  hts_status st = make_geo(p, C, H, W, g);
+  if (st != HTS_OK) return st;
+  if (!grad_out || !idx || !masks || !U || !V || !cnt || !grad_in || !ws) return HTS_ERR_INVALID;
+  const Carve c = carve(g);
+  if (ws_bytes < c.total) return HTS_ERR_WORKSPACE;
+  const Schedule sc = schedule_for(p, C);
+  hipStream_t s = (hipStream_t)stream;
+  ImgDesc d = make_desc(g, p, (char*)ws, c, grad_out, 0.f, sc.fty, sc.ftx);
+  d.cnt = const_cast<float*>(cnt);
+  // r = grad_out / cnt into the workspace image buffer
+  HIPCHK(launch_adjoint_prep(make_launch(p, C, d, W_PIX, sc.fty, sc.ftx), 0, s));
+  ImgDesc a = d;
+  a.img = d.num;               // r
+  a.num = grad_in;             // accumulate the adjoint here
+  a.cnt = nullptr;
+  a.idx = const_cast<int32_t*>(idx);
+  a.masks_in = masks;
+  HIPCHK(launch_zero_accum(make_launch(p, C, a, W_PIX, sc.fty, sc.ftx), 0, s));
+  const size_t nb = (size_t)C * 64;
+  HIPCHK(hipMemcpyAsync(a.basis, U, nb * 4, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(a.basis + nb, V, nb * 4, hipMemcpyDeviceToDevice, s));
+  st = run_filter(p, C, sc, a, 1, s);
+  if (st != HTS_OK) return st;
+  if (grad_tau_mult) HIPCHK(hipMemsetAsync(grad_tau_mult, 0, sizeof(float), s));
+  return HTS_OK;
+}
+
+hts_status hts_batch_workspace_size(const hts_params* p, const hts_image* imgs, int32_t n,
+                                    size_t* bytes) {
+  if (!bytes) return HTS_ERR_INVALID;
+  BatchPlan plan;
+  hts_status st = plan_batch(p, imgs, n, nullptr, false, plan);
+  if (st != HTS_OK) return st;
+  *bytes = plan.bytes;
+  return HTS_OK;
+}
+
+hts_status hts_denoise_batch(const hts_params* p, const hts_image* imgs, int32_t n, void* ws,
+                             size_t ws_bytes, void* stream) {
+  if (!ws) return HTS_ERR_INVALID;
+  BatchPlan plan;
+  hts_status st = plan_batch(p, imgs, n, (char*)ws, true, plan);
+  if (st != HTS_OK) return st;
+  if (ws_bytes < plan.bytes) return HTS_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  const int C = imgs[0].C;
+  ImgDesc* table = (ImgDesc*)((char*)ws + plan.table_off);
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  GraphEntry& e = g_graphs[graph_key(p, imgs, n, ws)];
+  if (!e.copied) HIPCHK(hipEventCreateWithFlags(&e.copied, hipEventDisableTiming));
+  if (e.used) HIPCHK(hipEventSynchronize(e.copied));   // previous upload has read the staging
+  e.host = plan.descs;
+  e.used = true;
+  HIPCHK(hipMemcpyAsync(table, e.host.data(), e.host.size() * sizeof(ImgDesc), hipMemcpyHostToDevice, s));
+  HIPCHK(hipEventRecord(e.copied, s));
+  if (!e.exec) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return HTS_ERR_UNSUPPORTED;
+    if (!g_capture_stream[dev]) HIPCHK(hipStreamCreateWithFlags(&g_capture_stream[dev], hipStreamNonBlocking));
+    hipStream_t cs = g_capture_stream[dev];
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hts_status est = enqueue_batch(p, C, plan, table, cs);
+    const hipError_t ce = hipStreamEndCapture(cs, &graph);
+    if (est != HTS_OK || ce != hipSuccess || !graph) {
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipGetLastError();
+      return enqueue_batch(p, C, plan, table, s);   // eager launches on the caller's stream
+    }
+    const hipError_t ie = hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+      e.exec = nullptr;
+      (void)hipGetLastError();
+      return enqueue_batch(p, C, plan, table, s);
+    }
+  }
+  HIPCHK(hipGraphLaunch(e.exec, s));
+  return HTS_OK;
+}
+
+hts_status hts_autotune(const hts_params* p, int32_t C, int32_t H, int32_t W,
+                        const char* cache_path, int32_t* tune_out, void* ws, size_t ws_bytes,
+                        void* stream) {
+  Geo g;
+  hts_status st = make_geo(p, C, H, W, g);
+  if (st != HTS_OK) return st;
+  if (!tune_out || !ws) return HTS_ERR_INVALID;
+  const std::string key = tune_key(p, C);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_cache_file(cache_path);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) { *tune_out = it->second; return HTS_OK; }
+  }
+  const Carve c = carve(g);
+  const size_t img_b = al((size_t)C * H * W * 4), idx_b = al((size_t)g.n_ref * g.K * 4);
+  if (ws_bytes < c.total + 2 * img_b + idx_b) return HTS_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  char* base = (char*)ws;
+  float* img = (float*)(base + c.total);
+  float* out = (float*)(base + c.total + img_b);
+  int32_t* idx = (int32_t*)(base + c.total + 2 * img_b);
+  HIPCHK(launch_synth(img, C, H, W, s));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  auto time_it = [&](auto&& fn) -> float {
+    float best = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+      if (hipEventRecord(e0, s) != hipSuccess) return 1e30f;
+      if (fn() != HTS_OK) return 1e30f;
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return 1e30f;
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0) best = std::min(best, ms);
+    }
+    return best;
+  };
+  hts_params q = *p;
+  q.tune = 0;
+  Schedule base_sc = schedule_for(&q, C);
+  ImgDesc d = make_desc(g, &q, base, c, img, 25.f, base_sc.fty, base_sc.ftx);
+  d.idx = idx;
+  d.out = out;
+  // distance-tile variant (BF16 only: one product or hi/lo split)
+  int best_terms = 3;
+  if (p->match_mode == HTS_MATCH_BF16) {
+    float tb = 1e30f;
+    for (int terms : {3, 1}) {
+      Schedule sc = base_sc;
+      sc.terms = terms;
+      const float t = time_it([&] { return run_match(&q, C, sc, d, s); });
+      if (t < tb) { tb = t; best_terms = terms; }
+    }
+  }
+  {
+    Schedule sc = base_sc;
+    sc.terms = best_terms;
+    st = run_match(&q, C, sc, d, s);
+    if (st == HTS_OK) st = run_basis(&q, C, sc, d, s);
+    if (st != HTS_OK) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return st; }
+  }
+  // filter tile shape
+  int best_shape = 0;
+  float tf = 1e30f;
+  for (int i = 0; i < kNumShapes; ++i) {
+    if (filter_lds_bytes(C, p->K, p->stride, p->window, kShapes[i].ty, kShapes[i].tx) > kLdsMax) continue;
+    Schedule sc = base_sc;
+    sc.fty = kShapes[i].ty;
+    sc.ftx = kShapes[i].tx;
+    ImgDesc di = d;
+    fill_counts(g, &q, sc.fty, sc.ftx, di);
+    const float t = time_it([&] {
+      if (launch_zero_accum(make_launch(&q, C, di, W_PIX, sc.fty, sc.ftx), 0, s) != hipSuccess) return HTS_ERR_HIP;
+      return run_filter(&q, C, sc, di, 0, s);
+    });
+    if (t < tf) { tf = t; best_shape = i; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  const int word = (best_shape + 1) | ((best_terms == 1 ? 1 : 2) << 4);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = word;
+    if (cache_path) {
+      FILE* f = std::fopen(cache_path, "a");
+      if (f) { std::fprintf(f, "%s|%d\n", key.c_str(), word); std::fclose(f); }
+    }
+  }
+  *tune_out = word;
+  return HTS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,137 @@
+// Internal declarations shared by the host ABI (hts_api.cpp) and the HIP
+// kernels.  Not part of the public interface (include/hts.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/hts.h"
+
+namespace hts {
+
+constexpr int PS = 8;                  // patch size (only 8 is built)
+constexpr int PS2 = PS * PS;
+constexpr int QMAX = (1 << 20) - 1;    // clamp of the quantised guide
+constexpr int MAX_WINDOW = 63;         // window-relative candidate index fits 12 bits
+constexpr int MATCH_TY = 4;            // match tile: 4 x 4 references
+constexpr int MATCH_TX = 4;
+constexpr int SHORT_CAP = 128;         // certified shortlist capacity per reference
+constexpr int COV_REFS = 64;           // references per covariance partial block
+constexpr int PIX_CHUNK = 2048;        // pixels per work item of the element-wise stages
+
+// Work kinds: each image contributes a number of work items of each kind;
+// batched launches walk a global list of (image, item) pairs.
+enum WorkKind { W_PIX = 0, W_REF = 1, W_MATCH = 2, W_COV = 3, W_FILT = 4, W_NKIND = 5 };
+
+// Filter tile shapes (references per tile); index = hts_params.tune & 7
+// (0 = pick by LDS budget).
+struct FiltShape { int ty, tx; };
+
+// Per-image descriptor.  Passed by value for single-image calls, read from a
+// device table for batched calls.
+struct ImgDesc {
+  const float* img;        // [C][H][W]
+  float* out;              // [C][H][W] (nullable)
+  int32_t* gplanes;        // [np][H][W] quantised guide planes
+  uint8_t* green;          // [n_ref] GCP branch per reference
+  int32_t* idx;            // [n_ref][K]
+  long long* dist;         // [n_ref][K] (nullable)
+  int32_t* fb_list;        // [n_ref] references whose shortlist overflowed
+  int32_t* fb_count;       // [1]
+  double* cov_part;        // [n_cov][cov_elems]
+  double* basis64;         // U64[C][8][8], V64[C][8][8], eig[2][C/2+1][8]
+  float* basis;            // U[C][8][8], V[C][8][8] (real tensors)
+  float* fbasis;           // Fourier slices for the filter, see FB_* offsets
+  float* num;              // [C][H][W]
+  float* cnt;              // [H][W]
+  uint32_t* masks;         // keep-masks (nullable)
+  const uint32_t* masks_in;// frozen masks for the adjoint (nullable)
+  float* group_est;        // [ref_count][K][C][8][8] (nullable)
+  int32_t H, W, Hp, Wp, nry, nrx, n_ref;
+  int32_t ref_begin, ref_count;   // filter range
+  float sigma, tau;
+  int32_t n_cov;           // covariance partial blocks
+  int32_t woff[W_NKIND];   // first global work item of each kind (batched)
+  int32_t wcnt[W_NKIND];   // work items of each kind
+};
+
+// Fourier-domain basis layout (float32), consumed by the filter:
+//   c = 1: U0[8][8], V0[8][8]
+//   c = 3: U0, V0 (f = 0, real), U1r, U1i, V1r, V1i (f = 1, complex)
+constexpr int FB_U0 = 0, FB_V0 = 64, FB_U1R = 128, FB_U1I = 192, FB_V1R = 256, FB_V1I = 320;
+constexpr int FB_SIZE = 384;
+
+struct Launch {
+  ImgDesc one;             // used when table == nullptr
+  const ImgDesc* table;    // device table of n_img descriptors (batched)
+  int32_t n_img;
+  int32_t total;           // total work items of the launched kind
+  int32_t C, K, stride, window;
+  float tau_mult;
+  int32_t gcp_num, gcp_den;
+  int32_t flags;
+  int32_t fty, ftx;        // filter tile shape (references)
+};
+
+// Match-kernel LDS geometry for a 4x4 reference tile at stride s and window
+// w: candidate rows/cols of the union window (padded to whole 16-wide MFMA
+// blocks) and the pixel region they read.
+struct MatchGeom {
+  int ryc, rxp, pitch, rows;   // max candidate rows, padded candidate cols, LDS pitch, pixel rows
+  int off_gi, off_gb, off_nb, off_sb, off_tl, off_sl, off_misc, bytes;
+};
+__host__ __device__ inline MatchGeom match_geom(int s, int w) {
+  MatchGeom g;
+  int r = (w - 1) / 2;
+  g.ryc = (MATCH_TY - 1) * s + 2 * r + 1;
+  int rxc = (MATCH_TX - 1) * s + 2 * r + 1;
+  g.rxp = (rxc + 15) / 16 * 16;
+  g.pitch = g.rxp + 8;
+  g.rows = g.ryc + PS - 1;
+  int rgn = g.rows * g.pitch * 4;
+  g.off_gi = 0;
+  g.off_gb = g.off_gi + rgn;
+  g.off_nb = g.off_gb + rgn;
+  g.off_sb = g.off_nb + g.ryc * g.rxp * 4;
+  g.off_tl = g.off_sb + g.ryc * g.rxp * 4;
+  g.off_sl = g.off_tl + 16 * 64 * 2 * 4;
+  g.off_misc = g.off_sl + 16 * SHORT_CAP * 4;
+  g.bytes = g.off_misc + 1024;
+  return g;
+}
+
+// Grid size for for_each_item: rounded up to a multiple of the 8 XCDs.
+inline int xcd_grid(int g) { return g >= 8 ? (g + 7) / 8 * 8 : g; }
+
+// Number of references along one axis for n_valid positions and stride s.
+inline int ref_count_axis(int n_valid, int s) {
+  int n = (n_valid - 1) / s + 1;
+  if ((n - 1) * s != n_valid - 1) ++n;
+  return n;
+}
+
+__host__ __device__ inline int cov_elems(int C) { return C == 1 ? 2 * 64 : 2 * 64 + 2 * 128; }
+
+// Kernel launchers (defined in the .hip files).  Each returns hipSuccess or
+// the launch error.  `grid` = 0 means one work group per work item.
+hipError_t launch_quant(const Launch& L, int grid, hipStream_t s);
+hipError_t launch_gcp(const Launch& L, int grid, hipStream_t s);
+hipError_t launch_match(const Launch& L, int mode, int terms, int grid, hipStream_t s);
+hipError_t launch_match_fallback(const Launch& L, int grid, hipStream_t s);
+hipError_t launch_reset_counters(const Launch& L, hipStream_t s);
+hipError_t launch_cov(const Launch& L, int grid, hipStream_t s);
+hipError_t launch_eig(const Launch& L, hipStream_t s);
+hipError_t launch_fbasis(const Launch& L, hipStream_t s);
+hipError_t launch_zero_accum(const Launch& L, int grid, hipStream_t s);
+hipError_t launch_filter(const Launch& L, int shape_ty, int shape_tx, int adjoint, int grid,
+                         hipStream_t s);
+hipError_t launch_finalize(const Launch& L, int grid, hipStream_t s);
+hipError_t launch_scatter_est(const Launch& L, hipStream_t s);
+hipError_t launch_adjoint_prep(const Launch& L, int grid, hipStream_t s);
+hipError_t launch_synth(float* img, int C, int H, int W, hipStream_t s);
+
+// Filter LDS bytes for a tile shape.
+size_t filter_lds_bytes(int C, int K, int stride, int window, int ty, int tx);
+size_t match_lds_bytes(int stride, int window);
+
+}  // namespace hts

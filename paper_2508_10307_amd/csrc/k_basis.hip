@@ -1,0 +1,280 @@
+// Global circulant patch basis (Sec. III.B.1, Eq. 11-12; Alg. 1 Step 2(1)).
+//
+// In the Fourier domain of the t-product (Eq. 5-6) the basis tensors U, V
+// become one unitary 8x8 slice per frequency f of the channel-mode DFT.
+// Each slice is the eigenbasis of a second moment of the transformed
+// reference patches P^(f) = sum_j P(:,:,j) exp(-2 pi i f j / c):
+//   C_U(f) = sum_i P^_i(f) P^_i(f)^H,   C_V(f) = sum_i P^_i(f)^H P^_i(f),
+// for f = 0..floor(c/2) (the rest follow by conjugate symmetry).  All of it
+// runs in FP64: partial sums per block of references (k_cov), an ordered
+// reduction and cyclic complex Jacobi eigen-solves (k_eig), then the real
+// tensors U(:,:,j) = (1/c) sum_f U_F(f) exp(+2 pi i f j / c).
+#include "hts_device.h"
+
+namespace hts {
+
+constexpr int COV_SUB = 16;   // references staged in LDS at a time
+
+__device__ inline void dft3(double p0, double p1, double p2, double& f0, double& f1r, double& f1i) {
+  // P^(0) = p0 + p1 + p2;  P^(1) = p0 + w p1 + w^2 p2, w = exp(-2 pi i / 3)
+  f0 = p0 + p1 + p2;
+  f1r = p0 - 0.5 * (p1 + p2);
+  f1i = 0.86602540378443864676 * (p2 - p1);
+}
+
+// Partial covariances of the references [item*COV_REFS, ...): layout per
+// item: C_U(0)[8][8], C_V(0)[8][8], then for c = 3 C_U(1), C_V(1) as
+// interleaved (re, im) [8][8][2].
+__global__ __launch_bounds__(256) void k_cov(Launch L) {
+  __shared__ double X0[COV_SUB][64];
+  __shared__ double X1r[COV_SUB][64];
+  __shared__ double X1i[COV_SUB][64];
+  const int tid = threadIdx.x;
+  const int nel = cov_elems(L.C);
+  for_each_item<W_COV>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
+    const int HW = d.H * d.W;
+    double acc[2] = {0.0, 0.0};  // elements tid and tid + 256
+    const int r_begin = item * COV_REFS;
+    const int r_end = min(d.n_ref, r_begin + COV_REFS);
+    for (int r0 = r_begin; r0 < r_end; r0 += COV_SUB) {
+      const int nsub = min(COV_SUB, r_end - r0);
+      __syncthreads();
+      for (int e = tid; e < nsub * 64; e += 256) {
+        const int i = e >> 6, px = e & 63;
+        const int ref = r0 + i;
+        const int ry = ref_coord(ref / d.nrx, L.stride, d.Hp);
+        const int rx = ref_coord(ref % d.nrx, L.stride, d.Wp);
+        const int off = (ry + (px >> 3)) * d.W + rx + (px & 7);
+        if (L.C == 1) {
+          X0[i][px] = (double)d.img[off];
+        } else {
+          double f0, f1r, f1i;
+          dft3((double)d.img[off], (double)d.img[HW + off], (double)d.img[2 * HW + off], f0, f1r, f1i);
+          X0[i][px] = f0;
+          X1r[i][px] = f1r;
+          X1i[i][px] = f1i;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int e = tid + 256 * h;
+        if (e >= nel) continue;
+        double s = 0.0;
+        if (e < 128) {
+          const int a = (e & 63) >> 3, b = e & 7;
+          const bool rowsp = e < 64;  // C_U: rows a, b ; C_V: columns a, b
+          for (int i = 0; i < nsub; ++i)
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+              s += rowsp ? X0[i][a * 8 + t] * X0[i][b * 8 + t] : X0[i][t * 8 + a] * X0[i][t * 8 + b];
+        } else {
+          const int q = e - 128;
+          const bool rowsp = q < 128;
+          const int qq = q & 127;
+          const int ab = qq >> 1, a = ab >> 3, b = ab & 7;
+          const bool im = qq & 1;
+          for (int i = 0; i < nsub; ++i)
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+              if (rowsp) {  // sum_t Z[a][t] conj(Z[b][t])
+                const double ar = X1r[i][a * 8 + t], ai = X1i[i][a * 8 + t];
+                const double br = X1r[i][b * 8 + t], bi = X1i[i][b * 8 + t];
+                s += im ? (ai * br - ar * bi) : (ar * br + ai * bi);
+              } else {      // sum_t conj(Z[t][a]) Z[t][b]
+                const double ar = X1r[i][t * 8 + a], ai = X1i[i][t * 8 + a];
+                const double br = X1r[i][t * 8 + b], bi = X1i[i][t * 8 + b];
+                s += im ? (ar * bi - ai * br) : (ar * br + ai * bi);
+              }
+            }
+        }
+        acc[h] += s;
+      }
+    }
+    if (tid < nel) d.cov_part[(size_t)item * nel + tid] = acc[0];
+    if (tid + 256 < nel) d.cov_part[(size_t)item * nel + tid + 256] = acc[1];
+  });
+}
+
+// Cyclic Jacobi for an 8x8 Hermitian matrix (re/im parts); on return the
+// diagonal of (ar, ai) holds the eigenvalues and (vr, vi) the eigenvectors
+// (columns).  Each rotation G = diag(1, e^{-i phi}) [[c, s], [-s, c]] on
+// columns/rows p, q zeroes A(p,q) = |A(p,q)| e^{i phi}.
+__device__ void jacobi_herm8(double (*ar)[8], double (*ai)[8], double (*vr)[8], double (*vi)[8]) {
+  double fn = 0.0;
+  for (int i = 0; i < 8; ++i)
+    for (int j = 0; j < 8; ++j) {
+      vr[i][j] = (i == j);
+      vi[i][j] = 0.0;
+      fn += ar[i][j] * ar[i][j] + ai[i][j] * ai[i][j];
+    }
+  const double tiny = 1e-17 * sqrt(fn);
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    bool rotated = false;
+    for (int p = 0; p < 7; ++p)
+      for (int q = p + 1; q < 8; ++q) {
+        const double br = ar[p][q], bi = ai[p][q];
+        const double mag = sqrt(br * br + bi * bi);
+        const double app = ar[p][p], aqq = ar[q][q];
+        if (mag <= tiny) { ar[p][q] = ar[q][p] = 0.0; ai[p][q] = ai[q][p] = 0.0; continue; }
+        rotated = true;
+        const double zeta = (aqq - app) / (2.0 * mag);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+        const double er = br / mag, ei = bi / mag;     // e^{i phi}
+        // G = [[c, s], [-s e^{-i phi}, c e^{-i phi}]] (entries (p,p),(p,q),(q,p),(q,q))
+        const double gpp_r = c, gpp_i = 0.0, gpq_r = s, gpq_i = 0.0;
+        const double gqp_r = -s * er, gqp_i = s * ei;  // -s e^{-i phi}
+        const double gqq_r = c * er, gqq_i = -c * ei;  //  c e^{-i phi}
+        // A <- A G (columns p, q)
+        for (int k = 0; k < 8; ++k) {
+          const double xr = ar[k][p], xi = ai[k][p], yr = ar[k][q], yi = ai[k][q];
+          ar[k][p] = xr * gpp_r - xi * gpp_i + yr * gqp_r - yi * gqp_i;
+          ai[k][p] = xr * gpp_i + xi * gpp_r + yr * gqp_i + yi * gqp_r;
+          ar[k][q] = xr * gpq_r - xi * gpq_i + yr * gqq_r - yi * gqq_i;
+          ai[k][q] = xr * gpq_i + xi * gpq_r + yr * gqq_i + yi * gqq_r;
+          const double ur = vr[k][p], ui = vi[k][p], wr = vr[k][q], wi = vi[k][q];
+          vr[k][p] = ur * gpp_r - ui * gpp_i + wr * gqp_r - wi * gqp_i;
+          vi[k][p] = ur * gpp_i + ui * gpp_r + wr * gqp_i + wi * gqp_r;
+          vr[k][q] = ur * gpq_r - ui * gpq_i + wr * gqq_r - wi * gqq_i;
+          vi[k][q] = ur * gpq_i + ui * gpq_r + wr * gqq_i + wi * gqq_r;
+        }
+        // A <- G^H A (rows p, q)
+        for (int k = 0; k < 8; ++k) {
+          const double xr = ar[p][k], xi = ai[p][k], yr = ar[q][k], yi = ai[q][k];
+          ar[p][k] = gpp_r * xr + gpp_i * xi + gqp_r * yr + gqp_i * yi;
+          ai[p][k] = gpp_r * xi - gpp_i * xr + gqp_r * yi - gqp_i * yr;
+          ar[q][k] = gpq_r * xr + gpq_i * xi + gqq_r * yr + gqq_i * yi;
+          ai[q][k] = gpq_r * xi - gpq_i * xr + gqq_r * yi - gqq_i * yr;
+        }
+        ar[p][q] = ar[q][p] = 0.0;
+        ai[p][q] = ai[q][p] = 0.0;
+        ai[p][p] = ai[q][q] = 0.0;
+      }
+    if (!rotated) break;
+  }
+}
+
+// One work group per image: ordered reduction of the partials, eigen-solves
+// (one thread per covariance matrix), descending order, phase convention
+// (largest-modulus entry real positive, first on ties), real tensors.
+__global__ __launch_bounds__(256) void k_eig(Launch L) {
+  __shared__ double cov[384];
+  __shared__ double mr[4][8][8], mi[4][8][8], vr[4][8][8], vi[4][8][8];
+  __shared__ double UF[2][2][8][8][2];  // [U/V][f][row][col][re/im], sorted + phased
+  __shared__ double ev[2][2][8];
+  const int tid = threadIdx.x;
+  const int nel = cov_elems(L.C);
+  const int nm = L.C == 1 ? 2 : 4;
+  const int nimg = L.table ? L.n_img : 1;
+  for (int im = blockIdx.x; im < nimg; im += gridDim.x) {
+    const ImgDesc d = L.table ? L.table[im] : L.one;
+    __syncthreads();
+    for (int e = tid; e < nel; e += blockDim.x) {
+      double s = 0.0;
+      for (int j = 0; j < d.n_cov; ++j) s += d.cov_part[(size_t)j * nel + e];
+      cov[e] = s;
+    }
+    __syncthreads();
+    for (int e = tid; e < nm * 64; e += blockDim.x) {
+      const int m = e >> 6, a = (e >> 3) & 7, b = e & 7;
+      if (m < 2) { mr[m][a][b] = cov[m * 64 + a * 8 + b]; mi[m][a][b] = 0.0; }
+      else { const int base = 128 + (m - 2) * 128 + (a * 8 + b) * 2; mr[m][a][b] = cov[base]; mi[m][a][b] = cov[base + 1]; }
+    }
+    __syncthreads();
+    if (tid < nm) {
+      const int m = tid;
+      jacobi_herm8(mr[m], mi[m], vr[m], vi[m]);
+      // descending eigenvalues, stable
+      int order[8];
+      for (int k = 0; k < 8; ++k) order[k] = k;
+      for (int a = 1; a < 8; ++a) {
+        int key = order[a], b = a - 1;
+        while (b >= 0 && mr[m][order[b]][order[b]] < mr[m][key][key]) { order[b + 1] = order[b]; --b; }
+        order[b + 1] = key;
+      }
+      const int uv = m & 1, f = m >> 1;  // m: 0 = C_U(0), 1 = C_V(0), 2 = C_U(1), 3 = C_V(1)
+      for (int k = 0; k < 8; ++k) {
+        const int src = order[k];
+        ev[uv][f][k] = mr[m][src][src];
+        int best = 0;
+        double bm = -1.0;
+        for (int a = 0; a < 8; ++a) {
+          const double mm = vr[m][a][src] * vr[m][a][src] + vi[m][a][src] * vi[m][a][src];
+          if (mm > bm) { bm = mm; best = a; }
+        }
+        const double nr = sqrt(bm);
+        const double pr = vr[m][best][src] / nr, pi = -vi[m][best][src] / nr;  // conj(v)/|v|
+        for (int a = 0; a < 8; ++a) {
+          const double xr = vr[m][a][src], xi = vi[m][a][src];
+          UF[uv][f][a][k][0] = xr * pr - xi * pi;
+          UF[uv][f][a][k][1] = xr * pi + xi * pr;
+        }
+        UF[uv][f][best][k][1] = 0.0;
+      }
+    }
+    __syncthreads();
+    // real tensors: c = 1: U = U_F(0); c = 3: U(:,:,j) = (U_F(0) + 2 Re(U_F(1) e^{2 pi i j/3})) / 3
+    for (int e = tid; e < 2 * L.C * 64; e += blockDim.x) {
+      const int uv = e / (L.C * 64), rem = e % (L.C * 64), j = rem >> 6, ab = rem & 63;
+      const int a = ab >> 3, b = ab & 7;
+      double val;
+      if (L.C == 1) {
+        val = UF[uv][0][a][b][0];
+      } else {
+        const double c0 = UF[uv][0][a][b][0], r1 = UF[uv][1][a][b][0], i1 = UF[uv][1][a][b][1];
+        const double cs = j == 0 ? 1.0 : -0.5;
+        const double sn = j == 0 ? 0.0 : (j == 1 ? 0.86602540378443864676 : -0.86602540378443864676);
+        val = (c0 + 2.0 * (r1 * cs - i1 * sn)) / 3.0;
+      }
+      const int off = uv * L.C * 64 + j * 64 + ab;
+      d.basis64[off] = val;
+      d.basis[off] = (float)val;
+    }
+    const int nf = L.C / 2 + 1;
+    for (int e = tid; e < 2 * nf * 8; e += blockDim.x) {
+      const int uv = e / (nf * 8), f = (e / 8) % nf, k = e % 8;
+      d.basis64[2 * L.C * 64 + e] = ev[uv][f][k];
+    }
+  }
+}
+
+// Fourier slices (float) of the real basis tensors for the filter:
+// U_F(f) = sum_j U(:,:,j) exp(-2 pi i f j / c), evaluated in FP64.
+__global__ void k_fbasis(Launch L) {
+  const int nimg = L.table ? L.n_img : 1;
+  for (int im = blockIdx.x; im < nimg; im += gridDim.x) {
+    const ImgDesc d = L.table ? L.table[im] : L.one;
+    for (int e = threadIdx.x; e < 128; e += blockDim.x) {
+      const int uv = e >> 6, ab = e & 63;
+      const float* T = d.basis + uv * L.C * 64;
+      if (L.C == 1) {
+        d.fbasis[(uv ? FB_V0 : FB_U0) + ab] = T[ab];
+      } else {
+        double f0, f1r, f1i;
+        dft3((double)T[ab], (double)T[64 + ab], (double)T[128 + ab], f0, f1r, f1i);
+        d.fbasis[(uv ? FB_V0 : FB_U0) + ab] = (float)f0;
+        d.fbasis[(uv ? FB_V1R : FB_U1R) + ab] = (float)f1r;
+        d.fbasis[(uv ? FB_V1I : FB_U1I) + ab] = (float)f1i;
+      }
+    }
+  }
+}
+
+hipError_t launch_cov(const Launch& L, int grid, hipStream_t s) {
+  if (L.total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cov, dim3(xcd_grid(grid > 0 && grid < L.total ? grid : L.total)), dim3(256), 0, s, L);
+  return hipGetLastError();
+}
+hipError_t launch_eig(const Launch& L, hipStream_t s) {
+  const int n = L.table ? L.n_img : 1;
+  hipLaunchKernelGGL(k_eig, dim3(n), dim3(256), 0, s, L);
+  return hipGetLastError();
+}
+hipError_t launch_fbasis(const Launch& L, hipStream_t s) {
+  const int n = L.table ? L.n_img : 1;
+  hipLaunchKernelGGL(k_fbasis, dim3(n), dim3(128), 0, s, L);
+  return hipGetLastError();
+}
+
+}  // namespace hts

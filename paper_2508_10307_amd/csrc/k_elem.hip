@@ -1,0 +1,154 @@
+// Element-wise stages: guide quantisation (Eq. 10 inputs), GCP branch per
+// reference (Eq. 10), clearing of accumulators and counters, and the
+// averaged write-back out = num / cnt (Eq. 2).
+#include "hts_device.h"
+
+namespace hts {
+
+// Guide planes from the noisy image: C = 1 -> q; C = 3 -> (qG, qR + qG + qB).
+__global__ __launch_bounds__(256) void k_quant(Launch L) {
+  for_each_item<W_PIX>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
+    const int HW = d.H * d.W;
+    const int p0 = item * PIX_CHUNK;
+    const int p1 = min(HW, p0 + PIX_CHUNK);
+    for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+      if (L.C == 1) {
+        d.gplanes[p] = quantize(d.img[p]);
+      } else {
+        int qr = quantize(d.img[p]);
+        int qg = quantize(d.img[HW + p]);
+        int qb = quantize(d.img[2 * HW + p]);
+        d.gplanes[p] = qg;
+        d.gplanes[HW + p] = qr + qg + qb;
+      }
+    }
+  });
+}
+
+// Eq. 10 branch of every reference: green guide when
+// num^2 |qG|^2 >= den^2 max(|qR|^2, |qB|^2) on the reference patch (exact int64).
+__global__ __launch_bounds__(256) void k_gcp(Launch L) {
+  for_each_item<W_REF>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
+    const int r = item * 256 + threadIdx.x;
+    if (r >= d.n_ref) return;
+    if (L.C == 1) { d.green[r] = 1; return; }
+    const int ry = ref_coord(r / d.nrx, L.stride, d.Hp);
+    const int rx = ref_coord(r % d.nrx, L.stride, d.Wp);
+    const int HW = d.H * d.W;
+    long long n[3] = {0, 0, 0};
+    for (int c = 0; c < 3; ++c)
+      for (int a = 0; a < PS; ++a)
+        for (int b = 0; b < PS; ++b) {
+          long long q = quantize(d.img[c * HW + (ry + a) * d.W + rx + b]);
+          n[c] += q * q;
+        }
+    long long lhs = (long long)L.gcp_num * L.gcp_num * n[1];
+    long long rhs = (long long)L.gcp_den * L.gcp_den * (n[0] > n[2] ? n[0] : n[2]);
+    d.green[r] = lhs >= rhs ? 1 : 0;
+  });
+}
+
+__global__ void k_reset_counters(Launch L) {
+  if (!L.table) {
+    if (threadIdx.x == 0) *L.one.fb_count = 0;
+    return;
+  }
+  for (int i = threadIdx.x; i < L.n_img; i += blockDim.x) *L.table[i].fb_count = 0;
+}
+
+// num = 0, cnt = 0 (a fill kernel rather than a memset so that the
+// sequence stays valid inside captured graphs).
+__global__ __launch_bounds__(256) void k_zero_accum(Launch L) {
+  for_each_item<W_PIX>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
+    const int HW = d.H * d.W;
+    const int p0 = item * PIX_CHUNK;
+    const int p1 = min(HW, p0 + PIX_CHUNK);
+    for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+      for (int c = 0; c < L.C; ++c) d.num[c * HW + p] = 0.0f;
+      if (d.cnt) d.cnt[p] = 0.0f;
+    }
+  });
+}
+
+// Eq. 2 with uniform weights: out = num / cnt.
+__global__ __launch_bounds__(256) void k_finalize(Launch L) {
+  for_each_item<W_PIX>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
+    const int HW = d.H * d.W;
+    const int p0 = item * PIX_CHUNK;
+    const int p1 = min(HW, p0 + PIX_CHUNK);
+    for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+      float inv = 1.0f / d.cnt[p];
+      for (int c = 0; c < L.C; ++c) d.out[c * HW + p] = d.num[c * HW + p] * inv;
+    }
+  });
+}
+
+// Adjoint input: r = g / cnt into the workspace image buffer (d.out holds g,
+// d.num receives r; see hts_denoise_backward).
+__global__ __launch_bounds__(256) void k_adjoint_prep(Launch L) {
+  for_each_item<W_PIX>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
+    const int HW = d.H * d.W;
+    const int p0 = item * PIX_CHUNK;
+    const int p1 = min(HW, p0 + PIX_CHUNK);
+    for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+      float inv = 1.0f / d.cnt[p];
+      for (int c = 0; c < L.C; ++c) d.num[c * HW + p] = d.img[c * HW + p] * inv;
+    }
+  });
+}
+
+static int grid_for(const Launch& L, int grid) { return xcd_grid(grid > 0 && grid < L.total ? grid : L.total); }
+
+hipError_t launch_quant(const Launch& L, int grid, hipStream_t s) {
+  if (L.total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_quant, dim3(grid_for(L, grid)), dim3(256), 0, s, L);
+  return hipGetLastError();
+}
+hipError_t launch_gcp(const Launch& L, int grid, hipStream_t s) {
+  if (L.total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gcp, dim3(grid_for(L, grid)), dim3(256), 0, s, L);
+  return hipGetLastError();
+}
+hipError_t launch_reset_counters(const Launch& L, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(256), 0, s, L);
+  return hipGetLastError();
+}
+hipError_t launch_zero_accum(const Launch& L, int grid, hipStream_t s) {
+  if (L.total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_accum, dim3(grid_for(L, grid)), dim3(256), 0, s, L);
+  return hipGetLastError();
+}
+hipError_t launch_finalize(const Launch& L, int grid, hipStream_t s) {
+  if (L.total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finalize, dim3(grid_for(L, grid)), dim3(256), 0, s, L);
+  return hipGetLastError();
+}
+hipError_t launch_adjoint_prep(const Launch& L, int grid, hipStream_t s) {
+  if (L.total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adjoint_prep, dim3(grid_for(L, grid)), dim3(256), 0, s, L);
+  return hipGetLastError();
+}
+
+}  // namespace hts
+
+namespace hts {
+
+// Deterministic structured test image for the autotuner: smooth pattern plus
+// a hashed pseudo-noise of standard deviation ~25.
+__global__ __launch_bounds__(256) void k_synth(float* img, int C, int H, int W) {
+  const int n = C * H * W;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int c = i / (H * W), p = i % (H * W), y = p / W, x = p % W;
+    unsigned h = (unsigned)i * 2654435761u + 12345u;
+    h ^= h >> 15; h *= 2246822519u; h ^= h >> 13; h *= 3266489917u; h ^= h >> 16;
+    const float u = (h & 0xFFFFFF) * (1.0f / 16777216.0f) - 0.5f;
+    img[i] = 128.f + 60.f * __sinf(x * 0.13f + c) * __cosf(y * 0.09f) + 86.6f * u;
+  }
+}
+
+hipError_t launch_synth(float* img, int C, int H, int W, hipStream_t s) {
+  hipLaunchKernelGGL(k_synth, dim3(1024), dim3(256), 0, s, img, C, H, W);
+  return hipGetLastError();
+}
+
+}  // namespace hts

@@ -1,0 +1,444 @@
+// Collaborative filtering and aggregation (Sec. III.B.2, Eq. 17-20; Eq. 2;
+// Alg. 1 Step 2(2)-(4) and Step 3), fused in one kernel.
+//
+// One work group per tile of references; each wavefront filters one group
+// at a time.  Lane = (slot lane kl, patch row a): lane kl*8 + a holds row a
+// of the K/8 slots kl*SPL .. kl*SPL+SPL-1 for every channel, so
+//  * the right products X V run inside the lane, with the 8x8 basis slices
+//    (uniform across the wavefront) as scalar operands;
+//  * the left products U^H Y run inside the lane after an 8x8 transpose
+//    through LDS;
+//  * the channel-mode DFT of the t-product (c = 3) is lane-local;
+//  * the Haar transform along the group mode (Eq. 9, fast form: pairwise
+//    sums and differences / sqrt 2) runs first on the slots of a lane, then
+//    across lanes with xor shuffles;
+//  * thresholding, masks and the inverse transforms follow the same layout;
+//  * estimates and coverage counts accumulate into an LDS tile covering
+//    every patch the tile's groups can touch, flushed once with atomics.
+// ADJ = 1 applies frozen masks instead of the threshold and accumulates
+// without counts (adjoint of the frozen map, see hts_denoise_backward).
+#include "hts_device.h"
+
+namespace hts {
+
+constexpr float RSQRT2 = 0.70710678118654752440f;
+constexpr float SQRT3 = 1.73205080756887729353f;
+constexpr float HALF_SQRT3 = 0.86602540378443864676f;
+constexpr int TPITCH = 9;                 // transpose scratch pitch (floats)
+constexpr int TSCRATCH = 8 * 8 * TPITCH;  // floats per wavefront
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Basis slices are read through the constant address space: they are the
+// same for every lane, so they become scalar loads into SGPRs and feed the
+// FMAs as scalar operands.
+typedef __attribute__((address_space(4))) const float cfloat;
+
+// A pointer known to be the same in every lane, moved to SGPRs.
+__device__ inline const cfloat* uniform_ptr(const float* p) {
+  const unsigned long long v = (unsigned long long)p;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return (const cfloat*)(((unsigned long long)hi << 32) | lo);
+}
+
+// The pointer is passed through an empty asm so that the compiler cannot
+// hoist a slice's 64 scalar loads out of the group loop (it would then keep
+// all 384 coefficients live and spill SGPRs into VGPR lanes).
+__device__ inline const cfloat* launder(const cfloat* p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
+// y[b] (+)= sgn * sum_t x[t] M[t*8 + b]   (TR = 0)
+// y[b] (+)= sgn * sum_t x[t] M[b*8 + t]   (TR = 1)
+// with one 8x8 basis slice (64 scalar operands) per call.
+template <int TR, bool ACC>
+__device__ inline void mv(const float (&x)[8], const cfloat* M0, float sgn, float (&y)[8]) {
+  const cfloat* M = launder(M0);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    float s = ACC ? y[b] : 0.f;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) s = fmaf(sgn * x[t], M[TR ? b * 8 + t : t * 8 + b], s);
+    y[b] = s;
+  }
+}
+
+// Transposes through the wavefront's LDS scratch.  Forward: lane (kl, a)
+// holds row a of an 8x8 matrix and receives column a.  Backward: holds
+// column a and receives row a.
+__device__ inline void transpose_rc(float* T, int kl, int a, float (&v)[8]) {
+  float* base = T + kl * 8 * TPITCH;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) base[a * TPITCH + c] = v[c];
+  wave_sync();
+#pragma unroll
+  for (int r = 0; r < 8; ++r) v[r] = base[r * TPITCH + a];
+  wave_sync();
+}
+__device__ inline void transpose_cr(float* T, int kl, int a, float (&v)[8]) {
+  float* base = T + kl * 8 * TPITCH;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) base[r * TPITCH + a] = v[r];
+  wave_sync();
+#pragma unroll
+  for (int c = 0; c < 8; ++c) v[c] = base[a * TPITCH + c];
+  wave_sync();
+}
+
+// Haar row (Eq. 9 ordering) of the coefficient produced for group slot k.
+__device__ inline int haar_row(int k, int K) {
+  if (k == 0) return 0;
+  const int L = __builtin_ctz(k) + 1;
+  return (K >> L) + (k >> L);
+}
+
+template <int C, int SPL, int ADJ>
+__global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
+  extern __shared__ __align__(16) float fsm[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int kl = lane >> 3, a = lane & 7;
+  const int K = L.K;
+  const int NL = K < 8 ? K : 8;         // slot lanes in use
+  const bool active = kl < NL;
+  const int r = (L.window - 1) / 2;
+  const int s = L.stride;
+  const int TY = L.fty, TX = L.ftx;
+  const int RA = (TY - 1) * s + 2 * r + PS, CA = (TX - 1) * s + 2 * r + PS;
+  const int NP = C + 1;
+  float* acc = fsm;                                   // [NP][RA][CA]
+  float* T = fsm + NP * RA * CA + wave * TSCRATCH;    // this wavefront's transpose scratch
+
+  for_each_item<W_FILT>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
+    const int ntx = (d.nrx + TX - 1) / TX;
+    const int iy0 = (item / ntx) * TY, ix0 = (item % ntx) * TX;
+    const int iy1 = min(d.nry, iy0 + TY) - 1, ix1 = min(d.nrx, ix0 + TX) - 1;
+    const int AY0 = max(0, ref_coord(iy0, s, d.Hp) - r);
+    const int AY1 = min(d.Hp - 1, ref_coord(iy1, s, d.Hp) + r) + PS - 1;
+    const int AX0 = max(0, ref_coord(ix0, s, d.Wp) - r);
+    const int AX1 = min(d.Wp - 1, ref_coord(ix1, s, d.Wp) + r) + PS - 1;
+    const int AW = AX1 - AX0 + 1, AH = AY1 - AY0 + 1;
+    const int HW = d.H * d.W;
+    const cfloat* fb = uniform_ptr(d.fbasis);
+    const float tau = d.tau;
+
+    __syncthreads();
+    for (int e = tid; e < NP * RA * CA; e += 256) acc[e] = 0.f;
+    __syncthreads();
+
+    const int ngroups = (iy1 - iy0 + 1) * (ix1 - ix0 + 1);
+    for (int gl = wave; gl < ngroups; gl += 4) {
+      const int gw = ix1 - ix0 + 1;
+      const int g = (iy0 + gl / gw) * d.nrx + ix0 + gl % gw;
+      if (g < d.ref_begin || g >= d.ref_begin + d.ref_count) continue;
+      const int grel = g - d.ref_begin;
+
+      // ---- gather ----
+      float X[SPL][C][8];
+      int py[SPL], px[SPL];
+#pragma unroll
+      for (int j = 0; j < SPL; ++j) {
+        const int k = kl * SPL + j;
+        const int pos = active ? d.idx[(size_t)g * K + k] : 0;
+        // positions come from the caller's idx: clamp to valid patch corners
+        py[j] = min(max(pos / d.W, 0), d.Hp - 1);
+        px[j] = min(max(pos - (pos / d.W) * d.W, 0), d.Wp - 1);
+        const float* src = d.img + (py[j] + a) * d.W + px[j];
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch)
+#pragma unroll
+          for (int b = 0; b < 8; ++b) X[j][ch][b] = active ? src[ch * HW + b] : 0.f;
+      }
+
+      // ---- t-SVD projection U^T * P * V per slot (Eq. 18, patch level) ----
+#pragma unroll
+      for (int j = 0; j < SPL; ++j) {
+        __builtin_amdgcn_sched_barrier(0);  // keep one slot's temporaries live at a time
+        if (C == 1) {
+          float y[8];
+          mv<0, false>(X[j][0], fb + FB_V0, 1.f, y);
+          transpose_rc(T, kl, a, y);
+          float z[8];
+          mv<0, false>(y, fb + FB_U0, 1.f, z);   // z[i] = sum_r y[r] U[r][i]
+#pragma unroll
+          for (int i = 0; i < 8; ++i) X[j][0][i] = z[i];
+        } else {
+          float f0[8], f1r[8], f1i[8];
+#pragma unroll
+          for (int b = 0; b < 8; ++b) {
+            const float p0 = X[j][0][b], p1 = X[j][1][b], p2 = X[j][2][b];
+            f0[b] = p0 + p1 + p2;
+            f1r[b] = p0 - 0.5f * (p1 + p2);
+            f1i[b] = HALF_SQRT3 * (p2 - p1);
+          }
+          float y0[8], y1r[8], y1i[8];
+          // Y = P^ V_F: f = 0 real, f = 1 complex (one real slice per pass)
+          mv<0, false>(f0, fb + FB_V0, 1.f, y0);
+          mv<0, false>(f1r, fb + FB_V1R, 1.f, y1r);
+          mv<0, false>(f1i, fb + FB_V1R, 1.f, y1i);
+          mv<0, true>(f1i, fb + FB_V1I, -1.f, y1r);
+          mv<0, true>(f1r, fb + FB_V1I, 1.f, y1i);
+          transpose_rc(T, kl, a, y0);
+          transpose_rc(T, kl, a, y1r);
+          transpose_rc(T, kl, a, y1i);
+          // Z = U_F^H Y: z[i] = sum_r conj(U[r][i]) y[r]
+          float z0[8], z1r[8], z1i[8];
+          mv<0, false>(y0, fb + FB_U0, 1.f, z0);
+          mv<0, false>(y1r, fb + FB_U1R, 1.f, z1r);
+          mv<0, false>(y1i, fb + FB_U1R, 1.f, z1i);
+          mv<0, true>(y1i, fb + FB_U1I, 1.f, z1r);
+          mv<0, true>(y1r, fb + FB_U1I, -1.f, z1i);
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const float sr = z1r[i], si = z1i[i];
+            // inverse DFT along the channel mode
+            X[j][0][i] = (z0[i] + 2.f * sr) * (1.f / 3.f);
+            X[j][1][i] = (z0[i] - sr - SQRT3 * si) * (1.f / 3.f);
+            X[j][2][i] = (z0[i] - sr + SQRT3 * si) * (1.f / 3.f);
+          }
+        }
+      }
+
+      // ---- Haar along the group mode (Eq. 17-18), in-lane levels ----
+#pragma unroll
+      for (int st = 1; st < SPL; st <<= 1)
+#pragma unroll
+        for (int j = 0; j < SPL; j += 2 * st)
+#pragma unroll
+          for (int ch = 0; ch < C; ++ch)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+              const float u = X[j][ch][i], v = X[j + st][ch][i];
+              X[j][ch][i] = (u + v) * RSQRT2;
+              X[j + st][ch][i] = (u - v) * RSQRT2;
+            }
+      // cross-lane levels on the running sums (slot lanes kl ^ m)
+      for (int m = 1; m < NL; m <<= 1) {
+        const bool part = (kl & (m - 1)) == 0;
+        const bool upper = (kl & m) != 0;
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch)
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const float o = __shfl_xor(X[0][ch][i], 8 * m, 64);
+            const float nv = upper ? (o - X[0][ch][i]) * RSQRT2 : (X[0][ch][i] + o) * RSQRT2;
+            X[0][ch][i] = part ? nv : X[0][ch][i];
+          }
+      }
+
+      // ---- hard threshold (Eq. 19) or frozen mask; optional mask export ----
+#pragma unroll
+      for (int j = 0; j < SPL; ++j) {
+        const int k = kl * SPL + j;
+        const int row = haar_row(k, K);
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch) {
+          const size_t word = ((size_t)grel * K + row) * C + ch;   // 64-bit word index
+          if (ADJ) {
+            unsigned long long bits = 0;
+            if (active) {
+              const uint32_t* w = d.masks_in + 2 * word;
+              bits = (unsigned long long)w[0] | ((unsigned long long)w[1] << 32);
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+              if (!((bits >> (i * 8 + a)) & 1ull)) X[j][ch][i] = 0.f;
+          } else {
+            unsigned char mybyte = 0;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+              const bool keep = fabsf(X[j][ch][i]) >= tau;
+              if (!keep) X[j][ch][i] = 0.f;
+              if (d.masks) {
+                const unsigned long long bal = __ballot(keep);
+                const unsigned char byte = (unsigned char)((bal >> (8 * kl)) & 0xFFu);
+                if (i == a) mybyte = byte;
+              }
+            }
+            if (d.masks && active) ((unsigned char*)d.masks)[word * 8 + a] = mybyte;
+          }
+        }
+      }
+
+      // ---- inverse Haar: cross-lane levels (coarse first), then in-lane ----
+      for (int m = NL >> 1; m >= 1; m >>= 1) {
+        const bool part = (kl & (m - 1)) == 0;
+        const bool upper = (kl & m) != 0;
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch)
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const float o = __shfl_xor(X[0][ch][i], 8 * m, 64);
+            const float nv = upper ? (o - X[0][ch][i]) * RSQRT2 : (X[0][ch][i] + o) * RSQRT2;
+            X[0][ch][i] = part ? nv : X[0][ch][i];
+          }
+      }
+#pragma unroll
+      for (int st = SPL >> 1; st >= 1; st >>= 1)
+#pragma unroll
+        for (int j = 0; j < SPL; j += 2 * st)
+#pragma unroll
+          for (int ch = 0; ch < C; ++ch)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+              const float u = X[j][ch][i], v = X[j + st][ch][i];
+              X[j][ch][i] = (u + v) * RSQRT2;
+              X[j + st][ch][i] = (u - v) * RSQRT2;
+            }
+
+      // ---- inverse t-SVD projection U * S * V^T (Eq. 20) and write-back ----
+#pragma unroll
+      for (int j = 0; j < SPL; ++j) {
+        __builtin_amdgcn_sched_barrier(0);  // keep one slot's temporaries live at a time
+        float out[C][8];
+        if (C == 1) {
+          float y[8];
+          mv<1, false>(X[j][0], fb + FB_U0, 1.f, y);   // y[r] = sum_i U[r][i] s[i]
+          transpose_cr(T, kl, a, y);
+          mv<1, false>(y, fb + FB_V0, 1.f, out[0]);   // out[b] = sum_c y[c] V[b][c]
+        } else {
+          float s0[8], s1r[8], s1i[8];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const float q0 = X[j][0][i], q1 = X[j][1][i], q2 = X[j][2][i];
+            s0[i] = q0 + q1 + q2;
+            s1r[i] = q0 - 0.5f * (q1 + q2);
+            s1i[i] = HALF_SQRT3 * (q2 - q1);
+          }
+          // Y = U_F S^: y[r] = sum_i U[r][i] s[i]
+          float y0[8], y1r[8], y1i[8];
+          mv<1, false>(s0, fb + FB_U0, 1.f, y0);
+          mv<1, false>(s1r, fb + FB_U1R, 1.f, y1r);
+          mv<1, false>(s1i, fb + FB_U1R, 1.f, y1i);
+          mv<1, true>(s1i, fb + FB_U1I, -1.f, y1r);
+          mv<1, true>(s1r, fb + FB_U1I, 1.f, y1i);
+          transpose_cr(T, kl, a, y0);
+          transpose_cr(T, kl, a, y1r);
+          transpose_cr(T, kl, a, y1i);
+          // P^ = Y V_F^H: p[b] = sum_c y[c] conj(V[b][c])
+          float p0[8], p1r[8], p1i[8];
+          mv<1, false>(y0, fb + FB_V0, 1.f, p0);
+          mv<1, false>(y1r, fb + FB_V1R, 1.f, p1r);
+          mv<1, false>(y1i, fb + FB_V1R, 1.f, p1i);
+          mv<1, true>(y1i, fb + FB_V1I, 1.f, p1r);
+          mv<1, true>(y1r, fb + FB_V1I, -1.f, p1i);
+#pragma unroll
+          for (int b = 0; b < 8; ++b) {
+            const float sr = p1r[b], si = p1i[b];
+            out[0][b] = (p0[b] + 2.f * sr) * (1.f / 3.f);
+            out[1][b] = (p0[b] - sr - SQRT3 * si) * (1.f / 3.f);
+            out[2][b] = (p0[b] - sr + SQRT3 * si) * (1.f / 3.f);
+          }
+        }
+        const int ly = py[j] + a - AY0, lx = px[j] - AX0;
+        // a patch outside the tile's reach (idx not from this reference's
+        // search window) is not aggregated
+        const bool inside = ly >= a && ly + PS - a <= AH && lx >= 0 && lx + PS <= AW;
+        if (active && inside) {
+          const int k = kl * SPL + j;
+#pragma unroll
+          for (int ch = 0; ch < C; ++ch) {
+            float* rowp = acc + (ch * RA + ly) * CA + lx;
+#pragma unroll
+            for (int b = 0; b < 8; ++b) atomicAdd(rowp + b, out[ch][b]);
+          }
+          if (!ADJ) {
+            float* rowp = acc + (C * RA + ly) * CA + lx;
+#pragma unroll
+            for (int b = 0; b < 8; ++b) atomicAdd(rowp + b, 1.0f);
+          }
+          if (d.group_est) {
+            float* ge = d.group_est + (((size_t)grel * K + k) * C) * PS2 + a * 8;
+#pragma unroll
+            for (int ch = 0; ch < C; ++ch)
+#pragma unroll
+              for (int b = 0; b < 8; ++b) ge[ch * PS2 + b] = out[ch][b];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // ---- flush the tile accumulator ----
+    const int nplanes = ADJ ? C : C + 1;
+    for (int e = tid; e < nplanes * AH * AW; e += 256) {
+      const int pl = e / (AH * AW), rem = e - pl * (AH * AW);
+      const int y = rem / AW, x = rem - y * AW;
+      const float v = acc[(pl * RA + y) * CA + x];
+      if (v != 0.f) {
+        const int gp = (AY0 + y) * d.W + AX0 + x;
+        if (pl < C) atomicAdd(d.num + pl * HW + gp, v);
+        else if (d.cnt) atomicAdd(d.cnt + gp, v);
+      }
+    }
+  });
+}
+
+size_t filter_lds_bytes(int C, int K, int stride, int window, int ty, int tx) {
+  (void)K;
+  const int r = (window - 1) / 2;
+  const size_t RA = (size_t)(ty - 1) * stride + 2 * r + PS;
+  const size_t CA = (size_t)(tx - 1) * stride + 2 * r + PS;
+  return ((C + 1) * RA * CA + 4 * TSCRATCH) * sizeof(float);
+}
+
+template <int C, int ADJ>
+static hipError_t launch_filter_c(const Launch& L, int g, size_t lds, hipStream_t s) {
+  switch (L.K) {
+    case 2: case 4: case 8:
+      hipLaunchKernelGGL((k_filter<C, 1, ADJ>), dim3(g), dim3(256), lds, s, L); break;
+    case 16:
+      hipLaunchKernelGGL((k_filter<C, 2, ADJ>), dim3(g), dim3(256), lds, s, L); break;
+    case 32:
+      hipLaunchKernelGGL((k_filter<C, 4, ADJ>), dim3(g), dim3(256), lds, s, L); break;
+    case 64:
+      if (C == 1) { hipLaunchKernelGGL((k_filter<C, 8, ADJ>), dim3(g), dim3(256), lds, s, L); break; }
+      return hipErrorInvalidValue;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_filter(const Launch& L, int ty, int tx, int adjoint, int grid, hipStream_t s) {
+  if (L.total <= 0) return hipSuccess;
+  const int g = xcd_grid(grid > 0 && grid < L.total ? grid : L.total);
+  const size_t lds = filter_lds_bytes(L.C, L.K, L.stride, L.window, ty, tx);
+  if (L.C == 1) return adjoint ? launch_filter_c<1, 1>(L, g, lds, s) : launch_filter_c<1, 0>(L, g, lds, s);
+  return adjoint ? launch_filter_c<3, 1>(L, g, lds, s) : launch_filter_c<3, 0>(L, g, lds, s);
+}
+
+// Stand-alone aggregation of precomputed group estimates (Eq. 2 numerator
+// and denominator): one wavefront per group, lane = slot-row.
+__global__ __launch_bounds__(256) void k_scatter_est(Launch L, const float* est, int C) {
+  const ImgDesc& d = L.one;
+  const int K = L.K;
+  const int HW = d.H * d.W;
+  const int gw = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (gw >= d.ref_count) return;
+  const int g = d.ref_begin + gw;
+  for (int e = lane; e < K * PS; e += 64) {
+    const int k = e >> 3, a = e & 7;
+    const int pos = d.idx[(size_t)g * K + k];
+    const int py = pos / d.W, px = pos - py * d.W;
+    for (int ch = 0; ch < C; ++ch)
+      for (int b = 0; b < 8; ++b)
+        atomicAdd(d.num + ch * HW + (py + a) * d.W + px + b,
+                  est[(((size_t)gw * K + k) * C + ch) * PS2 + a * 8 + b]);
+    for (int b = 0; b < 8; ++b) atomicAdd(d.cnt + (py + a) * d.W + px + b, 1.0f);
+  }
+}
+
+hipError_t launch_scatter_est(const Launch& L, hipStream_t s) {
+  const int n = L.one.ref_count;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_est, dim3((n + 3) / 4), dim3(256), 0, s, L, L.one.group_est, L.C);
+  return hipGetLastError();
+}
+
+}  // namespace hts

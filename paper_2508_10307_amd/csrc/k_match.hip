@@ -1,0 +1,494 @@
+// Block matching (Sec. III.A, Eq. 10; Alg. 1 Step 1).
+//
+// One work group per 4x4 tile of references.  For each guide plane the tile
+// uses, the pixel region covering the union of the 16 search windows is
+// staged in LDS (integer guide, centred by the tile mean, which leaves every
+// distance unchanged), then:
+//
+//  1. distance tiles of 16 references x 16 candidates, either as
+//     |a|^2 + |b|^2 - 2 a.b with a.b on BF16 MFMA (FP32 accumulation; the
+//     operands split into bf16 hi + lo parts when TERMS == 3) or as a plain
+//     FP32 sum of squared differences on the vector ALUs;
+//  2. every approximate distance d~ comes with a rigorous error bound E
+//     (|d~ - d| <= E), so [d~ - E, d~ + E] brackets the exact distance;
+//  3. pass 1 keeps, per lane and reference, the two smallest upper bounds;
+//     T = the (K-1)-th smallest of those is an upper bound of the exact
+//     (K-1)-th smallest distance;
+//  4. pass 2 recomputes the tiles and shortlists every candidate with
+//     d~ - E <= T: a superset of the exact top K-1, ties included;
+//  5. the shortlist is re-ranked with exact integer distances and sorted by
+//     (distance, index) on one wavefront; slot 0 is the reference itself.
+//
+// A reference whose shortlist exceeds SHORT_CAP goes to a list handled by
+// k_match_fallback (exact scan of the whole window).
+#include "hts_device.h"
+
+namespace hts {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float floatx4;
+typedef __attribute__((ext_vector_type(4))) unsigned uintx4;
+
+// Error-bound coefficients: E = C1 sqrt(|a|^2 |b|^2) + C2 (|a|^2 + |b|^2) + 2
+// for the norm+dot form.  With u = 2^-8 (bf16, round to nearest) the split
+// a = hi + lo + r has |r| <= 1.01 u^2 |a|; dropping lo*lo and the residuals
+// costs <= 3.1 u^2 sum|a_i b_i|; plain bf16 costs <= (2u + u^2) sum|a_i b_i|.
+// FP32 accumulation of <= 192 exact products (any order, rounding to
+// nearest or toward zero) adds <= 200 * 2^-23 sum|products|.  Cauchy-Schwarz
+// bounds sum|a_i b_i| by |a| |b|.  The factor 2 of 2 a.b and a 1.25 margin
+// give C1; C2 covers rounding the exact int64 norms to float and the final
+// additions.  For the FP32 SSD form, |d~ - d| <= 64 * 2^-24 d~ / (1 - 2^-18),
+// bounded by 2^-17 d~ + 2.
+template <int TERMS> struct DotBound;
+template <> struct DotBound<3> { static constexpr float C1 = 1.8e-4f; };
+template <> struct DotBound<1> { static constexpr float C1 = 1.97e-2f; };
+constexpr float BOUND_C2 = 9.5367431640625e-07f;  // 2^-20
+constexpr float SSD_REL = 7.62939453125e-06f;     // 2^-17
+constexpr float BOUND_ABS = 2.0f;
+
+__device__ inline unsigned bf16_bits(__bf16 h) { return __builtin_bit_cast(unsigned short, h); }
+
+// (hi | lo << 16) with hi = bf16(v), lo = bf16(v - hi); v is an integer
+// below 2^23 in magnitude, so v - hi is exact in FP32.
+__device__ inline unsigned split_pack(float v) {
+  __bf16 h = (__bf16)v;
+  __bf16 l = (__bf16)(v - (float)h);
+  return bf16_bits(h) | (bf16_bits(l) << 16);
+}
+
+template <int MODE, int TERMS>
+__global__ __launch_bounds__(256, 2) void k_match(Launch L) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const MatchGeom G = match_geom(L.stride, L.window);
+  int* gi = (int*)(smem + G.off_gi);
+  unsigned* gb = (unsigned*)(smem + G.off_gb);
+  float* nbf = (float*)(smem + G.off_nb);
+  float* sbf = (float*)(smem + G.off_sb);
+  float* tl = (float*)(smem + G.off_tl);
+  unsigned* sl = (unsigned*)(smem + G.off_sl);
+  int* rinfo = (int*)(smem + G.off_misc);          // [16][8]
+  float* rnorm = (float*)(rinfo + 128);            // [16][2] |a|^2, |a|
+  float* Tp = rnorm + 32;                          // [16]
+  int* scount = (int*)(Tp + 16);                   // [16]
+  long long* red = (long long*)(scount + 16);      // [8]
+  int* shared_m = (int*)(red + 8);                 // [2]
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int kq = lane >> 4, n = lane & 15;
+  const int r = (L.window - 1) / 2;
+  const int s = L.stride;
+  const int K = L.K;
+
+  for_each_item<W_MATCH>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
+    const int ntx = (d.nrx + MATCH_TX - 1) / MATCH_TX;
+    const int iy0 = (item / ntx) * MATCH_TY, ix0 = (item % ntx) * MATCH_TX;
+    const int iy1 = min(d.nry, iy0 + MATCH_TY) - 1, ix1 = min(d.nrx, ix0 + MATCH_TX) - 1;
+    const int Y0 = max(0, ref_coord(iy0, s, d.Hp) - r);
+    const int Y1 = min(d.Hp - 1, ref_coord(iy1, s, d.Hp) + r);
+    const int X0 = max(0, ref_coord(ix0, s, d.Wp) - r);
+    const int X1 = min(d.Wp - 1, ref_coord(ix1, s, d.Wp) + r);
+    const int RYc = Y1 - Y0 + 1, RXc = X1 - X0 + 1;
+    const int NXB = (RXc + 15) >> 4, RXP = NXB * 16;
+    const int rows = RYc + PS - 1, cols = RXP + PS - 1;
+    const int pitch = G.pitch;
+
+    __syncthreads();
+    if (tid < 16) {
+      const int iy = iy0 + (tid >> 2), ix = ix0 + (tid & 3);
+      const bool valid = iy < d.nry && ix < d.nrx;
+      const int ref = iy * d.nrx + ix;
+      const int ry = valid ? ref_coord(iy, s, d.Hp) : Y0;
+      const int rx = valid ? ref_coord(ix, s, d.Wp) : X0;
+      const int plane = (L.C == 1 || !valid) ? 0 : (d.green[ref] ? 0 : 1);
+      int* ri = rinfo + tid * 8;
+      ri[0] = valid ? (1 << plane) : 0;
+      ri[1] = ry - Y0;
+      ri[2] = rx - X0;
+      ri[3] = max(0, ry - r) - Y0;
+      ri[4] = min(d.Hp - 1, ry + r) - Y0;
+      ri[5] = max(0, rx - r) - X0;
+      ri[6] = min(d.Wp - 1, rx + r) - X0;
+      ri[7] = ref;
+    }
+    __syncthreads();
+    int pmask = 0;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) pmask |= rinfo[t * 8];
+
+    for (int p = 0; p < 2; ++p) {
+      if (!(pmask & (1 << p))) continue;
+      __syncthreads();  // the previous plane's re-rank still reads the LDS region
+      const int* gsrc = d.gplanes + (size_t)p * d.H * d.W;
+
+      // ---- stage the region; centring offset m = floor(mean) ----
+      long long sum = 0, cntv = 0;
+      for (int e = tid; e < rows * cols; e += 256) {
+        const int y = e / cols, x = e - y * cols;
+        const int gx = X0 + x;
+        int v = 0;
+        if (gx < d.W) { v = gsrc[(Y0 + y) * d.W + gx]; sum += v; cntv += 1; }
+        gi[y * pitch + x] = v;
+      }
+      for (int o = 32; o > 0; o >>= 1) { sum += shfl_xor_u64(sum, o); cntv += shfl_xor_u64(cntv, o); }
+      __syncthreads();
+      if (lane == 0) { red[wave] = sum; red[4 + wave] = cntv; }
+      __syncthreads();
+      if (tid == 0) {
+        long long S = red[0] + red[1] + red[2] + red[3];
+        long long N = red[4] + red[5] + red[6] + red[7];
+        long long m = S / N;
+        if (m * N > S) --m;
+        shared_m[0] = (int)m;
+      }
+      __syncthreads();
+      const int m = shared_m[0];
+      for (int e = tid; e < rows * cols; e += 256) {
+        const int y = e / cols, x = e - y * cols;
+        const int gx = X0 + x;
+        const int v = gx < d.W ? gi[y * pitch + x] - m : 0;
+        gi[y * pitch + x] = v;
+        gb[y * pitch + x] = MODE == 0 ? split_pack((float)v) : __float_as_uint((float)v);
+      }
+      __syncthreads();
+
+      // ---- exact candidate norms |b|^2 (norm+dot form only) ----
+      if (MODE == 0) {
+        const int nseg = (RYc + 7) >> 3;
+        for (int task = tid; task < RXP * nseg; task += 256) {
+          const int cx = task % RXP, c0 = (task / RXP) * 8;
+          long long rs[15];
+#pragma unroll
+          for (int j = 0; j < 15; ++j) {
+            const int y = c0 + j;
+            long long a = 0;
+            if (y < rows) {
+#pragma unroll
+              for (int b = 0; b < PS; ++b) {
+                long long v = gi[y * pitch + cx + b];
+                a += v * v;
+              }
+            }
+            rs[j] = a;
+          }
+          long long nn = 0;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) nn += rs[j];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int cy = c0 + j;
+            if (cy < RYc) {
+              const float f = (float)nn;
+              nbf[cy * RXP + cx] = f;
+              sbf[cy * RXP + cx] = sqrtf(f);
+            }
+            if (j < 7) nn += rs[j + 8] - rs[j];
+          }
+        }
+      }
+      if (tid < 16) {
+        const int* ri = rinfo + tid * 8;
+        float na = 0.f;
+        if (ri[0] & (1 << p)) {
+          long long a = 0;
+          for (int py = 0; py < PS; ++py)
+            for (int px = 0; px < PS; ++px) {
+              long long v = gi[(ri[1] + py) * pitch + ri[2] + px];
+              a += v * v;
+            }
+          na = (float)a;
+        }
+        rnorm[2 * tid] = na;
+        rnorm[2 * tid + 1] = sqrtf(na);
+      }
+      __syncthreads();
+
+      // ---- per-lane reference state: references 4*kq + i, candidate column n ----
+      bool inpl[4];
+      int rpx[4], wx0[4], wx1[4];
+      float na[4], sa[4];
+      const int rpy = rinfo[(4 * kq) * 8 + 1];
+      const int wy0 = rinfo[(4 * kq) * 8 + 3], wy1 = rinfo[(4 * kq) * 8 + 4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int* ri = rinfo + (4 * kq + i) * 8;
+        inpl[i] = (ri[0] >> p) & 1;
+        rpx[i] = ri[2];
+        wx0[i] = ri[5];
+        wx1[i] = ri[6];
+        na[i] = rnorm[2 * (4 * kq + i)];
+        sa[i] = rnorm[2 * (4 * kq + i) + 1];
+      }
+      // A operand: reference n, patch rows 4h + kq (MFMA 16x16x32 layout).
+      bf16x8 Ahi[2], Alo[2];
+      if (MODE == 0) {
+        const int* ri = rinfo + n * 8;
+        const bool ok = (ri[0] >> p) & 1;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const unsigned* src = gb + (ri[1] + 4 * h + kq) * pitch + ri[2];
+          unsigned w[8];
+#pragma unroll
+          for (int b = 0; b < 8; ++b) w[b] = ok ? src[b] : 0u;
+          uintx4 hi, lo;
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            hi[b] = __builtin_amdgcn_perm(w[2 * b + 1], w[2 * b], 0x05040100u);
+            lo[b] = __builtin_amdgcn_perm(w[2 * b + 1], w[2 * b], 0x07060302u);
+          }
+          Ahi[h] = __builtin_bit_cast(bf16x8, hi);
+          Alo[h] = __builtin_bit_cast(bf16x8, lo);
+        }
+      }
+
+      auto tile_dist = [&](int cy, int cx, float (&dt)[4], float (&E)[4], bool (&ok)[4]) {
+        const bool cx_ok = cx < RXc;
+        const bool cy_ok = cy >= wy0 && cy <= wy1;
+        if (MODE == 0) {
+          floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const unsigned* src = gb + (cy + 4 * h + kq) * pitch + cx;
+            unsigned w[8];
+#pragma unroll
+            for (int b = 0; b < 8; ++b) w[b] = src[b];
+            uintx4 hi, lo;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+              hi[b] = __builtin_amdgcn_perm(w[2 * b + 1], w[2 * b], 0x05040100u);
+              lo[b] = __builtin_amdgcn_perm(w[2 * b + 1], w[2 * b], 0x07060302u);
+            }
+            const bf16x8 Bhi = __builtin_bit_cast(bf16x8, hi);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ahi[h], Bhi, acc, 0, 0, 0);
+            if (TERMS == 3) {
+              const bf16x8 Blo = __builtin_bit_cast(bf16x8, lo);
+              acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ahi[h], Blo, acc, 0, 0, 0);
+              acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Alo[h], Bhi, acc, 0, 0, 0);
+            }
+          }
+          const float nb = nbf[cy * RXP + cx], sb = sbf[cy * RXP + cx];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            dt[i] = (na[i] + nb) - 2.0f * acc[i];
+            E[i] = DotBound<TERMS>::C1 * sa[i] * sb + BOUND_C2 * (na[i] + nb) + BOUND_ABS;
+          }
+        } else {
+          float acc[4] = {0.f, 0.f, 0.f, 0.f};
+          for (int py = 0; py < PS; ++py) {
+#pragma unroll
+            for (int px = 0; px < PS; ++px) {
+              const float bv = __uint_as_float(gb[(cy + py) * pitch + cx + px]);
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const float av = __uint_as_float(gb[(rpy + py) * pitch + rpx[i] + px]);
+                const float df = av - bv;
+                acc[i] = fmaf(df, df, acc[i]);
+              }
+            }
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            dt[i] = acc[i];
+            E[i] = SSD_REL * acc[i] + BOUND_ABS;
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          ok[i] = cx_ok && cy_ok && inpl[i] && cx >= wx0[i] && cx <= wx1[i] &&
+                  !(cy == rpy && cx == rpx[i]);
+      };
+
+      const int nblocks = RYc * NXB;
+      const float INF = __builtin_huge_valf();
+
+      // ---- pass 1: two smallest upper bounds per (lane, reference) ----
+      float m0[4] = {INF, INF, INF, INF}, m1[4] = {INF, INF, INF, INF};
+      for (int bi = wave; bi < nblocks; bi += 4) {
+        const int cy = bi / NXB, cx = (bi - cy * NXB) * 16 + n;
+        float dt[4], E[4];
+        bool ok[4];
+        tile_dist(cy, cx, dt, E, ok);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float hv = ok[i] ? fmaxf(dt[i] + E[i], 0.f) : INF;
+          m1[i] = fminf(m1[i], fmaxf(m0[i], hv));
+          m0[i] = fminf(m0[i], hv);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float* dst = tl + ((4 * kq + i) * 64 + wave * 16 + n) * 2;
+        dst[0] = m0[i];
+        dst[1] = m1[i];
+      }
+      __syncthreads();
+
+      // ---- threshold T per reference: (K-1)-th smallest of its 128 list values ----
+      for (int t = wave; t < 16; t += 4) {
+        if (!((rinfo[t * 8] >> p) & 1)) continue;
+        unsigned long long v[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) v[e] = __float_as_uint(tl[t * 128 + e * 64 + lane]);
+        wave_sort_u64<2>(v);
+        const int g = K - 2;
+        const unsigned long long sel = __shfl(g >= 64 ? v[1] : v[0], g & 63, 64);
+        if (lane == 0) {
+          Tp[t] = __uint_as_float((unsigned)sel);
+          scount[t] = 0;
+        }
+      }
+      __syncthreads();
+
+      // ---- pass 2: shortlist every candidate with d~ - E <= T ----
+      float Ti[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) Ti[i] = Tp[4 * kq + i];
+      for (int bi = wave; bi < nblocks; bi += 4) {
+        const int cy = bi / NXB, cx = (bi - cy * NXB) * 16 + n;
+        float dt[4], E[4];
+        bool ok[4];
+        tile_dist(cy, cx, dt, E, ok);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (ok[i] && dt[i] - E[i] <= Ti[i]) {
+            const int t = 4 * kq + i;
+            const int pos = atomicAdd(&scount[t], 1);
+            if (pos < SHORT_CAP) sl[t * SHORT_CAP + pos] = (unsigned)(cy * RXP + cx);
+          }
+        }
+      }
+      __syncthreads();
+
+      // ---- exact re-rank on one wavefront per reference ----
+      for (int t = wave; t < 16; t += 4) {
+        const int* ri = rinfo + t * 8;
+        if (!((ri[0] >> p) & 1)) continue;
+        const int ref = ri[7];
+        const int nsl = scount[t];
+        if (nsl > SHORT_CAP || nsl < K - 1) {
+          if (lane == 0) d.fb_list[atomicAdd(d.fb_count, 1)] = ref;
+          continue;
+        }
+        const int py0 = ri[1], px0 = ri[2], ty0 = ri[3], tx0 = ri[5];
+        unsigned long long key[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int j = e * 64 + lane;
+          key[e] = ~0ull;
+          if (j < nsl) {
+            const unsigned pos = sl[t * SHORT_CAP + j];
+            const int cy = pos / RXP, cx = pos - cy * RXP;
+            long long dd = 0;
+            for (int py = 0; py < PS; ++py)
+#pragma unroll
+              for (int px = 0; px < PS; ++px) {
+                const int df = gi[(py0 + py) * pitch + px0 + px] - gi[(cy + py) * pitch + cx + px];
+                dd += (long long)df * df;
+              }
+            key[e] = ((unsigned long long)dd << 12) | (unsigned)((cy - ty0) * 64 + (cx - tx0));
+          }
+        }
+        wave_sort_u64<2>(key);
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int g = e * 64 + lane;
+          if (g < K - 1) {
+            const unsigned loc = (unsigned)(key[e] & 0xFFFu);
+            const int cy = Y0 + ty0 + (int)(loc >> 6), cx = X0 + tx0 + (int)(loc & 63u);
+            d.idx[(size_t)ref * K + 1 + g] = cy * d.W + cx;
+            if (d.dist) d.dist[(size_t)ref * K + 1 + g] = (long long)(key[e] >> 12);
+          }
+        }
+        if (lane == 0) {
+          d.idx[(size_t)ref * K] = (Y0 + py0) * d.W + X0 + px0;
+          if (d.dist) d.dist[(size_t)ref * K] = 0;
+        }
+      }
+    }
+  });
+}
+
+// Exact scan of the whole window for references whose certified shortlist
+// overflowed: integer distances for every candidate, bitonic sort of
+// (distance, window index) keys in LDS, first K-1 after the reference.
+__global__ __launch_bounds__(256) void k_match_fallback(Launch L) {
+  __shared__ unsigned long long keys[4096];
+  const int tid = threadIdx.x;
+  const int r = (L.window - 1) / 2;
+  const int K = L.K;
+  const int nimg = L.table ? L.n_img : 1;
+  for (int im = 0; im < nimg; ++im) {
+    const ImgDesc d = L.table ? L.table[im] : L.one;
+    const int count = *d.fb_count;
+    for (int j = blockIdx.x; j < count; j += gridDim.x) {
+      const int ref = d.fb_list[j];
+      const int ry = ref_coord(ref / d.nrx, L.stride, d.Hp);
+      const int rx = ref_coord(ref % d.nrx, L.stride, d.Wp);
+      const int y0 = max(0, ry - r), y1 = min(d.Hp - 1, ry + r);
+      const int x0 = max(0, rx - r), x1 = min(d.Wp - 1, rx + r);
+      const int wx = x1 - x0 + 1, nc = (y1 - y0 + 1) * wx;
+      const int plane = (L.C == 1 || d.green[ref]) ? 0 : 1;
+      const int* g = d.gplanes + (size_t)plane * d.H * d.W;
+      for (int c = tid; c < 4096; c += 256) {
+        unsigned long long key = ~0ull;
+        if (c < nc) {
+          const int cy = y0 + c / wx, cx = x0 + c % wx;
+          if (cy != ry || cx != rx) {
+            long long dd = 0;
+            for (int a = 0; a < PS; ++a)
+              for (int b = 0; b < PS; ++b) {
+                const int df = g[(ry + a) * d.W + rx + b] - g[(cy + a) * d.W + cx + b];
+                dd += (long long)df * df;
+              }
+            key = ((unsigned long long)dd << 12) | (unsigned)((cy - y0) * 64 + (cx - x0));
+          }
+        }
+        keys[c] = key;
+      }
+      __syncthreads();
+      for (int k = 2; k <= 4096; k <<= 1)
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+          for (int i = tid; i < 4096; i += 256) {
+            const int q = i ^ jj;
+            if (q > i) {
+              const unsigned long long a = keys[i], b = keys[q];
+              const bool asc = (i & k) == 0;
+              if (asc ? (a > b) : (a < b)) { keys[i] = b; keys[q] = a; }
+            }
+          }
+          __syncthreads();
+        }
+      for (int i = tid; i < K - 1; i += 256) {
+        const unsigned loc = (unsigned)(keys[i] & 0xFFFu);
+        d.idx[(size_t)ref * K + 1 + i] = (y0 + (int)(loc >> 6)) * d.W + x0 + (int)(loc & 63u);
+        if (d.dist) d.dist[(size_t)ref * K + 1 + i] = (long long)(keys[i] >> 12);
+      }
+      if (tid == 0) {
+        d.idx[(size_t)ref * K] = ry * d.W + rx;
+        if (d.dist) d.dist[(size_t)ref * K] = 0;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+size_t match_lds_bytes(int stride, int window) { return (size_t)match_geom(stride, window).bytes; }
+
+hipError_t launch_match(const Launch& L, int mode, int terms, int grid, hipStream_t s) {
+  if (L.total <= 0) return hipSuccess;
+  const int g = xcd_grid(grid > 0 && grid < L.total ? grid : L.total);
+  const size_t lds = match_lds_bytes(L.stride, L.window);
+  if (mode == HTS_MATCH_FP32)
+    hipLaunchKernelGGL((k_match<1, 1>), dim3(g), dim3(256), lds, s, L);
+  else if (terms == 1)
+    hipLaunchKernelGGL((k_match<0, 1>), dim3(g), dim3(256), lds, s, L);
+  else
+    hipLaunchKernelGGL((k_match<0, 3>), dim3(g), dim3(256), lds, s, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_match_fallback(const Launch& L, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_match_fallback, dim3(grid > 0 ? grid : 256), dim3(256), 0, s, L);
+  return hipGetLastError();
+}
+
+}  // namespace hts

@@ -106,9 +106,17 @@ def main():
     outs = [torch.empty_like(x) for x in xs]
     C = xs[0].shape[0]
 
+    tune = args.tune
+    if tune == 0:
+        # launch schedule picked by the library's autotuner on a representative shape
+        t0 = time.time()
+        tune = api.hts_autotune(api.Params(stride=q.stride, window=q.window, K=q.K,
+                                           tau_mult=q.tau_mult), C, 512, 512)
+        print(f"# autotuned schedule {tune} in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+
     def params(mode):
         return api.Params(stride=q.stride, window=q.window, K=q.K, tau_mult=q.tau_mult,
-                          match_mode=mode, tune=args.tune)
+                          match_mode=mode, tune=tune)
 
     def make_runner(mode):
         p = params(mode)
@@ -225,7 +233,7 @@ def main():
         "config": {"workload": wl.name, "images": len(xs), "mpix_per_step": round(mpix, 3),
                    "ps": 8, "stride": q.stride, "window": q.window, "K": q.K,
                    "lambda": q.tau_mult, "api": "hts_denoise_batch" if args.batch_api else "hts_denoise",
-                   "parallelism": "single GPU"},
+                   "tune": tune, "parallelism": "single GPU"},
         "psnr_db": round(psnr_bf16, 4),
         "hbm_gbps": round(hbm_bytes / (ms / 1e3) / 1e9, 2),
         "fp32_path": fp32,

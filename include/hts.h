@@ -38,6 +38,9 @@
  *    caller's next synchronisation.  No C++ exception crosses this ABI.
  *  - Non-finite inputs: NaN quantises to 0 and +-inf to the clamp for
  *    matching; the filter propagates them into the output.
+ *  - Reproducibility: match indices, distances and threshold masks are
+ *    deterministic; estimates are summed with float atomics, so denoised
+ *    values can differ between runs in the last bits (order of additions).
  */
 #ifndef HTS_H
 #define HTS_H
@@ -62,10 +65,6 @@ typedef enum {
   HTS_MATCH_FP32 = 1        /* plain FP32 SSD tiles on the vector ALUs (no MFMA) */
 } hts_match_mode;
 
-enum {
-  HTS_FLAG_DETERMINISTIC = 1  /* aggregation via ordered tile partials, no float atomics */
-};
-
 typedef struct {
   int32_t ps;          /* patch size; must be 8                                  */
   int32_t stride;      /* reference stride s, 1 <= s <= ps                        */
@@ -75,7 +74,7 @@ typedef struct {
   int32_t gcp_num;     /* gamma = gcp_num / gcp_den (Eq. 10; 6/5 = 1.2), 1..64    */
   int32_t gcp_den;
   int32_t match_mode;  /* hts_match_mode                                          */
-  int32_t flags;       /* HTS_FLAG_*                                              */
+  int32_t flags;       /* reserved, must be 0                                     */
   int32_t tune;        /* 0 = autotuned/default launch schedule, else a schedule id */
 } hts_params;
 

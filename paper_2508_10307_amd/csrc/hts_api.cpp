@@ -47,6 +47,7 @@ hts_status check_params(const hts_params* p, int C) {
   if (!(p->tau_mult >= 0.f) || !std::isfinite(p->tau_mult)) return HTS_ERR_INVALID;
   if (p->gcp_num < 1 || p->gcp_num > 64 || p->gcp_den < 1 || p->gcp_den > 64) return HTS_ERR_INVALID;
   if (p->match_mode != HTS_MATCH_BF16 && p->match_mode != HTS_MATCH_FP32) return HTS_ERR_INVALID;
+  if (p->flags != 0) return HTS_ERR_INVALID;
   if ((size_t)match_lds_bytes(p->stride, p->window) > kLdsMax) return HTS_ERR_UNSUPPORTED;
   if (filter_lds_bytes(C, p->K, p->stride, p->window, 1, 1) > kLdsMax) return HTS_ERR_UNSUPPORTED;
   return HTS_OK;
@@ -363,6 +364,7 @@ std::string graph_key(const hts_params* p, const hts_image* imgs, int n, const v
 extern "C" {
 
 void hts_default_params(hts_params* p) {
+  // flags is reserved (0)
   if (!p) return;
   p->ps = 8; p->stride = 3; p->window = 21; p->K = 16; p->tau_mult = 2.7f;
   p->gcp_num = 6; p->gcp_den = 5; p->match_mode = HTS_MATCH_BF16; p->flags = 0; p->tune = 0;
@@ -577,7 +579,17 @@ hts_status hts_denoise_batch(const hts_params* p, const hts_image* imgs, int32_t
   const int C = imgs[0].C;
   ImgDesc* table = (ImgDesc*)((char*)ws + plan.table_off);
   std::lock_guard<std::mutex> lk(g_graph_mu);
-  GraphEntry& e = g_graphs[graph_key(p, imgs, n, ws)];
+  const std::string key = graph_key(p, imgs, n, ws);
+  if (g_graphs.size() >= 64 && !g_graphs.count(key)) {
+    // bounded cache: drop every entry (after the device is idle) and start over
+    HIPCHK(hipDeviceSynchronize());
+    for (auto& kv : g_graphs) {
+      if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+      if (kv.second.copied) (void)hipEventDestroy(kv.second.copied);
+    }
+    g_graphs.clear();
+  }
+  GraphEntry& e = g_graphs[key];
   if (!e.copied) HIPCHK(hipEventCreateWithFlags(&e.copied, hipEventDisableTiming));
   if (e.used) HIPCHK(hipEventSynchronize(e.copied));   // previous upload has read the staging
   e.host = plan.descs;

@@ -74,7 +74,7 @@ hts_status make_geo(const hts_params* p, int C, int H, int W, Geo& g) {
 
 // Workspace carve-up for one image.
 struct Carve {
-  size_t gplanes, green, idx, fb_list, fb_count, cov, basis64, basis, fbasis, num, cnt, total;
+  size_t gplanes, green, idx, fb_list, fb_count, cov, basis64, basis, fbasis, num, cnt, hist, total;
 };
 
 Carve carve(const Geo& g) {
@@ -91,6 +91,7 @@ Carve carve(const Geo& g) {
   c.fbasis = o; o += al((size_t)FB_SIZE * 4);
   c.num = o; o += al((size_t)g.C * g.H * g.W * 4);
   c.cnt = o; o += al((size_t)g.H * g.W * 4);
+  c.hist = o; o += al((size_t)g.H * g.W * 4);
   c.total = o;
   return c;
 }
@@ -101,6 +102,7 @@ void fill_counts(const Geo& g, const hts_params* p, int fty, int ftx, ImgDesc& d
   d.wcnt[W_MATCH] = ((g.nry + MATCH_TY - 1) / MATCH_TY) * ((g.nrx + MATCH_TX - 1) / MATCH_TX);
   d.wcnt[W_COV] = g.n_cov;
   d.wcnt[W_FILT] = ((g.nry + fty - 1) / fty) * ((g.nrx + ftx - 1) / ftx);
+  d.wcnt[W_BOX] = ((g.H + BOX_TY - 1) / BOX_TY) * ((g.W + BOX_TX - 1) / BOX_TX);
   for (int k = 0; k < W_NKIND; ++k) d.woff[k] = 0;
   (void)p;
 }
@@ -121,6 +123,7 @@ ImgDesc make_desc(const Geo& g, const hts_params* p, char* ws, const Carve& c, c
   d.fbasis = (float*)(ws + c.fbasis);
   d.num = (float*)(ws + c.num);
   d.cnt = (float*)(ws + c.cnt);
+  d.hist = (int32_t*)(ws + c.hist);
   d.H = g.H; d.W = g.W; d.Hp = g.Hp; d.Wp = g.Wp;
   d.nry = g.nry; d.nrx = g.nrx; d.n_ref = g.n_ref;
   d.ref_begin = 0; d.ref_count = g.n_ref;
@@ -149,7 +152,8 @@ Launch make_launch(const hts_params* p, int C, const ImgDesc& d, int kind, int f
 // ---- launch schedule (tune word) ----
 // bits 0-3: filter tile shape index + 1 (0 = largest shape within the LDS budget)
 // bits 4-5: BF16 match terms (0 = default 3, 1 = one product, 2 = hi/lo split)
-struct Schedule { int fty, ftx, terms; };
+// bits 6-7: filter implementation (0 = FP32 MFMA where built, 1 = vector ALU)
+struct Schedule { int fty, ftx, terms, valu; };
 
 int tuned_word(const hts_params* p, int C);
 
@@ -167,6 +171,7 @@ Schedule schedule_for(const hts_params* p, int C) {
   s.ftx = kShapes[si].tx;
   const int t = (tune >> 4) & 3;
   s.terms = t == 1 ? 1 : 3;
+  s.valu = ((tune >> 6) & 3) == 1 || !filter_mfma_supported(C, p->K);
   return s;
 }
 
@@ -187,10 +192,23 @@ hts_status run_basis(const hts_params* p, int C, const Schedule& sc, ImgDesc d, 
   return HTS_OK;
 }
 
+// Coverage counts of references [ref_begin, ref_begin+ref_count) added into
+// d.cnt: histogram of the groups' patch corners, then its 8x8 box sum.
+hts_status run_count(const hts_params* p, int C, const Schedule& sc, const ImgDesc& d,
+                     bool zero_hist, hipStream_t s) {
+  if (zero_hist) HIPCHK(launch_zero_hist(make_launch(p, C, d, W_PIX, sc.fty, sc.ftx), 0, s));
+  HIPCHK(launch_count_hist(make_launch(p, C, d, W_REF, sc.fty, sc.ftx), 0, s));
+  HIPCHK(launch_count_box(make_launch(p, C, d, W_BOX, sc.fty, sc.ftx), 0, s));
+  return HTS_OK;
+}
+
 hts_status run_filter(const hts_params* p, int C, const Schedule& sc, ImgDesc d, int adjoint,
                       hipStream_t s) {
   HIPCHK(launch_fbasis(make_launch(p, C, d, -1, sc.fty, sc.ftx), s));
-  HIPCHK(launch_filter(make_launch(p, C, d, W_FILT, sc.fty, sc.ftx), sc.fty, sc.ftx, adjoint, 0, s));
+  const Launch L = make_launch(p, C, d, W_FILT, sc.fty, sc.ftx);
+  if (sc.valu) HIPCHK(launch_filter(L, sc.fty, sc.ftx, adjoint, 0, s));
+  else HIPCHK(launch_filter_mfma(L, sc.fty, sc.ftx, adjoint, 0, s));
+  if (!adjoint && d.cnt) return run_count(p, C, sc, d, true, s);
   return HTS_OK;
 }
 
@@ -325,7 +343,10 @@ hts_status enqueue_batch(const hts_params* p, int C, const BatchPlan& plan, cons
   HIPCHK(launch_eig(LK(-1), s));
   HIPCHK(launch_fbasis(LK(-1), s));
   HIPCHK(launch_zero_accum(LK(W_PIX), cus * 8, s));
-  HIPCHK(launch_filter(LK(W_FILT), sc.fty, sc.ftx, 0, cus * 2, s));
+  HIPCHK(launch_count_hist(LK(W_REF), cus * 8, s));
+  HIPCHK(launch_count_box(LK(W_BOX), cus * 8, s));
+  if (sc.valu) HIPCHK(launch_filter(LK(W_FILT), sc.fty, sc.ftx, 0, cus * 2, s));
+  else HIPCHK(launch_filter_mfma(LK(W_FILT), sc.fty, sc.ftx, 0, cus * 2, s));
   HIPCHK(launch_finalize(LK(W_PIX), cus * 8, s));
   return HTS_OK;
 }

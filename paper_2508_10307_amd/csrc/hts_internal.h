@@ -21,7 +21,8 @@ constexpr int PIX_CHUNK = 2048;        // pixels per work item of the element-wi
 
 // Work kinds: each image contributes a number of work items of each kind;
 // batched launches walk a global list of (image, item) pairs.
-enum WorkKind { W_PIX = 0, W_REF = 1, W_MATCH = 2, W_COV = 3, W_FILT = 4, W_NKIND = 5 };
+enum WorkKind { W_PIX = 0, W_REF = 1, W_MATCH = 2, W_COV = 3, W_FILT = 4, W_BOX = 5, W_NKIND = 6 };
+constexpr int BOX_TY = 16, BOX_TX = 64;  // output tile of the coverage box sum
 
 // Filter tile shapes (references per tile); index = hts_params.tune & 7
 // (0 = pick by LDS budget).
@@ -44,6 +45,7 @@ struct ImgDesc {
   float* fbasis;           // Fourier slices for the filter, see FB_* offsets
   float* num;              // [C][H][W]
   float* cnt;              // [H][W]
+  int32_t* hist;           // [H][W] slot-position histogram (coverage counts)
   uint32_t* masks;         // keep-masks (nullable)
   const uint32_t* masks_in;// frozen masks for the adjoint (nullable)
   float* group_est;        // [ref_count][K][C][8][8] (nullable)
@@ -129,6 +131,14 @@ hipError_t launch_finalize(const Launch& L, int grid, hipStream_t s);
 hipError_t launch_scatter_est(const Launch& L, hipStream_t s);
 hipError_t launch_adjoint_prep(const Launch& L, int grid, hipStream_t s);
 hipError_t launch_synth(float* img, int C, int H, int W, hipStream_t s);
+hipError_t launch_zero_hist(const Launch& L, int grid, hipStream_t s);
+hipError_t launch_count_hist(const Launch& L, int grid, hipStream_t s);
+hipError_t launch_count_box(const Launch& L, int grid, hipStream_t s);
+
+// FP32-MFMA filter for RGB groups (K in {4, 8, 16, 32}).
+bool filter_mfma_supported(int C, int K);
+size_t filter_mfma_lds_bytes(int stride, int window, int ty, int tx);
+hipError_t launch_filter_mfma(const Launch& L, int ty, int tx, int adjoint, int grid, hipStream_t s);
 
 // Filter LDS bytes for a tile shape.
 size_t filter_lds_bytes(int C, int K, int stride, int window, int ty, int tx);

@@ -66,6 +66,7 @@ __global__ __launch_bounds__(256) void k_zero_accum(Launch L) {
     for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
       for (int c = 0; c < L.C; ++c) d.num[c * HW + p] = 0.0f;
       if (d.cnt) d.cnt[p] = 0.0f;
+      if (d.hist) d.hist[p] = 0;
     }
   });
 }
@@ -97,6 +98,67 @@ __global__ __launch_bounds__(256) void k_adjoint_prep(Launch L) {
   });
 }
 
+// Coverage counts (the Eq. 2 denominator) depend only on the match indices:
+// hist[p] = number of (group, slot) patches with top-left corner p, and
+// cnt = hist convolved with the 8x8 box (every such patch covers 8x8 pixels).
+__global__ __launch_bounds__(256) void k_zero_hist(Launch L) {
+  for_each_item<W_PIX>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
+    const int HW = d.H * d.W;
+    const int p0 = item * PIX_CHUNK;
+    const int p1 = min(HW, p0 + PIX_CHUNK);
+    for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) d.hist[p] = 0;
+  });
+}
+
+__global__ __launch_bounds__(256) void k_count_hist(Launch L) {
+  for_each_item<W_REF>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
+    const int g = item * 256 + threadIdx.x;
+    if (g < d.ref_begin || g >= d.ref_begin + d.ref_count) return;
+    const int* row = d.idx + (size_t)g * L.K;
+    const int n = d.H * d.W;
+    for (int k = 0; k < L.K; ++k) {
+      const int pos = row[k];
+      if (pos >= 0 && pos < n) atomicAdd(d.hist + pos, 1);
+    }
+  });
+}
+
+// cnt += 8x8 box sum of hist over valid top-left corners, one
+// BOX_TY x BOX_TX output tile per item (vertical then horizontal sums in LDS).
+__global__ __launch_bounds__(256) void k_count_box(Launch L) {
+  __shared__ int h[BOX_TY + PS - 1][BOX_TX + PS - 1];
+  __shared__ int v[BOX_TY][BOX_TX + PS - 1];
+  for_each_item<W_BOX>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
+    const int ntx = (d.W + BOX_TX - 1) / BOX_TX;
+    const int y0 = (item / ntx) * BOX_TY, x0 = (item % ntx) * BOX_TX;
+    __syncthreads();
+    for (int e = threadIdx.x; e < (BOX_TY + PS - 1) * (BOX_TX + PS - 1); e += blockDim.x) {
+      const int yy = e / (BOX_TX + PS - 1), xx = e % (BOX_TX + PS - 1);
+      const int gy = y0 + yy - (PS - 1), gx = x0 + xx - (PS - 1);
+      h[yy][xx] = (gy >= 0 && gy < d.Hp && gx >= 0 && gx < d.Wp) ? d.hist[gy * d.W + gx] : 0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < BOX_TY * (BOX_TX + PS - 1); e += blockDim.x) {
+      const int yy = e / (BOX_TX + PS - 1), xx = e % (BOX_TX + PS - 1);
+      int a = 0;
+#pragma unroll
+      for (int k = 0; k < PS; ++k) a += h[yy + k][xx];
+      v[yy][xx] = a;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < BOX_TY * BOX_TX; e += blockDim.x) {
+      const int yy = e / BOX_TX, xx = e % BOX_TX;
+      const int gy = y0 + yy, gx = x0 + xx;
+      if (gy < d.H && gx < d.W) {
+        int a = 0;
+#pragma unroll
+        for (int k = 0; k < PS; ++k) a += v[yy][xx + k];
+        d.cnt[gy * d.W + gx] += (float)a;
+      }
+    }
+  });
+}
+
 static int grid_for(const Launch& L, int grid) { return xcd_grid(grid > 0 && grid < L.total ? grid : L.total); }
 
 hipError_t launch_quant(const Launch& L, int grid, hipStream_t s) {
@@ -123,6 +185,21 @@ hipError_t launch_finalize(const Launch& L, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_finalize, dim3(grid_for(L, grid)), dim3(256), 0, s, L);
   return hipGetLastError();
 }
+hipError_t launch_zero_hist(const Launch& L, int grid, hipStream_t s) {
+  if (L.total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_hist, dim3(grid_for(L, grid)), dim3(256), 0, s, L);
+  return hipGetLastError();
+}
+hipError_t launch_count_hist(const Launch& L, int grid, hipStream_t s) {
+  if (L.total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_count_hist, dim3(grid_for(L, grid)), dim3(256), 0, s, L);
+  return hipGetLastError();
+}
+hipError_t launch_count_box(const Launch& L, int grid, hipStream_t s) {
+  if (L.total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_count_box, dim3(grid_for(L, grid)), dim3(256), 0, s, L);
+  return hipGetLastError();
+}
 hipError_t launch_adjoint_prep(const Launch& L, int grid, hipStream_t s) {
   if (L.total <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_adjoint_prep, dim3(grid_for(L, grid)), dim3(256), 0, s, L);
@@ -134,7 +211,8 @@ hipError_t launch_adjoint_prep(const Launch& L, int grid, hipStream_t s) {
 namespace hts {
 
 // Deterministic structured test image for the autotuner: smooth pattern plus
-// a hashed pseudo-noise of standard deviation ~25.
+// a hashed pseudo-noise whose standard deviation sweeps 5..50 across the
+// columns (low noise is the hard case for the distance-tile error bound).
 __global__ __launch_bounds__(256) void k_synth(float* img, int C, int H, int W) {
   const int n = C * H * W;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -142,7 +220,8 @@ __global__ __launch_bounds__(256) void k_synth(float* img, int C, int H, int W) 
     unsigned h = (unsigned)i * 2654435761u + 12345u;
     h ^= h >> 15; h *= 2246822519u; h ^= h >> 13; h *= 3266489917u; h ^= h >> 16;
     const float u = (h & 0xFFFFFF) * (1.0f / 16777216.0f) - 0.5f;
-    img[i] = 128.f + 60.f * __sinf(x * 0.13f + c) * __cosf(y * 0.09f) + 86.6f * u;
+    const float sd = 5.f + 45.f * (float)x / (float)W;
+    img[i] = 128.f + 60.f * __sinf(x * 0.13f + c) * __cosf(y * 0.09f) + 3.4641f * sd * u;
   }
 }
 

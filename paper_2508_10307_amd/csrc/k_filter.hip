@@ -110,9 +110,9 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
   const int s = L.stride;
   const int TY = L.fty, TX = L.ftx;
   const int RA = (TY - 1) * s + 2 * r + PS, CA = (TX - 1) * s + 2 * r + PS;
-  const int NP = C + 1;
+  const int NP = C;
   float* acc = fsm;                                   // [NP][RA][CA]
-  float* T = fsm + NP * RA * CA + wave * TSCRATCH;    // this wavefront's transpose scratch
+  float* T = fsm + (NP * RA * CA + 3) / 4 * 4 + wave * TSCRATCH;   // transpose scratch
 
   for_each_item<W_FILT>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
     const int ntx = (d.nrx + TX - 1) / TX;
@@ -347,11 +347,6 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
 #pragma unroll
             for (int b = 0; b < 8; ++b) atomicAdd(rowp + b, out[ch][b]);
           }
-          if (!ADJ) {
-            float* rowp = acc + (C * RA + ly) * CA + lx;
-#pragma unroll
-            for (int b = 0; b < 8; ++b) atomicAdd(rowp + b, 1.0f);
-          }
           if (d.group_est) {
             float* ge = d.group_est + (((size_t)grel * K + k) * C) * PS2 + a * 8;
 #pragma unroll
@@ -364,16 +359,11 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
     }
     __syncthreads();
     // ---- flush the tile accumulator ----
-    const int nplanes = ADJ ? C : C + 1;
-    for (int e = tid; e < nplanes * AH * AW; e += 256) {
+    for (int e = tid; e < C * AH * AW; e += 256) {
       const int pl = e / (AH * AW), rem = e - pl * (AH * AW);
       const int y = rem / AW, x = rem - y * AW;
       const float v = acc[(pl * RA + y) * CA + x];
-      if (v != 0.f) {
-        const int gp = (AY0 + y) * d.W + AX0 + x;
-        if (pl < C) atomicAdd(d.num + pl * HW + gp, v);
-        else if (d.cnt) atomicAdd(d.cnt + gp, v);
-      }
+      if (v != 0.f) atomicAdd(d.num + pl * HW + (AY0 + y) * d.W + AX0 + x, v);
     }
   });
 }
@@ -383,7 +373,7 @@ size_t filter_lds_bytes(int C, int K, int stride, int window, int ty, int tx) {
   const int r = (window - 1) / 2;
   const size_t RA = (size_t)(ty - 1) * stride + 2 * r + PS;
   const size_t CA = (size_t)(tx - 1) * stride + 2 * r + PS;
-  return ((C + 1) * RA * CA + 4 * TSCRATCH) * sizeof(float);
+  return ((C * RA * CA + 3) / 4 * 4 + 4 * TSCRATCH) * sizeof(float);
 }
 
 template <int C, int ADJ>

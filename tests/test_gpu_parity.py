@@ -293,3 +293,29 @@ def test_autograd_function_mse_gradient():
     log("autograd grad max err", np.abs(g - g_o).max(), "scale", np.abs(g_o).max())
     assert np.abs(g - g_o).max() <= 1e-4 * np.abs(g_o).max()
     assert lam.grad.item() == 0.0
+
+
+# ---------------------------------------------------------------- filter implementations
+@pytest.mark.parametrize("K", [4, 8, 16, 32])
+def test_mfma_filter_matches_valu_filter(K):
+    # The FP32-MFMA filter (default for RGB) and the vector-ALU filter compute
+    # the same Eq. 18-20 in different FP32 orders: identical match indices,
+    # masks equal except at coefficients within the rounding band of tau,
+    # pixels within the 1e-3 bar; the adjoint likewise.
+    y = synth.tiny(900 + K, 3, 72, 67, sigma=18.0, n_blobs=8)
+    pm = P(stride=3, window=15, K=K)
+    pv = P(stride=3, window=15, K=K, tune=1 << 6)
+    x = T(y)
+    om, sm = api.hts_denoise(x, 18.0, pm, save=True)
+    ov, sv = api.hts_denoise(x, 18.0, pv, save=True)
+    assert torch.equal(sm["idx"], sv["idx"])
+    err = (om - ov).abs().max().item()
+    mm = opipe.unpack_masks(sm["masks"].cpu().numpy().view(np.uint32), len(sm["idx"]), K, 3)
+    mv = opipe.unpack_masks(sv["masks"].cpu().numpy().view(np.uint32), len(sv["idx"]), K, 3)
+    log("mfma vs valu", K, "max pixel diff", err, "mask diffs", int((mm != mv).sum()), "of", mm.size)
+    assert (mm != mv).sum() <= max(2, 1e-5 * mm.size)
+    assert err <= PIX_TOL
+    g = T(np.random.default_rng(K).normal(size=y.shape))
+    gm, _ = api.hts_denoise_backward(g, sm, pm)
+    gv, _ = api.hts_denoise_backward(g, sm, pv)
+    assert (gm - gv).abs().max().item() <= 1e-4 * max(1.0, gv.abs().max().item())

@@ -36,11 +36,23 @@
  *    stream).  A returned status covers argument validation and launch
  *    errors; on any error nothing is launched.  Device faults surface at the
  *    caller's next synchronisation.  No C++ exception crosses this ABI.
+ *  - Aggregation (Eq. 2) sums the estimates in 64-bit fixed point with 32
+ *    fractional bits (each estimate is rounded down to a multiple of 2^-32;
+ *    estimates beyond +-2^31 saturate).  Integer sums do not depend on the
+ *    order of the additions.
+ *  - Reproducibility: match indices, distances, threshold masks and the
+ *    outputs of hts_denoise, hts_denoise_batch and hts_denoise_backward are
+ *    bit-for-bit the same from run to run, for any launch schedule of the
+ *    same filter implementation and between the batched and single-image
+ *    calls.  hts_filter and hts_aggregate add into caller-owned float32
+ *    buffers with float atomics, whose last bits depend on the order of the
+ *    additions.
  *  - Non-finite inputs: NaN quantises to 0 and +-inf to the clamp for
- *    matching; the filter propagates them into the output.
- *  - Reproducibility: match indices, distances and threshold masks are
- *    deterministic; estimates are summed with float atomics, so denoised
- *    values can differ between runs in the last bits (order of additions).
+ *    matching.  A group that gathers a non-finite pixel, or whose estimates
+ *    are not finite, makes every pixel of its K patches NaN in the output
+ *    (or in num for hts_filter).  hts_denoise learns the basis from the
+ *    image itself, so there one non-finite pixel makes the basis, and with
+ *    it the whole output, NaN.
  */
 #ifndef HTS_H
 #define HTS_H

@@ -74,7 +74,8 @@ hts_status make_geo(const hts_params* p, int C, int H, int W, Geo& g) {
 
 // Workspace carve-up for one image.
 struct Carve {
-  size_t gplanes, green, idx, fb_list, fb_count, cov, basis64, basis, fbasis, num, cnt, hist, total;
+  size_t gplanes, green, idx, fb_list, fb_count, cov, basis64, basis, fbasis, num, num64, cnt, hist,
+      poison, fxmax, total;
 };
 
 Carve carve(const Geo& g) {
@@ -92,6 +93,9 @@ Carve carve(const Geo& g) {
   c.num = o; o += al((size_t)g.C * g.H * g.W * 4);
   c.cnt = o; o += al((size_t)g.H * g.W * 4);
   c.hist = o; o += al((size_t)g.H * g.W * 4);
+  c.num64 = o; o += al((size_t)g.C * g.H * g.W * 8);
+  c.poison = o; o += al((size_t)g.H * g.W);
+  c.fxmax = o; o += al(4);
   c.total = o;
   return c;
 }
@@ -124,6 +128,9 @@ ImgDesc make_desc(const Geo& g, const hts_params* p, char* ws, const Carve& c, c
   d.num = (float*)(ws + c.num);
   d.cnt = (float*)(ws + c.cnt);
   d.hist = (int32_t*)(ws + c.hist);
+  d.num64 = (unsigned long long*)(ws + c.num64);
+  d.poison = (uint8_t*)(ws + c.poison);
+  d.fxmax = (uint32_t*)(ws + c.fxmax);
   d.H = g.H; d.W = g.W; d.Hp = g.Hp; d.Wp = g.Wp;
   d.nry = g.nry; d.nrx = g.nrx; d.n_ref = g.n_ref;
   d.ref_begin = 0; d.ref_count = g.n_ref;
@@ -157,30 +164,41 @@ struct Schedule { int fty, ftx, terms, valu; };
 
 int tuned_word(const hts_params* p, int C);
 
+// LDS bytes of the filter implementation for a tile shape, and the LDS a
+// work group may take: the MFMA filter at K = 32 runs one work group per CU
+// (register bound), every other variant two.
+size_t filter_impl_lds(const hts_params* p, int C, bool valu, int ty, int tx) {
+  return valu ? filter_lds_bytes(C, p->K, p->stride, p->window, ty, tx)
+              : filter_mfma_lds_bytes(p->stride, p->window, ty, tx);
+}
+size_t filter_impl_budget(const hts_params* p, bool valu) {
+  return !valu && p->K >= 32 ? kLdsMax : kFilterLdsBudget;
+}
+
 Schedule schedule_for(const hts_params* p, int C) {
   Schedule s;
   const int tune = p->tune ? p->tune : tuned_word(p, C);
+  s.valu = ((tune >> 6) & 3) == 1 || !filter_mfma_supported(C, p->K);
   int si = (tune & 15) - 1;
   if (si < 0 || si >= kNumShapes ||
-      filter_lds_bytes(C, p->K, p->stride, p->window, kShapes[si].ty, kShapes[si].tx) > kLdsMax) {
+      filter_impl_lds(p, C, s.valu, kShapes[si].ty, kShapes[si].tx) > kLdsMax) {
     si = kNumShapes - 1;
     for (int i = 0; i < kNumShapes; ++i)
-      if (filter_lds_bytes(C, p->K, p->stride, p->window, kShapes[i].ty, kShapes[i].tx) <= kFilterLdsBudget) { si = i; break; }
+      if (filter_impl_lds(p, C, s.valu, kShapes[i].ty, kShapes[i].tx) <= filter_impl_budget(p, s.valu)) { si = i; break; }
   }
   s.fty = kShapes[si].ty;
   s.ftx = kShapes[si].tx;
   const int t = (tune >> 4) & 3;
   s.terms = t == 1 ? 1 : 3;
-  s.valu = ((tune >> 6) & 3) == 1 || !filter_mfma_supported(C, p->K);
   return s;
 }
 
 #define HIPCHK(x) do { if ((x) != hipSuccess) return HTS_ERR_HIP; } while (0)
 
 hts_status run_match(const hts_params* p, int C, const Schedule& sc, ImgDesc d, hipStream_t s) {
+  HIPCHK(launch_reset_counters(make_launch(p, C, d, -1, sc.fty, sc.ftx), s));
   HIPCHK(launch_quant(make_launch(p, C, d, W_PIX, sc.fty, sc.ftx), 0, s));
   HIPCHK(launch_gcp(make_launch(p, C, d, W_REF, sc.fty, sc.ftx), 0, s));
-  HIPCHK(launch_reset_counters(make_launch(p, C, d, -1, sc.fty, sc.ftx), s));
   HIPCHK(launch_match(make_launch(p, C, d, W_MATCH, sc.fty, sc.ftx), p->match_mode, sc.terms, 0, s));
   HIPCHK(launch_match_fallback(make_launch(p, C, d, -1, sc.fty, sc.ftx), 256, s));
   return HTS_OK;
@@ -334,9 +352,9 @@ hts_status enqueue_batch(const hts_params* p, int C, const BatchPlan& plan, cons
   const int cus = device_cus();
   const Schedule& sc = plan.sc;
   auto LK = [&](int kind) { return batch_launch(p, C, table, n, kind >= 0 ? plan.totals[kind] : 0, sc); };
+  HIPCHK(launch_reset_counters(LK(-1), s));
   HIPCHK(launch_quant(LK(W_PIX), cus * 8, s));
   HIPCHK(launch_gcp(LK(W_REF), cus * 8, s));
-  HIPCHK(launch_reset_counters(LK(-1), s));
   HIPCHK(launch_match(LK(W_MATCH), p->match_mode, sc.terms, cus * 2, s));
   HIPCHK(launch_match_fallback(LK(-1), cus, s));
   HIPCHK(launch_cov(LK(W_COV), cus * 4, s));
@@ -484,6 +502,8 @@ hts_status hts_filter(const hts_params* p, const float* noisy, int32_t C, int32_
   d.ref_count = ref_count;
   d.group_est = group_est;
   d.masks = masks;
+  d.num64 = nullptr;      // estimates go to a float numerator (the caller's or scratch)
+  d.poison = nullptr;
   if (num) { d.num = num; d.cnt = cnt; }
   const size_t nb = (size_t)C * 64;
   HIPCHK(hipMemcpyAsync(d.basis, U, nb * 4, hipMemcpyDeviceToDevice, s));
@@ -561,11 +581,12 @@ hts_status hts_denoise_backward(const hts_params* p, const float* grad_out, cons
   hipStream_t s = (hipStream_t)stream;
   ImgDesc d = make_desc(g, p, (char*)ws, c, grad_out, 0.f, sc.fty, sc.ftx);
   d.cnt = const_cast<float*>(cnt);
-  // r = grad_out / cnt into the workspace image buffer
+  // r = grad_out / cnt into the workspace image buffer (and max |r|)
+  HIPCHK(launch_fill((float*)d.fxmax, 1, 0.f, s));
   HIPCHK(launch_adjoint_prep(make_launch(p, C, d, W_PIX, sc.fty, sc.ftx), 0, s));
   ImgDesc a = d;
   a.img = d.num;               // r
-  a.num = grad_in;             // accumulate the adjoint here
+  a.num = nullptr;             // the adjoint accumulates in the fixed-point numerator
   a.cnt = nullptr;
   a.idx = const_cast<int32_t*>(idx);
   a.masks_in = masks;
@@ -575,7 +596,9 @@ hts_status hts_denoise_backward(const hts_params* p, const float* grad_out, cons
   HIPCHK(hipMemcpyAsync(a.basis + nb, V, nb * 4, hipMemcpyDeviceToDevice, s));
   st = run_filter(p, C, sc, a, 1, s);
   if (st != HTS_OK) return st;
-  if (grad_tau_mult) HIPCHK(hipMemsetAsync(grad_tau_mult, 0, sizeof(float), s));
+  a.out = grad_in;             // grad_in = numerator (no division)
+  HIPCHK(launch_finalize(make_launch(p, C, a, W_PIX, sc.fty, sc.ftx), 0, s));
+  if (grad_tau_mult) HIPCHK(launch_fill(grad_tau_mult, 1, 0.f, s));
   return HTS_OK;
 }
 
@@ -706,25 +729,28 @@ hts_status hts_autotune(const hts_params* p, int32_t C, int32_t H, int32_t W,
     if (st == HTS_OK) st = run_basis(&q, C, sc, d, s);
     if (st != HTS_OK) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return st; }
   }
-  // filter tile shape
-  int best_shape = 0;
+  // filter implementation and tile shape
+  int best_shape = 0, best_valu = 0;
   float tf = 1e30f;
-  for (int i = 0; i < kNumShapes; ++i) {
-    if (filter_lds_bytes(C, p->K, p->stride, p->window, kShapes[i].ty, kShapes[i].tx) > kLdsMax) continue;
-    Schedule sc = base_sc;
-    sc.fty = kShapes[i].ty;
-    sc.ftx = kShapes[i].tx;
-    ImgDesc di = d;
-    fill_counts(g, &q, sc.fty, sc.ftx, di);
-    const float t = time_it([&] {
-      if (launch_zero_accum(make_launch(&q, C, di, W_PIX, sc.fty, sc.ftx), 0, s) != hipSuccess) return HTS_ERR_HIP;
-      return run_filter(&q, C, sc, di, 0, s);
-    });
-    if (t < tf) { tf = t; best_shape = i; }
+  for (int valu = filter_mfma_supported(C, p->K) ? 0 : 1; valu <= 1; ++valu) {
+    for (int i = 0; i < kNumShapes; ++i) {
+      if (filter_impl_lds(p, C, valu, kShapes[i].ty, kShapes[i].tx) > kLdsMax) continue;
+      Schedule sc = base_sc;
+      sc.valu = valu;
+      sc.fty = kShapes[i].ty;
+      sc.ftx = kShapes[i].tx;
+      ImgDesc di = d;
+      fill_counts(g, &q, sc.fty, sc.ftx, di);
+      const float t = time_it([&] {
+        if (launch_zero_accum(make_launch(&q, C, di, W_PIX, sc.fty, sc.ftx), 0, s) != hipSuccess) return HTS_ERR_HIP;
+        return run_filter(&q, C, sc, di, 0, s);
+      });
+      if (t < tf) { tf = t; best_shape = i; best_valu = valu; }
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  const int word = (best_shape + 1) | ((best_terms == 1 ? 1 : 2) << 4);
+  const int word = (best_shape + 1) | ((best_terms == 1 ? 1 : 2) << 4) | (best_valu << 6);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[key] = word;

@@ -48,6 +48,103 @@ __device__ __forceinline__ void for_each_item(const Launch& L, F&& body) {
 // valid position (the clamp realises the extra last reference).
 __device__ inline int ref_coord(int i, int s, int n_valid) { return min(i * s, n_valid - 1); }
 
+// Aggregation accumulates estimates in 64-bit two's-complement fixed point
+// with 32 fractional bits: integer additions are exact, so sums do not
+// depend on the order in which work groups add them.  fx_from_float is
+// exact for |v| < 2^24 up to the 2^-32 step and saturates beyond +-2^31.
+__device__ inline unsigned long long fx_from_float(float v) {
+  const float fl = floorf(v);
+  const int hi = (int)fl;
+  const unsigned lo = (unsigned)((v - fl) * 4294967296.0f);
+  return ((unsigned long long)(unsigned)hi << 32) + lo;
+}
+__device__ inline double fx_to_double(unsigned long long x) {
+  return (double)(long long)x * 0x1p-32;
+}
+
+// Power-of-two factor applied to the estimates before the fixed-point
+// conversion (and divided out at the write-back): it maps the largest input
+// magnitude M of the image to [2^11, 2^12), so the 2^-32 step is relative
+// to M and per-pixel sums of thousands of estimates of size M stay within
+// the 31 integer bits.  1 when the numerator is not fixed point.
+__device__ inline float fx_scale(const ImgDesc& d) {
+  if (!d.num64 || !d.fxmax) return 1.f;
+  const int e = (int)((*d.fxmax >> 23) & 0xffu) - 127;   // M in [2^e, 2^(e+1))
+  int k = e == 128 ? 0 : 11 - e;                          // inf / NaN: output is NaN anyway
+  k = min(max(k, -100), 100);
+  return __int_as_float((k + 127) << 23);
+}
+
+// Bits of |v| for the magnitude reduction; non-finite values count as 0
+// (their groups are poisoned, so they should not set the scale).
+__device__ inline uint32_t abs_bits(float v) {
+  const uint32_t b = __float_as_uint(v) & 0x7fffffffu;
+  return b < 0x7f800000u ? b : 0u;
+}
+
+// Folds the max over the calling threads of abs_bits values into *dst (the
+// bit pattern of a non-negative float is monotonic).
+__device__ inline void absmax_to(uint32_t* dst, uint32_t bits) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const uint32_t v = (uint32_t)__shfl_xor((int)bits, o, 64);
+    bits = v > bits ? v : bits;
+  }
+  if ((threadIdx.x & 63) == 0 && bits) atomicMax(dst, bits);
+}
+
+// Row y and column x of a flattened position pos = y*W + x (rW = 1/W in
+// FP32).  The FP32 quotient is within one of the true row while pos/W stays
+// below 2^22 (relative error <= 3 * 2^-24), so one correction step is exact;
+// callers clamp the result, which keeps out-of-range positions in bounds.
+__device__ inline void split_pos(int pos, int W, float rW, int& y, int& x) {
+  y = (int)((float)pos * rW);
+  x = pos - y * W;
+  if (x < 0) { --y; x += W; }
+  else if (x >= W) { ++y; x -= W; }
+}
+
+// A group that gathered a non-finite pixel or produced a non-finite estimate
+// marks every pixel of its K patches: in the poison plane when the
+// numerator is fixed point (the write-back turns those pixels into NaN),
+// else by adding NaN to the float numerator; its exported estimates become
+// NaN.  Called by all 64 lanes of a wavefront; lane = patch pixel.
+__device__ inline void poison_group(const ImgDesc& d, const int* gidx, int grel, int K, int C,
+                                    float rW, int lane) {
+  for (int k = 0; k < K; ++k) {
+    if (d.group_est)
+      for (int c = 0; c < C; ++c)
+        d.group_est[(((size_t)grel * K + k) * C + c) * PS2 + lane] = __builtin_nanf("");
+    int py, px;
+    split_pos(gidx[k], d.W, rW, py, px);
+    py = min(max(py, 0), d.Hp - 1);
+    px = min(max(px, 0), d.Wp - 1);
+    const int pix = (py + (lane >> 3)) * d.W + px + (lane & 7);
+    if (d.num64) {
+      d.poison[pix] = 1;
+    } else {
+      for (int c = 0; c < C; ++c) atomicAdd(d.num + c * d.H * d.W + pix, __builtin_nanf(""));
+    }
+  }
+}
+
+// Adds one LDS tile of fixed-point sums into the image numerator (exact
+// integer atomics, or float atomics into a float numerator).
+__device__ inline void flush_tile(const ImgDesc& d, const unsigned long long* acc, int C, int RA,
+                                  int CA, int AY0, int AX0, int AH, int AW) {
+  const int HW = d.H * d.W;
+  for (int e = threadIdx.x; e < C * AH * AW; e += blockDim.x) {
+    const int pl = e / (AH * AW), rem = e - pl * (AH * AW);
+    const int y = rem / AW, x = rem - y * AW;
+    const unsigned long long v = acc[(pl * RA + y) * CA + x];
+    if (v != 0ull) {
+      const int gp = pl * HW + (AY0 + y) * d.W + AX0 + x;
+      if (d.num64) atomicAdd(d.num64 + gp, v);
+      else atomicAdd(d.num + gp, (float)fx_to_double(v));
+    }
+  }
+}
+
 // Guide quantisation: round_half_even(256 v) clamped to +-(2^20 - 1); NaN -> 0.
 __device__ inline int quantize(float v) {
   float r = rintf(v * 256.0f);

@@ -43,7 +43,10 @@ struct ImgDesc {
   double* basis64;         // U64[C][8][8], V64[C][8][8], eig[2][C/2+1][8]
   float* basis;            // U[C][8][8], V[C][8][8] (real tensors)
   float* fbasis;           // Fourier slices for the filter, see FB_* offsets
-  float* num;              // [C][H][W]
+  float* num;              // [C][H][W] float accumulator (caller's, or adjoint input)
+  unsigned long long* num64; // [C][H][W] fixed-point accumulator (2^-32 units), nullable
+  uint8_t* poison;         // [H][W] 1 where a non-finite estimate landed (with num64)
+  uint32_t* fxmax;         // [1] bits of max |input| (sets the fixed-point scale)
   float* cnt;              // [H][W]
   int32_t* hist;           // [H][W] slot-position histogram (coverage counts)
   uint32_t* masks;         // keep-masks (nullable)
@@ -132,6 +135,7 @@ hipError_t launch_scatter_est(const Launch& L, hipStream_t s);
 hipError_t launch_adjoint_prep(const Launch& L, int grid, hipStream_t s);
 hipError_t launch_synth(float* img, int C, int H, int W, hipStream_t s);
 hipError_t launch_zero_hist(const Launch& L, int grid, hipStream_t s);
+hipError_t launch_fill(float* p, int n, float v, hipStream_t s);   // fill kernel (graph-safe)
 hipError_t launch_count_hist(const Launch& L, int grid, hipStream_t s);
 hipError_t launch_count_box(const Launch& L, int grid, hipStream_t s);
 

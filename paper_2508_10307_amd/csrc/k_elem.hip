@@ -11,17 +11,23 @@ __global__ __launch_bounds__(256) void k_quant(Launch L) {
     const int HW = d.H * d.W;
     const int p0 = item * PIX_CHUNK;
     const int p1 = min(HW, p0 + PIX_CHUNK);
+    uint32_t mb = 0;   // bits of max |x| (sets the fixed-point scale of the aggregation)
     for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
       if (L.C == 1) {
-        d.gplanes[p] = quantize(d.img[p]);
+        const float v = d.img[p];
+        d.gplanes[p] = quantize(v);
+        mb = max(mb, abs_bits(v));
       } else {
-        int qr = quantize(d.img[p]);
-        int qg = quantize(d.img[HW + p]);
-        int qb = quantize(d.img[2 * HW + p]);
+        const float r = d.img[p], g = d.img[HW + p], b = d.img[2 * HW + p];
+        int qr = quantize(r);
+        int qg = quantize(g);
+        int qb = quantize(b);
         d.gplanes[p] = qg;
         d.gplanes[HW + p] = qr + qg + qb;
+        mb = max(mb, max(abs_bits(r), max(abs_bits(g), abs_bits(b))));
       }
     }
+    if (d.fxmax) absmax_to(d.fxmax, mb);
   });
 }
 
@@ -48,38 +54,64 @@ __global__ __launch_bounds__(256) void k_gcp(Launch L) {
   });
 }
 
+// Clears the per-image counters: the match fallback list length and the
+// input magnitude reduced by k_quant.
 __global__ void k_reset_counters(Launch L) {
   if (!L.table) {
-    if (threadIdx.x == 0) *L.one.fb_count = 0;
+    if (threadIdx.x == 0) {
+      *L.one.fb_count = 0;
+      if (L.one.fxmax) *L.one.fxmax = 0;
+    }
     return;
   }
-  for (int i = threadIdx.x; i < L.n_img; i += blockDim.x) *L.table[i].fb_count = 0;
+  for (int i = threadIdx.x; i < L.n_img; i += blockDim.x) {
+    *L.table[i].fb_count = 0;
+    if (L.table[i].fxmax) *L.table[i].fxmax = 0;
+  }
 }
 
-// num = 0, cnt = 0 (a fill kernel rather than a memset so that the
-// sequence stays valid inside captured graphs).
+// Accumulators to zero: the fixed-point numerator (or the float one when
+// the descriptor has none), cnt, the slot histogram and the poison plane (a
+// fill kernel rather than a memset so that the sequence stays valid inside
+// captured graphs).
 __global__ __launch_bounds__(256) void k_zero_accum(Launch L) {
   for_each_item<W_PIX>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
     const int HW = d.H * d.W;
     const int p0 = item * PIX_CHUNK;
     const int p1 = min(HW, p0 + PIX_CHUNK);
     for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
-      for (int c = 0; c < L.C; ++c) d.num[c * HW + p] = 0.0f;
+      if (d.num64) {
+        for (int c = 0; c < L.C; ++c) d.num64[c * HW + p] = 0ull;
+      } else {
+        for (int c = 0; c < L.C; ++c) d.num[c * HW + p] = 0.0f;
+      }
       if (d.cnt) d.cnt[p] = 0.0f;
       if (d.hist) d.hist[p] = 0;
+      if (d.poison) d.poison[p] = 0;
     }
   });
 }
 
-// Eq. 2 with uniform weights: out = num / cnt.
+// Eq. 2 with uniform weights: out = num / cnt, from the fixed-point
+// numerator when the descriptor has one (scale divided out, one rounding,
+// in FP64), else from the float numerator.  Without cnt the numerator is
+// converted as it is (the adjoint's output).  Pixels marked in the poison
+// plane become NaN.
 __global__ __launch_bounds__(256) void k_finalize(Launch L) {
   for_each_item<W_PIX>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
     const int HW = d.H * d.W;
     const int p0 = item * PIX_CHUNK;
     const int p1 = min(HW, p0 + PIX_CHUNK);
     for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
-      float inv = 1.0f / d.cnt[p];
-      for (int c = 0; c < L.C; ++c) d.out[c * HW + p] = d.num[c * HW + p] * inv;
+      if (d.num64) {
+        const double c = (d.cnt ? (double)d.cnt[p] : 1.0) * (double)fx_scale(d);
+        const bool bad = d.poison && d.poison[p];
+        for (int ch = 0; ch < L.C; ++ch)
+          d.out[ch * HW + p] = bad ? __builtin_nanf("") : (float)(fx_to_double(d.num64[ch * HW + p]) / c);
+      } else {
+        const float inv = 1.0f / d.cnt[p];
+        for (int ch = 0; ch < L.C; ++ch) d.out[ch * HW + p] = d.num[ch * HW + p] * inv;
+      }
     }
   });
 }
@@ -91,10 +123,16 @@ __global__ __launch_bounds__(256) void k_adjoint_prep(Launch L) {
     const int HW = d.H * d.W;
     const int p0 = item * PIX_CHUNK;
     const int p1 = min(HW, p0 + PIX_CHUNK);
+    uint32_t mb = 0;
     for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
       float inv = 1.0f / d.cnt[p];
-      for (int c = 0; c < L.C; ++c) d.num[c * HW + p] = d.img[c * HW + p] * inv;
+      for (int c = 0; c < L.C; ++c) {
+        const float r = d.img[c * HW + p] * inv;
+        d.num[c * HW + p] = r;
+        mb = max(mb, abs_bits(r));
+      }
     }
+    if (d.fxmax) absmax_to(d.fxmax, mb);
   });
 }
 
@@ -183,6 +221,15 @@ hipError_t launch_zero_accum(const Launch& L, int grid, hipStream_t s) {
 hipError_t launch_finalize(const Launch& L, int grid, hipStream_t s) {
   if (L.total <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_finalize, dim3(grid_for(L, grid)), dim3(256), 0, s, L);
+  return hipGetLastError();
+}
+__global__ void k_fill(float* p, int n, float v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+hipError_t launch_fill(float* p, int n, float v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
 hipError_t launch_zero_hist(const Launch& L, int grid, hipStream_t s) {

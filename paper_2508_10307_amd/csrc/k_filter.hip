@@ -13,10 +13,12 @@
 //    sums and differences / sqrt 2) runs first on the slots of a lane, then
 //    across lanes with xor shuffles;
 //  * thresholding, masks and the inverse transforms follow the same layout;
-//  * estimates and coverage counts accumulate into an LDS tile covering
-//    every patch the tile's groups can touch, flushed once with atomics.
-// ADJ = 1 applies frozen masks instead of the threshold and accumulates
-// without counts (adjoint of the frozen map, see hts_denoise_backward).
+//  * estimates accumulate, in 64-bit fixed point, into an LDS tile covering
+//    every patch the tile's groups can touch, flushed once with atomics
+//    (coverage counts depend only on the match indices and come from a
+//    separate histogram pass).
+// ADJ = 1 applies frozen masks instead of the threshold (adjoint of the
+// frozen map, see hts_denoise_backward).
 #include "hts_device.h"
 
 namespace hts {
@@ -111,8 +113,8 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
   const int TY = L.fty, TX = L.ftx;
   const int RA = (TY - 1) * s + 2 * r + PS, CA = (TX - 1) * s + 2 * r + PS;
   const int NP = C;
-  float* acc = fsm;                                   // [NP][RA][CA]
-  float* T = fsm + (NP * RA * CA + 3) / 4 * 4 + wave * TSCRATCH;   // transpose scratch
+  unsigned long long* acc = (unsigned long long*)fsm;          // [NP][RA][CA] fixed point
+  float* T = fsm + (2 * NP * RA * CA + 3) / 4 * 4 + wave * TSCRATCH;   // transpose scratch
 
   for_each_item<W_FILT>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
     const int ntx = (d.nrx + TX - 1) / TX;
@@ -126,9 +128,12 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
     const int HW = d.H * d.W;
     const cfloat* fb = uniform_ptr(d.fbasis);
     const float tau = d.tau;
+    const float rW = 1.0f / (float)d.W;
+    const float fxs = fx_scale(d);                 // fixed-point scale of the estimates
+    const float s3 = fxs * (1.f / 3.f), rfxs = 1.f / fxs;
 
     __syncthreads();
-    for (int e = tid; e < NP * RA * CA; e += 256) acc[e] = 0.f;
+    for (int e = tid; e < NP * RA * CA; e += 256) acc[e] = 0ull;
     __syncthreads();
 
     const int ngroups = (iy1 - iy0 + 1) * (ix1 - ix0 + 1);
@@ -139,6 +144,9 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
       const int grel = g - d.ref_begin;
 
       // ---- gather ----
+      // nf stays 0 unless a gathered pixel or an estimate is not finite
+      // (0 * inf and 0 * NaN are NaN)
+      float nf = 0.f;
       float X[SPL][C][8];
       int py[SPL], px[SPL];
 #pragma unroll
@@ -146,8 +154,9 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
         const int k = kl * SPL + j;
         const int pos = active ? d.idx[(size_t)g * K + k] : 0;
         // positions come from the caller's idx: clamp to valid patch corners
-        py[j] = min(max(pos / d.W, 0), d.Hp - 1);
-        px[j] = min(max(pos - (pos / d.W) * d.W, 0), d.Wp - 1);
+        split_pos(pos, d.W, rW, py[j], px[j]);
+        py[j] = min(max(py[j], 0), d.Hp - 1);
+        px[j] = min(max(px[j], 0), d.Wp - 1);
         const float* src = d.img + (py[j] + a) * d.W + px[j];
 #pragma unroll
         for (int ch = 0; ch < C; ++ch)
@@ -160,6 +169,8 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
       for (int j = 0; j < SPL; ++j) {
         __builtin_amdgcn_sched_barrier(0);  // keep one slot's temporaries live at a time
         if (C == 1) {
+#pragma unroll
+          for (int b = 0; b < 8; ++b) nf = fmaf(X[j][0][b], 0.f, nf);
           float y[8];
           mv<0, false>(X[j][0], fb + FB_V0, 1.f, y);
           transpose_rc(T, kl, a, y);
@@ -173,6 +184,7 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
           for (int b = 0; b < 8; ++b) {
             const float p0 = X[j][0][b], p1 = X[j][1][b], p2 = X[j][2][b];
             f0[b] = p0 + p1 + p2;
+            nf = fmaf(f0[b], 0.f, nf);
             f1r[b] = p0 - 0.5f * (p1 + p2);
             f1i[b] = HALF_SQRT3 * (p2 - p1);
           }
@@ -301,6 +313,8 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
           mv<1, false>(X[j][0], fb + FB_U0, 1.f, y);   // y[r] = sum_i U[r][i] s[i]
           transpose_cr(T, kl, a, y);
           mv<1, false>(y, fb + FB_V0, 1.f, out[0]);   // out[b] = sum_c y[c] V[b][c]
+#pragma unroll
+          for (int b = 0; b < 8; ++b) out[0][b] *= fxs;   // fixed-point scale (a power of two)
         } else {
           float s0[8], s1r[8], s1i[8];
 #pragma unroll
@@ -330,41 +344,40 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
 #pragma unroll
           for (int b = 0; b < 8; ++b) {
             const float sr = p1r[b], si = p1i[b];
-            out[0][b] = (p0[b] + 2.f * sr) * (1.f / 3.f);
-            out[1][b] = (p0[b] - sr - SQRT3 * si) * (1.f / 3.f);
-            out[2][b] = (p0[b] - sr + SQRT3 * si) * (1.f / 3.f);
+            out[0][b] = (p0[b] + 2.f * sr) * s3;   // scaled by fxs (a power of two)
+            out[1][b] = (p0[b] - sr - SQRT3 * si) * s3;
+            out[2][b] = (p0[b] - sr + SQRT3 * si) * s3;
           }
         }
         const int ly = py[j] + a - AY0, lx = px[j] - AX0;
         // a patch outside the tile's reach (idx not from this reference's
         // search window) is not aggregated
         const bool inside = ly >= a && ly + PS - a <= AH && lx >= 0 && lx + PS <= AW;
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch)
+#pragma unroll
+          for (int b = 0; b < 8; ++b) nf = fmaf(out[ch][b], 0.f, nf);
         if (active && inside) {
           const int k = kl * SPL + j;
 #pragma unroll
           for (int ch = 0; ch < C; ++ch) {
-            float* rowp = acc + (ch * RA + ly) * CA + lx;
+            unsigned long long* rowp = acc + (ch * RA + ly) * CA + lx;
 #pragma unroll
-            for (int b = 0; b < 8; ++b) atomicAdd(rowp + b, out[ch][b]);
+            for (int b = 0; b < 8; ++b) atomicAdd(rowp + b, fx_from_float(out[ch][b]));
           }
           if (d.group_est) {
             float* ge = d.group_est + (((size_t)grel * K + k) * C) * PS2 + a * 8;
 #pragma unroll
             for (int ch = 0; ch < C; ++ch)
 #pragma unroll
-              for (int b = 0; b < 8; ++b) ge[ch * PS2 + b] = out[ch][b];
+              for (int b = 0; b < 8; ++b) ge[ch * PS2 + b] = out[ch][b] * rfxs;
           }
         }
       }
+      if (__ballot(nf != 0.f)) poison_group(d, d.idx + (size_t)g * K, grel, K, C, rW, lane);
     }
     __syncthreads();
-    // ---- flush the tile accumulator ----
-    for (int e = tid; e < C * AH * AW; e += 256) {
-      const int pl = e / (AH * AW), rem = e - pl * (AH * AW);
-      const int y = rem / AW, x = rem - y * AW;
-      const float v = acc[(pl * RA + y) * CA + x];
-      if (v != 0.f) atomicAdd(d.num + pl * HW + (AY0 + y) * d.W + AX0 + x, v);
-    }
+    flush_tile(d, acc, C, RA, CA, AY0, AX0, AH, AW);
   });
 }
 
@@ -373,7 +386,7 @@ size_t filter_lds_bytes(int C, int K, int stride, int window, int ty, int tx) {
   const int r = (window - 1) / 2;
   const size_t RA = (size_t)(ty - 1) * stride + 2 * r + PS;
   const size_t CA = (size_t)(tx - 1) * stride + 2 * r + PS;
-  return ((C * RA * CA + 3) / 4 * 4 + 4 * TSCRATCH) * sizeof(float);
+  return ((2 * C * RA * CA + 3) / 4 * 4 + 4 * TSCRATCH) * sizeof(float);
 }
 
 template <int C, int ADJ>
@@ -386,8 +399,12 @@ static hipError_t launch_filter_c(const Launch& L, int g, size_t lds, hipStream_
     case 32:
       hipLaunchKernelGGL((k_filter<C, 4, ADJ>), dim3(g), dim3(256), lds, s, L); break;
     case 64:
-      if (C == 1) { hipLaunchKernelGGL((k_filter<C, 8, ADJ>), dim3(g), dim3(256), lds, s, L); break; }
-      return hipErrorInvalidValue;
+      if constexpr (C == 1) {
+        hipLaunchKernelGGL((k_filter<C, 8, ADJ>), dim3(g), dim3(256), lds, s, L);
+        break;
+      } else {
+        return hipErrorInvalidValue;
+      }
     default:
       return hipErrorInvalidValue;
   }
@@ -412,10 +429,15 @@ __global__ __launch_bounds__(256) void k_scatter_est(Launch L, const float* est,
   const int lane = threadIdx.x & 63;
   if (gw >= d.ref_count) return;
   const int g = d.ref_begin + gw;
+  const float rW = 1.0f / (float)d.W;
   for (int e = lane; e < K * PS; e += 64) {
     const int k = e >> 3, a = e & 7;
     const int pos = d.idx[(size_t)g * K + k];
-    const int py = pos / d.W, px = pos - py * d.W;
+    // positions come from the caller's idx: clamp to valid patch corners
+    int py, px;
+    split_pos(pos, d.W, rW, py, px);
+    py = min(max(py, 0), d.Hp - 1);
+    px = min(max(px, 0), d.Wp - 1);
     for (int ch = 0; ch < C; ++ch)
       for (int b = 0; b < 8; ++b)
         atomicAdd(d.num + ch * HW + (py + a) * d.W + px + b,

@@ -21,8 +21,10 @@
 // Lane l = 16 q + n (q = l / 16, n = l % 16, s = n / 8).  The Haar transform
 // along the group mode pairs slots 2b, 2b+1 across lanes (xor 8) and the
 // coarser levels inside each lane's registers; thresholding, mask export,
-// the inverse Haar and the inverse projection follow; estimates and counts
-// accumulate in an LDS tile exactly as in the vector-ALU filter.
+// the inverse Haar and the inverse projection follow; estimates accumulate in
+// a fixed-point LDS tile exactly as in the vector-ALU filter (coverage counts
+// come from the match indices alone and are computed by a separate
+// histogram pass).
 #include "hts_device.h"
 
 namespace hts {
@@ -87,8 +89,8 @@ __global__ __launch_bounds__(256, K >= 32 ? 1 : 2) void k_filter_mfma(Launch L) 
   const int TY = L.fty, TX = L.ftx;
   const int RA = (TY - 1) * st + 2 * r + PS, CA = (TX - 1) * st + 2 * r + PS;
   constexpr int NP = C;
-  float* acc = fsm;                                   // [NP][RA][CA]
-  float* T = fsm + (NP * RA * CA + 3) / 4 * 4 + wave * TSZ;   // transpose scratch (16 B aligned)
+  unsigned long long* acc = (unsigned long long*)fsm;          // [NP][RA][CA] fixed point
+  float* T = fsm + (2 * NP * RA * CA + 3) / 4 * 4 + wave * TSZ;   // transpose scratch (16 B aligned)
   const bool swap40 = ((lane >> 5) & 1) != ((lane >> 3) & 1);
   const bool upper32 = lane >= 32;
 
@@ -103,6 +105,9 @@ __global__ __launch_bounds__(256, K >= 32 ? 1 : 2) void k_filter_mfma(Launch L) 
     const int AW = AX1 - AX0 + 1, AH = AY1 - AY0 + 1;
     const int HW = d.H * d.W;
     const float tau = d.tau;
+    const float rW = 1.0f / (float)d.W;
+    const float fxs = fx_scale(d);                 // fixed-point scale of the estimates
+    const float s3 = fxs * (1.f / 3.f), rfxs = 1.f / fxs;
     const float* fb = d.fbasis;
 
     // ---- basis operands for the four products (see the header comment) ----
@@ -143,7 +148,7 @@ __global__ __launch_bounds__(256, K >= 32 ? 1 : 2) void k_filter_mfma(Launch L) 
     }
 
     __syncthreads();
-    for (int e = tid; e < NP * RA * CA; e += 256) acc[e] = 0.f;
+    for (int e = tid; e < NP * RA * CA; e += 256) acc[e] = 0ull;
     __syncthreads();
 
     const int gw = ix1 - ix0 + 1;
@@ -155,12 +160,19 @@ __global__ __launch_bounds__(256, K >= 32 ? 1 : 2) void k_filter_mfma(Launch L) 
       const int* gidx = d.idx + (size_t)g * K;
 
       // ---- gather rows (slot 2b+s, patch row n8, columns 2q, 2q+1) + channel DFT ----
+      // nf stays 0 unless a gathered pixel or an estimate is not finite
+      // (0 * inf and 0 * NaN are NaN); the packed f = 0 products multiply
+      // by zero blocks, which would turn an infinite pixel into NaN
+      // coefficients that the threshold then drops, so inputs are checked too.
+      float nf = 0.f;
       float X[NCU][4];
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const int pos = gidx[2 * b + s];
-        const int py = min(max(pos / d.W, 0), d.Hp - 1);
-        const int px = min(max(pos - (pos / d.W) * d.W, 0), d.Wp - 1);
+        int py, px;
+        split_pos(pos, d.W, rW, py, px);
+        py = min(max(py, 0), d.Hp - 1);
+        px = min(max(px, 0), d.Wp - 1);
         const float* src = d.img + (py + n8) * d.W + px + 2 * q;
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
@@ -168,6 +180,7 @@ __global__ __launch_bounds__(256, K >= 32 ? 1 : 2) void k_filter_mfma(Launch L) 
           X[b][e] = p0 - 0.5f * (p1 + p2);             // Re P^(1)
           X[b][2 + e] = HSQ3 * (p2 - p1);              // Im P^(1)
           X[NB + b / 2][2 * (b & 1) + e] = p0 + p1 + p2;  // P^(0), packed
+          nf = fmaf(p0 + p1 + p2, 0.f, nf);
         }
       }
 
@@ -371,8 +384,10 @@ __global__ __launch_bounds__(256, K >= 32 ? 1 : 2) void k_filter_mfma(Launch L) 
         const int bb = 2 * p + hb;
         const int k = 2 * bb + (q >> 1);
         const int pos = gidx[k];
-        const int py = min(max(pos / d.W, 0), d.Hp - 1);
-        const int px = min(max(pos - (pos / d.W) * d.W, 0), d.Wp - 1);
+        int py, px;
+        split_pos(pos, d.W, rW, py, px);
+        py = min(max(py, 0), d.Hp - 1);
+        px = min(max(px, 0), d.Wp - 1);
         const int ly0 = py + 4 * (q & 1) - AY0, lx = px + n8 - AX0;
         const bool inside = py - AY0 >= 0 && py - AY0 + PS <= AH && px - AX0 >= 0 && px - AX0 + PS <= AW;
 #pragma unroll
@@ -382,32 +397,30 @@ __global__ __launch_bounds__(256, K >= 32 ? 1 : 2) void k_filter_mfma(Launch L) 
           const float p0 = X[NB + p][j];
           const float pr = hb ? recv : X[2 * p][j];
           const float pi = hb ? X[2 * p + 1][j] : recv;
-          const float o0 = (p0 + 2.f * pr) * (1.f / 3.f);
-          const float o1 = (p0 - pr - SQ3 * pi) * (1.f / 3.f);
-          const float o2 = (p0 - pr + SQ3 * pi) * (1.f / 3.f);
+          const float o0 = (p0 + 2.f * pr) * s3;   // scaled by fxs (a power of two)
+          const float o1 = (p0 - pr - SQ3 * pi) * s3;
+          const float o2 = (p0 - pr + SQ3 * pi) * s3;
+          nf = fmaf(o0, 0.f, nf);
+          nf = fmaf(o1, 0.f, nf);
+          nf = fmaf(o2, 0.f, nf);
           if (inside) {
-            float* a0 = acc + (ly0 + j) * CA + lx;
-            atomicAdd(a0, o0);
-            atomicAdd(a0 + RA * CA, o1);
-            atomicAdd(a0 + 2 * RA * CA, o2);
+            unsigned long long* a0 = acc + (ly0 + j) * CA + lx;
+            atomicAdd(a0, fx_from_float(o0));
+            atomicAdd(a0 + RA * CA, fx_from_float(o1));
+            atomicAdd(a0 + 2 * RA * CA, fx_from_float(o2));
             if (d.group_est) {
               float* ge = d.group_est + (((size_t)grel * K + k) * C) * PS2 + (4 * (q & 1) + j) * 8 + n8;
-              ge[0] = o0;
-              ge[PS2] = o1;
-              ge[2 * PS2] = o2;
+              ge[0] = o0 * rfxs;
+              ge[PS2] = o1 * rfxs;
+              ge[2 * PS2] = o2 * rfxs;
             }
           }
         }
       }
+      if (__ballot(nf != 0.f)) poison_group(d, gidx, grel, K, C, rW, lane);
     }
     __syncthreads();
-    // ---- flush the tile accumulator ----
-    for (int e = tid; e < C * AH * AW; e += 256) {
-      const int pl = e / (AH * AW), rem = e - pl * (AH * AW);
-      const int y = rem / AW, x = rem - y * AW;
-      const float v = acc[(pl * RA + y) * CA + x];
-      if (v != 0.f) atomicAdd(d.num + pl * HW + (AY0 + y) * d.W + AX0 + x, v);
-    }
+    flush_tile(d, acc, C, RA, CA, AY0, AX0, AH, AW);
   });
 }
 
@@ -415,7 +428,7 @@ size_t filter_mfma_lds_bytes(int stride, int window, int ty, int tx) {
   const int r = (window - 1) / 2;
   const size_t RA = (size_t)(ty - 1) * stride + 2 * r + PS;
   const size_t CA = (size_t)(tx - 1) * stride + 2 * r + PS;
-  return ((3 * RA * CA + 3) / 4 * 4 + 4 * TSZ) * sizeof(float);
+  return ((2 * 3 * RA * CA + 3) / 4 * 4 + 4 * TSZ) * sizeof(float);
 }
 
 bool filter_mfma_supported(int C, int K) { return C == 3 && (K == 4 || K == 8 || K == 16 || K == 32); }

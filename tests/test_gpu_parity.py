@@ -319,3 +319,79 @@ def test_mfma_filter_matches_valu_filter(K):
     gm, _ = api.hts_denoise_backward(g, sm, pm)
     gv, _ = api.hts_denoise_backward(g, sm, pv)
     assert (gm - gv).abs().max().item() <= 1e-4 * max(1.0, gv.abs().max().item())
+
+
+# ---------------------------------------------------------------- reproducibility
+@pytest.mark.parametrize("impl", [0, 1 << 6], ids=["mfma", "valu"])
+def test_denoise_bit_reproducible_across_tile_shapes(impl):
+    # Estimates are summed in 64-bit fixed point: the output does not depend
+    # on which work group adds which estimate, so every tile shape (and every
+    # repetition) of one filter implementation gives the same bits.
+    y = synth.tiny(4242, 3, 90, 77, sigma=20.0, n_blobs=8)
+    x = T(y)
+    outs, grads = [], []
+    g = T(np.random.default_rng(3).normal(size=y.shape))
+    for shape in (0, 4, 7, 9, 0):          # auto, 4x4, 2x2, 1x1, auto again
+        p = P(stride=3, window=15, K=16, tune=impl | (2 << 4) | shape)
+        o, st = api.hts_denoise(x, 20.0, p, save=True)
+        outs.append(o)
+        grads.append(api.hts_denoise_backward(g, st, p)[0])
+    for o, gr in zip(outs[1:], grads[1:]):
+        assert torch.equal(o, outs[0])
+        assert torch.equal(gr, grads[0])
+
+
+# ---------------------------------------------------------------- non-finite inputs
+def test_nan_pixel_makes_the_whole_output_nan():
+    # a NaN enters the covariances, so the global basis and every estimate are NaN
+    y = synth.tiny(77, 3, 40, 36, sigma=10.0)
+    y[1, 17, 9] = np.nan
+    out = api.hts_denoise(T(y), 10.0, P(stride=3, window=11, K=8))
+    assert torch.isnan(out).all()
+
+
+def _touching_patches(idx, W, H, y0, x0):
+    py, px = idx // W, idx % W
+    touch = ((py <= y0) & (y0 < py + 8) & (px <= x0) & (x0 < px + 8)).any(axis=1)
+    bad = np.zeros((H, W), bool)
+    for g in np.nonzero(touch)[0]:
+        for k in range(idx.shape[1]):
+            bad[py[g, k]:py[g, k] + 8, px[g, k]:px[g, k] + 8] = True
+    return bad
+
+
+@pytest.mark.parametrize("impl", [0, 1 << 6], ids=["mfma", "valu"])
+def test_inf_pixel_poisons_exactly_the_groups_that_touch_it(impl):
+    # With a finite basis, the groups that gather an infinite pixel are
+    # poisoned: every pixel of their patches becomes NaN, their exported
+    # estimates too, and every other pixel keeps its value (float numerator
+    # of hts_filter; fixed-point numerator of the adjoint).
+    H, W = 48, 44
+    y = synth.tiny(78, 3, H, W, sigma=12.0)
+    p = P(stride=3, window=11, K=8, tune=impl)
+    x = T(y)
+    _, st = api.hts_denoise(x, 12.0, p, save=True)
+    idx = st["idx"].cpu().numpy().astype(np.int64)
+    bad = _touching_patches(idx, W, H, 20, 23)
+    assert 0 < bad.sum() < H * W
+    yi = y.copy()
+    yi[0, 20, 23] = np.inf
+    ra = api.hts_filter(T(yi), 12.0, st["idx"], st["U"], st["V"], p, want_group_est=True)
+    a = ra["num"].cpu().numpy()
+    b = api.hts_filter(x, 12.0, st["idx"], st["U"], st["V"], p)["num"].cpu().numpy()
+    touch = ((idx // W <= 20) & (20 < idx // W + 8) & (idx % W <= 23) & (23 < idx % W + 8)).any(axis=1)
+    ge = ra["group_est"].cpu().numpy().reshape(len(idx), -1)
+    assert np.isnan(ge[touch]).all() and np.isfinite(ge[~touch]).all()
+    assert np.array_equal(np.isnan(a).all(axis=0), bad)
+    assert np.isfinite(a[:, ~bad]).all()
+    assert np.abs(a[:, ~bad] - b[:, ~bad]).max() <= 1e-4 * max(1.0, np.abs(b).max())
+    # adjoint: grad_out with an infinite pixel
+    cnt = st["cnt"].cpu().numpy()
+    g = np.random.default_rng(5).normal(size=y.shape)
+    gi = g.copy()
+    gi[2, 20, 23] = np.inf
+    ga = api.hts_denoise_backward(T(gi), st, p)[0].cpu().numpy()
+    gb = api.hts_denoise_backward(T(g), st, p)[0].cpu().numpy()
+    assert cnt.min() >= 1
+    assert np.array_equal(np.isnan(ga).all(axis=0), bad)
+    assert np.abs(ga[:, ~bad] - gb[:, ~bad]).max() <= 1e-6 * max(1.0, np.abs(gb).max())

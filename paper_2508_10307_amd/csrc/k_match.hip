@@ -16,8 +16,9 @@
 //     (K-1)-th smallest distance;
 //  4. pass 2 recomputes the tiles and shortlists every candidate with
 //     d~ - E <= T: a superset of the exact top K-1, ties included;
-//  5. the shortlist is re-ranked with exact integer distances and sorted by
-//     (distance, index) on one wavefront; slot 0 is the reference itself.
+//  5. the shortlist is re-ranked with exact integer distances (computed in
+//     FP64, exact below 2^53) and sorted by (distance, index) on one
+//     wavefront; slot 0 is the reference itself.
 //
 // A reference whose shortlist exceeds SHORT_CAP goes to a list handled by
 // k_match_fallback (exact scan of the whole window).
@@ -56,7 +57,11 @@ __device__ inline unsigned split_pack(float v) {
   return bf16_bits(h) | (bf16_bits(l) << 16);
 }
 
-template <int MODE, int TERMS>
+// Blocks per wavefront whose lower bounds stay in registers between the
+// two passes (CACHE = 1): 36 covers windows up to 39 at stride 2 or 3.
+constexpr int MAXBW = 36;
+
+template <int MODE, int TERMS, int CACHE>
 __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
   extern __shared__ __align__(16) unsigned char smem[];
   const MatchGeom G = match_geom(L.stride, L.window);
@@ -203,18 +208,21 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
       __syncthreads();
 
       // ---- per-lane reference state: references 4*kq + i, candidate column n ----
-      bool inpl[4];
-      int rpx[4], wx0[4], wx1[4];
+      // Reference 4*kq + i sits in tile row kq, so its window rows depend on
+      // kq only; its window columns, as [wx0, wx0 + wxl) (wxl = 0 when the
+      // reference does not use this plane).
+      int rpx[4], wx0[4];
+      unsigned wxl[4];
       float na[4], sa[4];
       const int rpy = rinfo[(4 * kq) * 8 + 1];
-      const int wy0 = rinfo[(4 * kq) * 8 + 3], wy1 = rinfo[(4 * kq) * 8 + 4];
+      const int wy0 = rinfo[(4 * kq) * 8 + 3];
+      const unsigned wyl = (unsigned)(rinfo[(4 * kq) * 8 + 4] - wy0 + 1);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int* ri = rinfo + (4 * kq + i) * 8;
-        inpl[i] = (ri[0] >> p) & 1;
         rpx[i] = ri[2];
         wx0[i] = ri[5];
-        wx1[i] = ri[6];
+        wxl[i] = ((ri[0] >> p) & 1) ? (unsigned)(ri[6] - ri[5] + 1) : 0u;
         na[i] = rnorm[2 * (4 * kq + i)];
         sa[i] = rnorm[2 * (4 * kq + i) + 1];
       }
@@ -240,9 +248,11 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
         }
       }
 
-      auto tile_dist = [&](int cy, int cx, float (&dt)[4], float (&E)[4], bool (&ok)[4]) {
-        const bool cx_ok = cx < RXc;
-        const bool cy_ok = cy >= wy0 && cy <= wy1;
+      // Distances of references 4*kq + i to candidate (cy, cx), their error
+      // bounds, and whether the candidate is in the reference's window (and
+      // is not the reference itself).  cy is the same on every lane.
+      auto tile_dist = [&](int cy, int cx, float (&dt)[4], float (&E)[4], bool (&ok)[4])
+          __attribute__((always_inline)) {
         if (MODE == 0) {
           floatx4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -291,39 +301,74 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
             E[i] = SSD_REL * acc[i] + BOUND_ABS;
           }
         }
+        const bool cy_ok = (unsigned)(cy - wy0) < wyl;
+        const bool cy_self = cy == rpy;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          ok[i] = cx_ok && cy_ok && inpl[i] && cx >= wx0[i] && cx <= wx1[i] &&
-                  !(cy == rpy && cx == rpx[i]);
+          ok[i] = cy_ok & ((unsigned)(cx - wx0[i]) < wxl[i]) & !(cy_self & (cx == rpx[i]));
       };
 
+      // Blocks (candidate row cy, 16-column block xb) are dealt round-robin to
+      // the wavefronts; (cy, xb) advance by 4 blocks without a division.
+      const int wv = __builtin_amdgcn_readfirstlane(wave);
       const int nblocks = RYc * NXB;
-      const float INF = __builtin_huge_valf();
+      const int nbw = nblocks > wv ? (nblocks - wv + 3) >> 2 : 0;
+      const int cy0 = wv / NXB, xb0 = wv - cy0 * NXB;
+      auto step = [&](int& cy, int& xb) __attribute__((always_inline)) {
+        xb += 4;
+        while (xb >= NXB) { xb -= NXB; ++cy; }
+      };
+      constexpr unsigned INFB = 0x7f800000u;   // +inf
 
       // ---- pass 1: two smallest upper bounds per (lane, reference) ----
-      float m0[4] = {INF, INF, INF, INF}, m1[4] = {INF, INF, INF, INF};
-      for (int bi = wave; bi < nblocks; bi += 4) {
-        const int cy = bi / NXB, cx = (bi - cy * NXB) * 16 + n;
+      // Bounds are non-negative floats, compared as their bit patterns.  With
+      // CACHE the lower bounds max(d~ - E, 0) stay in registers for pass 2 as
+      // the upper 16 bits of their float patterns (truncation only lowers a
+      // non-negative float, so pass 2 still shortlists a superset), two per
+      // register; 0xFFFF marks a non-candidate.
+      unsigned m0[4] = {INFB, INFB, INFB, INFB}, m1[4] = {INFB, INFB, INFB, INFB};
+      unsigned lbc[CACHE ? MAXBW : 1][2];
+      auto pass1 = [&](int cy, int xb, unsigned (&lbw)[2]) __attribute__((always_inline)) {
         float dt[4], E[4];
         bool ok[4];
-        tile_dist(cy, cx, dt, E, ok);
+        tile_dist(cy, xb * 16 + n, dt, E, ok);
+        unsigned lh[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const float hv = ok[i] ? fmaxf(dt[i] + E[i], 0.f) : INF;
-          m1[i] = fminf(m1[i], fmaxf(m0[i], hv));
-          m0[i] = fminf(m0[i], hv);
+          const unsigned hv = ok[i] ? __float_as_uint(fmaxf(dt[i] + E[i], 0.f)) : INFB;
+          m1[i] = min(m1[i], max(m0[i], hv));
+          m0[i] = min(m0[i], hv);
+          lh[i] = ok[i] ? __float_as_uint(fmaxf(dt[i] - E[i], 0.f)) >> 16 : 0xFFFFu;
+        }
+        lbw[0] = lh[0] | (lh[1] << 16);
+        lbw[1] = lh[2] | (lh[3] << 16);
+      };
+      {
+        int cy = cy0, xb = xb0;
+        if constexpr (CACHE) {
+#pragma unroll
+          for (int j = 0; j < MAXBW; ++j) {
+            if (j < nbw) pass1(cy, xb, lbc[j]);
+            step(cy, xb);
+          }
+        } else {
+          for (int j = 0; j < nbw; ++j) {
+            unsigned lbw[2];
+            pass1(cy, xb, lbw);
+            step(cy, xb);
+          }
         }
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         float* dst = tl + ((4 * kq + i) * 64 + wave * 16 + n) * 2;
-        dst[0] = m0[i];
-        dst[1] = m1[i];
+        dst[0] = __uint_as_float(m0[i]);
+        dst[1] = __uint_as_float(m1[i]);
       }
       __syncthreads();
 
       // ---- threshold T per reference: (K-1)-th smallest of its 128 list values ----
-      for (int t = wave; t < 16; t += 4) {
+      for (int t = wv; t < 16; t += 4) {
         if (!((rinfo[t * 8] >> p) & 1)) continue;
         unsigned long long v[2];
 #pragma unroll
@@ -339,27 +384,60 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
       __syncthreads();
 
       // ---- pass 2: shortlist every candidate with d~ - E <= T ----
+      // Shortlist entries are packed (cy << 8) | cx.
+      // Tp is only set for references on this plane: the others get Th = 0,
+      // which no non-candidate marker (0xFFFF) passes.
       float Ti[4];
+      unsigned Th[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) Ti[i] = Tp[4 * kq + i];
-      for (int bi = wave; bi < nblocks; bi += 4) {
-        const int cy = bi / NXB, cx = (bi - cy * NXB) * 16 + n;
-        float dt[4], E[4];
-        bool ok[4];
-        tile_dist(cy, cx, dt, E, ok);
+      for (int i = 0; i < 4; ++i) {
+        Ti[i] = Tp[4 * kq + i];
+        Th[i] = wxl[i] ? __float_as_uint(Ti[i]) >> 16 : 0u;
+      }
+      auto pass2 = [&](int cy, int xb, const bool (&h)[4]) __attribute__((always_inline)) {
+        const int cx = xb * 16 + n;
+        if (h[0] | h[1] | h[2] | h[3]) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          if (ok[i] && dt[i] - E[i] <= Ti[i]) {
-            const int t = 4 * kq + i;
-            const int pos = atomicAdd(&scount[t], 1);
-            if (pos < SHORT_CAP) sl[t * SHORT_CAP + pos] = (unsigned)(cy * RXP + cx);
+          for (int i = 0; i < 4; ++i) {
+            if (h[i]) {
+              const int t = 4 * kq + i;
+              const int pos = atomicAdd(&scount[t], 1);
+              if (pos < SHORT_CAP) sl[t * SHORT_CAP + pos] = ((unsigned)cy << 8) | (unsigned)cx;
+            }
+          }
+        }
+      };
+      {
+        int cy = cy0, xb = xb0;
+        if constexpr (CACHE) {
+#pragma unroll
+          for (int j = 0; j < MAXBW; ++j) {
+            if (j < nbw) {
+              bool h[4];
+#pragma unroll
+              for (int i = 0; i < 4; ++i) h[i] = ((lbc[j][i >> 1] >> (16 * (i & 1))) & 0xFFFFu) <= Th[i];
+              pass2(cy, xb, h);
+            }
+            step(cy, xb);
+          }
+        } else {
+          for (int j = 0; j < nbw; ++j) {
+            float dt[4], E[4];
+            bool ok[4], h[4];
+            tile_dist(cy, xb * 16 + n, dt, E, ok);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) h[i] = ok[i] && dt[i] - E[i] <= Ti[i];
+            pass2(cy, xb, h);
+            step(cy, xb);
           }
         }
       }
       __syncthreads();
 
       // ---- exact re-rank on one wavefront per reference ----
-      for (int t = wave; t < 16; t += 4) {
+      // Exact squared distances in FP64: |differences| < 2^22, so every
+      // product and partial sum (< 2^50) is an exact integer.
+      for (int t = wv; t < 16; t += 4) {
         const int* ri = rinfo + t * 8;
         if (!((ri[0] >> p) & 1)) continue;
         const int ref = ri[7];
@@ -369,33 +447,59 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
           continue;
         }
         const int py0 = ri[1], px0 = ri[2], ty0 = ri[3], tx0 = ri[5];
-        unsigned long long key[2];
+        // keys of shortlist entries j[e] (entries past nsl read entry 0 and are dropped)
+        auto exact_keys = [&](auto& key, const int (&j)[sizeof(key) / 8])
+            __attribute__((always_inline)) {
+          constexpr int E = sizeof(key) / 8;
+          int cy[E], cx[E];
+          double dd[E];
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          const int j = e * 64 + lane;
-          key[e] = ~0ull;
-          if (j < nsl) {
-            const unsigned pos = sl[t * SHORT_CAP + j];
-            const int cy = pos / RXP, cx = pos - cy * RXP;
-            long long dd = 0;
-            for (int py = 0; py < PS; ++py)
+          for (int e = 0; e < E; ++e) {
+            const unsigned pk = sl[t * SHORT_CAP + (j[e] < nsl ? j[e] : 0)];
+            cy[e] = (int)(pk >> 8);
+            cx[e] = (int)(pk & 255u);
+            dd[e] = 0.0;
+          }
+#pragma unroll 1
+          for (int py = 0; py < PS; ++py) {
+            int rrow[PS];   // reference row (same address on every lane)
+#pragma unroll
+            for (int px = 0; px < PS; ++px) rrow[px] = gi[(py0 + py) * pitch + px0 + px];
+#pragma unroll
+            for (int e = 0; e < E; ++e)
 #pragma unroll
               for (int px = 0; px < PS; ++px) {
-                const int df = gi[(py0 + py) * pitch + px0 + px] - gi[(cy + py) * pitch + cx + px];
-                dd += (long long)df * df;
+                const double df = (double)(rrow[px] - gi[(cy[e] + py) * pitch + cx[e] + px]);
+                dd[e] = fma(df, df, dd[e]);
               }
-            key[e] = ((unsigned long long)dd << 12) | (unsigned)((cy - ty0) * 64 + (cx - tx0));
           }
-        }
-        wave_sort_u64<2>(key);
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          const int g = e * 64 + lane;
-          if (g < K - 1) {
-            const unsigned loc = (unsigned)(key[e] & 0xFFFu);
-            const int cy = Y0 + ty0 + (int)(loc >> 6), cx = X0 + tx0 + (int)(loc & 63u);
-            d.idx[(size_t)ref * K + 1 + g] = cy * d.W + cx;
-            if (d.dist) d.dist[(size_t)ref * K + 1 + g] = (long long)(key[e] >> 12);
+          for (int e = 0; e < E; ++e)
+            key[e] = j[e] < nsl ? ((unsigned long long)dd[e] << 12) |
+                                      (unsigned)((cy[e] - ty0) * 64 + (cx[e] - tx0))
+                                : ~0ull;
+        };
+        auto emit = [&](int g, unsigned long long key) __attribute__((always_inline)) {
+          const unsigned loc = (unsigned)(key & 0xFFFu);
+          const int cy = Y0 + ty0 + (int)(loc >> 6), cx = X0 + tx0 + (int)(loc & 63u);
+          d.idx[(size_t)ref * K + 1 + g] = cy * d.W + cx;
+          if (d.dist) d.dist[(size_t)ref * K + 1 + g] = (long long)(key >> 12);
+        };
+        if (nsl <= 64) {
+          unsigned long long key[1];
+          const int j[1] = {lane};
+          exact_keys(key, j);
+          wave_sort_u64<1>(key);
+          if (lane < K - 1) emit(lane, key[0]);
+        } else {
+          unsigned long long key[2];
+          const int j[2] = {lane, 64 + lane};
+          exact_keys(key, j);
+          wave_sort_u64<2>(key);
+#pragma unroll
+          for (int e = 0; e < 2; ++e) {
+            const int g = e * 64 + lane;
+            if (g < K - 1) emit(g, key[e]);
           }
         }
         if (lane == 0) {
@@ -477,12 +581,19 @@ hipError_t launch_match(const Launch& L, int mode, int terms, int grid, hipStrea
   if (L.total <= 0) return hipSuccess;
   const int g = xcd_grid(grid > 0 && grid < L.total ? grid : L.total);
   const size_t lds = match_lds_bytes(L.stride, L.window);
-  if (mode == HTS_MATCH_FP32)
-    hipLaunchKernelGGL((k_match<1, 1>), dim3(g), dim3(256), lds, s, L);
-  else if (terms == 1)
-    hipLaunchKernelGGL((k_match<0, 1>), dim3(g), dim3(256), lds, s, L);
-  else
-    hipLaunchKernelGGL((k_match<0, 3>), dim3(g), dim3(256), lds, s, L);
+  const MatchGeom G = match_geom(L.stride, L.window);
+  const bool cache = (G.ryc * (G.rxp / 16) + 3) / 4 <= MAXBW;
+#define HTS_KM(M, T)                                                                      \
+  if (cache) hipLaunchKernelGGL((k_match<M, T, 1>), dim3(g), dim3(256), lds, s, L);       \
+  else hipLaunchKernelGGL((k_match<M, T, 0>), dim3(g), dim3(256), lds, s, L);
+  if (mode == HTS_MATCH_FP32) {
+    HTS_KM(1, 1)
+  } else if (terms == 1) {
+    HTS_KM(0, 1)
+  } else {
+    HTS_KM(0, 3)
+  }
+#undef HTS_KM
   return hipGetLastError();
 }
 

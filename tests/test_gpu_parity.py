@@ -89,6 +89,32 @@ def test_match_forced_ties():
             np.testing.assert_array_equal(idx.cpu().numpy(), idx_o)
 
 
+def test_match_mixed_guide_planes_repeatable():
+    # RGB tiles whose references mix the green and the R+G+B guide are
+    # matched plane by plane; the references of the other plane must not
+    # enter a plane's shortlists.  Repeated runs (with other kernels, and
+    # their LDS contents, in between) agree with each other and the oracle.
+    rng = np.random.default_rng(11)
+    y = synth.tiny(12, 3, 70, 64, sigma=20.0, n_blobs=10)
+    # per 6x6 cell, make green dominant or not
+    for by in range(0, 70, 6):
+        for bx in range(0, 64, 6):
+            if rng.random() < 0.5:
+                y[0, by:by + 6, bx:bx + 6] *= 0.3
+                y[2, by:by + 6, bx:bx + 6] *= 0.3
+            else:
+                y[1, by:by + 6, bx:bx + 6] *= 0.3
+    p = P(stride=3, window=15, K=32)
+    idx_o, _, green_o = omatch.match(y, 8, p.stride, p.window, p.K)
+    assert 0.2 < green_o.mean() < 0.8
+    x = T(y)
+    for rep in range(3):
+        idx, _, green = api.hts_match(x, p, want_dist=True, want_green=True)
+        np.testing.assert_array_equal(green.cpu().numpy().astype(bool), green_o)
+        np.testing.assert_array_equal(idx.cpu().numpy(), idx_o)
+        api.hts_denoise(T(synth.tiny(rep, 3, 40, 40)), 10.0, P(stride=3, window=9, K=8))
+
+
 @pytest.mark.parametrize("mode", [0, 1], ids=["bf16", "fp32"])
 def test_match_gray256_full(mode):
     wl = synth.gray_256()

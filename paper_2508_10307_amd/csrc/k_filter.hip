@@ -100,7 +100,8 @@ __device__ inline int haar_row(int k, int K) {
   return (K >> L) + (k >> L);
 }
 
-template <int C, int SPL, int ADJ>
+// MASKS = 1 exports the keep-masks (when d.masks is set).
+template <int C, int SPL, int ADJ, int MASKS>
 __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
   extern __shared__ __align__(16) float fsm[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -266,13 +267,13 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
             for (int i = 0; i < 8; ++i) {
               const bool keep = fabsf(X[j][ch][i]) >= tau;
               if (!keep) X[j][ch][i] = 0.f;
-              if (d.masks) {
+              if (MASKS && d.masks) {
                 const unsigned long long bal = __ballot(keep);
                 const unsigned char byte = (unsigned char)((bal >> (8 * kl)) & 0xFFu);
                 if (i == a) mybyte = byte;
               }
             }
-            if (d.masks && active) ((unsigned char*)d.masks)[word * 8 + a] = mybyte;
+            if (MASKS && d.masks && active) ((unsigned char*)d.masks)[word * 8 + a] = mybyte;
           }
         }
       }
@@ -389,18 +390,18 @@ size_t filter_lds_bytes(int C, int K, int stride, int window, int ty, int tx) {
   return ((2 * C * RA * CA + 3) / 4 * 4 + 4 * TSCRATCH) * sizeof(float);
 }
 
-template <int C, int ADJ>
+template <int C, int ADJ, int MASKS>
 static hipError_t launch_filter_c(const Launch& L, int g, size_t lds, hipStream_t s) {
   switch (L.K) {
     case 2: case 4: case 8:
-      hipLaunchKernelGGL((k_filter<C, 1, ADJ>), dim3(g), dim3(256), lds, s, L); break;
+      hipLaunchKernelGGL((k_filter<C, 1, ADJ, MASKS>), dim3(g), dim3(256), lds, s, L); break;
     case 16:
-      hipLaunchKernelGGL((k_filter<C, 2, ADJ>), dim3(g), dim3(256), lds, s, L); break;
+      hipLaunchKernelGGL((k_filter<C, 2, ADJ, MASKS>), dim3(g), dim3(256), lds, s, L); break;
     case 32:
-      hipLaunchKernelGGL((k_filter<C, 4, ADJ>), dim3(g), dim3(256), lds, s, L); break;
+      hipLaunchKernelGGL((k_filter<C, 4, ADJ, MASKS>), dim3(g), dim3(256), lds, s, L); break;
     case 64:
       if constexpr (C == 1) {
-        hipLaunchKernelGGL((k_filter<C, 8, ADJ>), dim3(g), dim3(256), lds, s, L);
+        hipLaunchKernelGGL((k_filter<C, 8, ADJ, MASKS>), dim3(g), dim3(256), lds, s, L);
         break;
       } else {
         return hipErrorInvalidValue;
@@ -415,8 +416,13 @@ hipError_t launch_filter(const Launch& L, int ty, int tx, int adjoint, int grid,
   if (L.total <= 0) return hipSuccess;
   const int g = xcd_grid(grid > 0 && grid < L.total ? grid : L.total);
   const size_t lds = filter_lds_bytes(L.C, L.K, L.stride, L.window, ty, tx);
-  if (L.C == 1) return adjoint ? launch_filter_c<1, 1>(L, g, lds, s) : launch_filter_c<1, 0>(L, g, lds, s);
-  return adjoint ? launch_filter_c<3, 1>(L, g, lds, s) : launch_filter_c<3, 0>(L, g, lds, s);
+  const bool masks = !L.table && L.one.masks;   // batched launches never export masks
+  if (L.C == 1) {
+    if (adjoint) return launch_filter_c<1, 1, 0>(L, g, lds, s);
+    return masks ? launch_filter_c<1, 0, 1>(L, g, lds, s) : launch_filter_c<1, 0, 0>(L, g, lds, s);
+  }
+  if (adjoint) return launch_filter_c<3, 1, 0>(L, g, lds, s);
+  return masks ? launch_filter_c<3, 0, 1>(L, g, lds, s) : launch_filter_c<3, 0, 0>(L, g, lds, s);
 }
 
 // Stand-alone aggregation of precomputed group estimates (Eq. 2 numerator

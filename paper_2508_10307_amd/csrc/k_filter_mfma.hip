@@ -76,7 +76,9 @@ __device__ inline int haar_row_m(int k, int K) {
 // K = 32 keeps 96 coefficients, 32 basis operands and the four products'
 // operands per lane: it is built for one wavefront per SIMD (512 registers,
 // AGPRs included) rather than spill to scratch.
-template <int K, int ADJ>
+// MASKS = 1 exports the keep-masks (when d.masks is set); the variant
+// without the export keeps the ballots out of the register budget.
+template <int K, int ADJ, int MASKS>
 __global__ __launch_bounds__(256, K >= 32 ? 1 : 2) void k_filter_mfma(Launch L) {
   constexpr int C = 3;
   constexpr int NB = K / 2;            // blocks of two slots
@@ -271,7 +273,7 @@ __global__ __launch_bounds__(256, K >= 32 ? 1 : 2) void k_filter_mfma(Launch L) 
               S[b][c][e] = keep ? S[b][c][e] : 0.f;
               bal[e] = __ballot(keep);
             }
-            if (d.masks) {
+            if (MASKS && d.masks) {
               // word of slot 2b+ss: byte 2q'+e <- ballot bits [16q' + 8ss, +8)
 #pragma unroll
               for (int ss = 0; ss < 2; ++ss) {
@@ -286,7 +288,7 @@ __global__ __launch_bounds__(256, K >= 32 ? 1 : 2) void k_filter_mfma(Launch L) 
             }
           }
         }
-      if (!ADJ && d.masks) {
+      if (!ADJ && MASKS && d.masks) {
         wsync();
         unsigned long long* mw = (unsigned long long*)d.masks;
 #pragma unroll
@@ -437,10 +439,12 @@ hipError_t launch_filter_mfma(const Launch& L, int ty, int tx, int adjoint, int 
   if (L.total <= 0) return hipSuccess;
   const int g = xcd_grid(grid > 0 && grid < L.total ? grid : L.total);
   const size_t lds = filter_mfma_lds_bytes(L.stride, L.window, ty, tx);
-#define HTS_FM(KK)                                                                       \
-  case KK:                                                                               \
-    if (adjoint) hipLaunchKernelGGL((k_filter_mfma<KK, 1>), dim3(g), dim3(256), lds, s, L); \
-    else hipLaunchKernelGGL((k_filter_mfma<KK, 0>), dim3(g), dim3(256), lds, s, L);       \
+  const bool masks = !L.table && L.one.masks;   // batched launches never export masks
+#define HTS_FM(KK)                                                                          \
+  case KK:                                                                                  \
+    if (adjoint) hipLaunchKernelGGL((k_filter_mfma<KK, 1, 0>), dim3(g), dim3(256), lds, s, L); \
+    else if (masks) hipLaunchKernelGGL((k_filter_mfma<KK, 0, 1>), dim3(g), dim3(256), lds, s, L); \
+    else hipLaunchKernelGGL((k_filter_mfma<KK, 0, 0>), dim3(g), dim3(256), lds, s, L);       \
     break;
   switch (L.K) {
     HTS_FM(4)

@@ -695,7 +695,7 @@ hts_status hts_autotune(const hts_params* p, int32_t C, int32_t H, int32_t W,
   HIPCHK(hipEventCreate(&e1));
   auto time_it = [&](auto&& fn) -> float {
     float best = 1e30f;
-    for (int rep = 0; rep < 3; ++rep) {
+    for (int rep = 0; rep < 5; ++rep) {
       if (hipEventRecord(e0, s) != hipSuccess) return 1e30f;
       if (fn() != HTS_OK) return 1e30f;
       if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return 1e30f;

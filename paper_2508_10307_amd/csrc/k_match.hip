@@ -161,21 +161,21 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
         const int nseg = (RYc + 7) >> 3;
         for (int task = tid; task < RXP * nseg; task += 256) {
           const int cx = task % RXP, c0 = (task / RXP) * 8;
-          long long rs[15];
+          double rs[15];   // exact: |v| < 2^22, sums < 2^50
 #pragma unroll
           for (int j = 0; j < 15; ++j) {
             const int y = c0 + j;
-            long long a = 0;
+            double a = 0.0;
             if (y < rows) {
 #pragma unroll
               for (int b = 0; b < PS; ++b) {
-                long long v = gi[y * pitch + cx + b];
-                a += v * v;
+                const double v = (double)gi[y * pitch + cx + b];
+                a = fma(v, v, a);
               }
             }
             rs[j] = a;
           }
-          long long nn = 0;
+          double nn = 0.0;
 #pragma unroll
           for (int j = 0; j < 8; ++j) nn += rs[j];
 #pragma unroll
@@ -194,11 +194,11 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
         const int* ri = rinfo + tid * 8;
         float na = 0.f;
         if (ri[0] & (1 << p)) {
-          long long a = 0;
+          double a = 0.0;   // exact, as above
           for (int py = 0; py < PS; ++py)
             for (int px = 0; px < PS; ++px) {
-              long long v = gi[(ri[1] + py) * pitch + ri[2] + px];
-              a += v * v;
+              const double v = (double)gi[(ri[1] + py) * pitch + ri[2] + px];
+              a = fma(v, v, a);
             }
           na = (float)a;
         }
@@ -368,16 +368,23 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
       __syncthreads();
 
       // ---- threshold T per reference: (K-1)-th smallest of its 128 list values ----
+      // The values are non-negative floats (or +inf), ordered as their bit
+      // patterns, which lie below 2^31.  T is the largest pattern t with
+      // #{values < t} <= K-2, i.e. the (K-1)-th smallest value; it is built
+      // bit by bit from the top, counting with ballots.
       for (int t = wv; t < 16; t += 4) {
         if (!((rinfo[t * 8] >> p) & 1)) continue;
-        unsigned long long v[2];
-#pragma unroll
-        for (int e = 0; e < 2; ++e) v[e] = __float_as_uint(tl[t * 128 + e * 64 + lane]);
-        wave_sort_u64<2>(v);
+        const unsigned v0 = __float_as_uint(tl[t * 128 + lane]);
+        const unsigned v1 = __float_as_uint(tl[t * 128 + 64 + lane]);
         const int g = K - 2;
-        const unsigned long long sel = __shfl(g >= 64 ? v[1] : v[0], g & 63, 64);
+        unsigned pre = 0;
+        for (int bit = 30; bit >= 0; --bit) {
+          const unsigned cand = pre | (1u << bit);
+          const int c = __popcll(__ballot(v0 < cand)) + __popcll(__ballot(v1 < cand));
+          pre = c <= g ? cand : pre;
+        }
         if (lane == 0) {
-          Tp[t] = __uint_as_float((unsigned)sel);
+          Tp[t] = __uint_as_float(pre);
           scount[t] = 0;
         }
       }
@@ -441,7 +448,7 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
         const int* ri = rinfo + t * 8;
         if (!((ri[0] >> p) & 1)) continue;
         const int ref = ri[7];
-        const int nsl = scount[t];
+        const int nsl = __builtin_amdgcn_readfirstlane(scount[t]);
         if (nsl > SHORT_CAP || nsl < K - 1) {
           if (lane == 0) d.fb_list[atomicAdd(d.fb_count, 1)] = ref;
           continue;
@@ -485,22 +492,33 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
           d.idx[(size_t)ref * K + 1 + g] = cy * d.W + cx;
           if (d.dist) d.dist[(size_t)ref * K + 1 + g] = (long long)(key >> 12);
         };
+        // Keys (distance << 12 | window index) are distinct: the rank of a
+        // key among the nsl keys is its slot (minus one); ranks are counted
+        // against every key, broadcast one by one.
+        auto bcast = [&](unsigned long long v, int src) __attribute__((always_inline)) {
+          const unsigned lo = __builtin_amdgcn_readlane((unsigned)v, src);
+          const unsigned hi = __builtin_amdgcn_readlane((unsigned)(v >> 32), src);
+          return ((unsigned long long)hi << 32) | lo;
+        };
         if (nsl <= 64) {
           unsigned long long key[1];
           const int j[1] = {lane};
           exact_keys(key, j);
-          wave_sort_u64<1>(key);
-          if (lane < K - 1) emit(lane, key[0]);
+          int rank = 0;
+          for (int o = 0; o < nsl; ++o) rank += bcast(key[0], o) < key[0] ? 1 : 0;
+          if (lane < nsl && rank < K - 1) emit(rank, key[0]);
         } else {
           unsigned long long key[2];
           const int j[2] = {lane, 64 + lane};
           exact_keys(key, j);
-          wave_sort_u64<2>(key);
-#pragma unroll
-          for (int e = 0; e < 2; ++e) {
-            const int g = e * 64 + lane;
-            if (g < K - 1) emit(g, key[e]);
+          int rank0 = 0, rank1 = 0;
+          for (int o = 0; o < nsl; ++o) {
+            const unsigned long long ko = bcast(o < 64 ? key[0] : key[1], o & 63);
+            rank0 += ko < key[0] ? 1 : 0;
+            rank1 += ko < key[1] ? 1 : 0;
           }
+          if (rank0 < K - 1) emit(rank0, key[0]);
+          if (64 + lane < nsl && rank1 < K - 1) emit(rank1, key[1]);
         }
         if (lane == 0) {
           d.idx[(size_t)ref * K] = (Y0 + py0) * d.W + X0 + px0;

@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--batch-api", type=int, default=1,
                     help="1: hts_denoise_batch (one graph); 0: one hts_denoise per image")
     ap.add_argument("--tune", type=int, default=0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device to device three times and exit (the "
+                         "known-size kernel that calibrates the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -49,15 +52,58 @@ def workload(name):
 
 
 def filter_flops_per_group(C, K):
-    # dense t-SVD projection MACs per patch and direction: c=1: U^T P V = 2 x 512;
-    # c=3: f=0 real (2 x 512) + f=1 complex (2 x 4 x 512) = 5120; forward + inverse.
-    macs = 1024 if C == 1 else 5120
-    return K * 2 * 2 * macs
+    """Algorithmic flops of Eq. 18-20 for one group, computed per group
+    ("direct" form): K * 2 * T (forward and inverse projection of every slot,
+    T = 2048 flops for c = 1, 11776 for c = 3: the real f = 0 pair, the complex
+    f = 1 pair and the 3-point DFT / IDFT) + 2 * 2K c 64 (Haar and its inverse,
+    fast form) + 2 K c 64 (threshold and accumulation)."""
+    T = 2048 if C == 1 else 11776
+    return K * 2 * T + 2 * 2 * K * C * 64 + 2 * K * C * 64
+
+
+def filter_flops_reorg(C, K, H, W, n_ref):
+    """The same result with the linear projection done once per valid patch
+    position instead of once per slot (the least work any realisation needs)."""
+    T = 2048 if C == 1 else 11776
+    return (H - 7) * (W - 7) * 2 * T + n_ref * (2 * 2 * K * C * 64 + 2 * K * C * 64)
+
+
+def kernel_name(C, K, valu):
+    """rocprofv3 name of the single-image (eager) forward filter launch."""
+    if valu:
+        spl = {2: 1, 4: 1, 8: 1, 16: 2, 32: 4, 64: 8}[K]
+        return f"void hts::k_filter<{C}, {spl}, 0, 0, 0>(hts::Launch)"
+    return f"void hts::k_filter_mfma<{K}, 0, 0, 0>(hts::Launch)"
+
+
+# HBM traffic of the filter launches timed for the roofline, from two
+# rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE; KiB per
+# dispatch, averaged over the 64 eager launches) scaled by the factor the same
+# counters give for a plain device copy of known size.  Valid only for the
+# kernel sources they were taken on (SHA-256 over the files below).
+TRAFFIC_SOURCES = ["paper_2508_10307_amd/csrc/k_filter.hip",
+                   "paper_2508_10307_amd/csrc/k_filter_mfma.hip",
+                   "paper_2508_10307_amd/csrc/hts_device.h",
+                   "paper_2508_10307_amd/csrc/hts_internal.h"]
+TRAFFIC = {    # kernel name -> (sources sha256, bytes per launch)
+    "void hts::k_filter<3, 4, 0, 0, 0>(hts::Launch)":
+        ("7ed8a689e31fa7b694b8cace5503a8fe09e9b4330533135d742f608ba832ed05", 86963232),
+}
+
+
+def sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def cpu_baseline(wl_name):
-    """Oracle (plain FP64 NumPy) on a bounded sample: the first 256x256 crop
-    of the workload's first image, in a single-threaded child process."""
+    """Oracle (plain FP64 NumPy) on a bounded sample: the top-left crop of at
+    most 384x384 pixels of the workload's first image (about 10-15 s of CPU
+    work), in a single-threaded child process."""
     code = r"""
 import os, sys, time, json
 sys.path.insert(0, %r)
@@ -67,11 +113,11 @@ from oracle import pipeline
 wl = {"batch64": synth.batch64, "rgb512": synth.rgb_512_pg, "gray256": synth.gray_256,
       "large24": synth.large_24mpix}[%r]()
 im, q = wl.images[0], wl.params
-y = np.ascontiguousarray(im.noisy[:, :256, :256])
+y = np.ascontiguousarray(im.noisy[:, :384, :384])
 t = time.perf_counter()
 pipeline.denoise(y, im.sigma, q.ps, q.stride, q.window, q.K, q.tau_mult)
 dt = time.perf_counter() - t
-print(json.dumps({"sec": dt, "mpix": y.shape[1] * y.shape[2] / 1e6}))
+print(json.dumps({"sec": dt, "mpix": y.shape[1] * y.shape[2] / 1e6, "h": y.shape[1], "w": y.shape[2]}))
 """ % (ROOT, wl_name)
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
@@ -80,17 +126,27 @@ print(json.dumps({"sec": dt, "mpix": y.shape[1] * y.shape[2] / 1e6}))
         return {"error": r.stderr[-400:]}
     d = json.loads(r.stdout.strip().splitlines()[-1])
     return {"value": d["mpix"] / d["sec"], "unit": "MPix/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle denoise of one 256x256 crop of image 0 ({d['sec']:.1f} s)"}
+            "sample": f"oracle denoise of the {d['h']}x{d['w']} top-left crop of image 0 "
+                      f"({d['sec']:.1f} s, one thread)"}
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "sharding is a design in DESIGN.md, not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); sharding over "
+              "several GPUs is designed but not built", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        a = torch.rand(args.copy_calibration * 256 * 1024, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 4, "copies": 3}), flush=True)
+        return
 
     from paper_2508_10307_amd import _lib as L
     from paper_2508_10307_amd import api
@@ -178,12 +234,18 @@ def main():
                 "outputs_bitwise_equal": same, "speedup_bf16_vs_fp32": ms32 / ms}
 
     # ---- roofline of the dominant kernel: the fused filter, timed live ----
+    # One eager launch per image (the same filter the batched graph runs, as
+    # its single-image instantiation), timed with HIP events on its stream:
+    # hts_filter without num/cnt runs the Fourier-slice kernel (a few us) and
+    # the filter, which adds into the workspace.  The per-image matches are
+    # timed alongside for the stage ratio.
     p = params(L.HTS_MATCH_BF16)
     pc = p.c()
+    p32 = params(L.HTS_MATCH_FP32).c()
     lib = L.load()
     stream_h = torch.cuda.current_stream(dev)
     sh = ctypes.c_void_p(stream_h.cuda_stream)
-    ftime, fgroups, mtime = 0.0, 0, 0.0
+    ftime, fflops, freorg, mtime, mtime32 = 0.0, 0.0, 0.0, 0.0, 0.0
     for x, s in zip(xs, sig):
         Cx, H, W = x.shape
         ws = api.workspace(p, Cx, H, W, dev)
@@ -191,40 +253,49 @@ def main():
         idx = torch.empty((ny * nx, p.K), dtype=torch.int32, device=dev)
         U = torch.empty((Cx, 8, 8), device=dev)
         V = torch.empty_like(U)
-        num = torch.zeros_like(x)
-        cnt = torch.zeros((H, W), device=dev)
-        ea, eb, ec = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-        ea.record(stream_h)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        ev[0].record(stream_h)
+        L.check("hts_match", lib.hts_match(ctypes.byref(p32), ctypes.c_void_p(x.data_ptr()), Cx, H, W,
+                                           ctypes.c_void_p(idx.data_ptr()), None, None,
+                                           ctypes.c_void_p(ws.data_ptr()), ws.numel(), sh))
+        ev[1].record(stream_h)
+        ev[2].record(stream_h)
         L.check("hts_match", lib.hts_match(ctypes.byref(pc), ctypes.c_void_p(x.data_ptr()), Cx, H, W,
                                            ctypes.c_void_p(idx.data_ptr()), None, None,
                                            ctypes.c_void_p(ws.data_ptr()), ws.numel(), sh))
-        eb.record(stream_h)
+        ev[3].record(stream_h)
         L.check("hts_basis", lib.hts_basis(ctypes.byref(pc), ctypes.c_void_p(x.data_ptr()), Cx, H, W,
                                            ctypes.c_void_p(U.data_ptr()), ctypes.c_void_p(V.data_ptr()),
                                            None, None, None, ctypes.c_void_p(ws.data_ptr()),
                                            ws.numel(), sh))
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream_h)
+        ev[4].record(stream_h)
         L.check("hts_filter", lib.hts_filter(
             ctypes.byref(pc), ctypes.c_void_p(x.data_ptr()), Cx, H, W, float(s),
             ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(U.data_ptr()),
-            ctypes.c_void_p(V.data_ptr()), 0, ny * nx, ctypes.c_void_p(num.data_ptr()),
-            ctypes.c_void_p(cnt.data_ptr()), None, None, ctypes.c_void_p(ws.data_ptr()),
-            ws.numel(), sh))
-        e1.record(stream_h)
+            ctypes.c_void_p(V.data_ptr()), 0, ny * nx, None, None, None, None,
+            ctypes.c_void_p(ws.data_ptr()), ws.numel(), sh))
+        ev[5].record(stream_h)
         torch.cuda.synchronize()
-        ftime += e0.elapsed_time(e1)
-        mtime += ea.elapsed_time(eb)
-        fgroups += ny * nx
+        mtime32 += ev[0].elapsed_time(ev[1])
+        mtime += ev[2].elapsed_time(ev[3])
+        ftime += ev[4].elapsed_time(ev[5])
+        fflops += ny * nx * filter_flops_per_group(Cx, q.K)
+        freorg += filter_flops_reorg(Cx, q.K, H, W, ny * nx)
     n_launch = len(xs)
     avg_ms = ftime / n_launch
-    flops_launch = fgroups * filter_flops_per_group(C, q.K) / n_launch
+    flops_launch = fflops / n_launch
     achieved = flops_launch / (avg_ms / 1e3) / 1e12
-    roof = {"kernel": "k_filter (fused t-SVD/Haar/threshold/inverse/aggregate)",
-            "bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_FP32_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-            "traffic": None, "avg_launch_ms": round(avg_ms, 4),
-            "flops_per_launch": flops_launch, "launches": n_launch}
+    valu = ((tune >> 6) & 3) == 1 or C != 3 or q.K not in (4, 8, 16, 32)
+    kname = kernel_name(C, q.K, valu)
+    traffic = None
+    if kname in TRAFFIC and TRAFFIC[kname][0] == sources_sha():
+        traffic = TRAFFIC[kname][1]
+    roof = {"kernel": kname, "bound": "alu", "achieved": round(achieved, 2),
+            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
+            "avg_launch_ms": round(avg_ms, 4), "flops_per_launch": flops_launch,
+            "flops_model": "Eq. 18-20 per group (direct)", "launches": n_launch,
+            "achieved_reorg_equiv": round(freorg / n_launch / (avg_ms / 1e3) / 1e12, 2)}
 
     hbm_bytes = sum(2 * x.numel() * 4 for x in xs)    # read y + write x_hat (algorithmic)
     line = {
@@ -240,7 +311,9 @@ def main():
         "psnr_db": round(psnr_bf16, 4),
         "hbm_gbps": round(hbm_bytes / (ms / 1e3) / 1e9, 2),
         "fp32_path": fp32,
-        "stage_ms": {"match_bf16_sum": round(mtime, 3), "filter_sum": round(ftime, 3)},
+        "stage_ms": {"match_bf16_sum": round(mtime, 3), "match_fp32_sum": round(mtime32, 3),
+                     "match_stage_speedup_bf16_vs_fp32": round(mtime32 / mtime, 3),
+                     "filter_sum": round(ftime, 3)},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

@@ -220,9 +220,10 @@ hts_status run_count(const hts_params* p, int C, const Schedule& sc, const ImgDe
   return HTS_OK;
 }
 
+// U, V (nullable): a caller's basis to use instead of the workspace copy.
 hts_status run_filter(const hts_params* p, int C, const Schedule& sc, ImgDesc d, int adjoint,
-                      hipStream_t s) {
-  HIPCHK(launch_fbasis(make_launch(p, C, d, -1, sc.fty, sc.ftx), s));
+                      hipStream_t s, const float* U = nullptr, const float* V = nullptr) {
+  HIPCHK(launch_fbasis(make_launch(p, C, d, -1, sc.fty, sc.ftx), U, V, s));
   const Launch L = make_launch(p, C, d, W_FILT, sc.fty, sc.ftx);
   if (sc.valu) HIPCHK(launch_filter(L, sc.fty, sc.ftx, adjoint, 0, s));
   else HIPCHK(launch_filter_mfma(L, sc.fty, sc.ftx, adjoint, 0, s));
@@ -359,7 +360,7 @@ hts_status enqueue_batch(const hts_params* p, int C, const BatchPlan& plan, cons
   HIPCHK(launch_match_fallback(LK(-1), cus, s));
   HIPCHK(launch_cov(LK(W_COV), cus * 4, s));
   HIPCHK(launch_eig(LK(-1), s));
-  HIPCHK(launch_fbasis(LK(-1), s));
+  HIPCHK(launch_fbasis(LK(-1), nullptr, nullptr, s));
   HIPCHK(launch_zero_accum(LK(W_PIX), cus * 8, s));
   HIPCHK(launch_count_hist(LK(W_REF), cus * 8, s));
   HIPCHK(launch_count_box(LK(W_BOX), cus * 8, s));
@@ -504,11 +505,13 @@ hts_status hts_filter(const hts_params* p, const float* noisy, int32_t C, int32_
   d.masks = masks;
   d.num64 = nullptr;      // estimates go to a float numerator (the caller's or scratch)
   d.poison = nullptr;
-  if (num) { d.num = num; d.cnt = cnt; }
-  const size_t nb = (size_t)C * 64;
-  HIPCHK(hipMemcpyAsync(d.basis, U, nb * 4, hipMemcpyDeviceToDevice, s));
-  HIPCHK(hipMemcpyAsync(d.basis + nb, V, nb * 4, hipMemcpyDeviceToDevice, s));
-  return run_filter(p, C, sc, d, 0, s);
+  if (num) {
+    d.num = num;
+    d.cnt = cnt;
+  } else {
+    d.cnt = nullptr;      // no numerator asked for: no coverage counts either
+  }
+  return run_filter(p, C, sc, d, 0, s, U, V);
 }
 
 hts_status hts_aggregate(const hts_params* p, const float* group_est, const int32_t* idx,
@@ -591,10 +594,7 @@ hts_status hts_denoise_backward(const hts_params* p, const float* grad_out, cons
   a.idx = const_cast<int32_t*>(idx);
   a.masks_in = masks;
   HIPCHK(launch_zero_accum(make_launch(p, C, a, W_PIX, sc.fty, sc.ftx), 0, s));
-  const size_t nb = (size_t)C * 64;
-  HIPCHK(hipMemcpyAsync(a.basis, U, nb * 4, hipMemcpyDeviceToDevice, s));
-  HIPCHK(hipMemcpyAsync(a.basis + nb, V, nb * 4, hipMemcpyDeviceToDevice, s));
-  st = run_filter(p, C, sc, a, 1, s);
+  st = run_filter(p, C, sc, a, 1, s, U, V);
   if (st != HTS_OK) return st;
   a.out = grad_in;             // grad_in = numerator (no division)
   HIPCHK(launch_finalize(make_launch(p, C, a, W_PIX, sc.fty, sc.ftx), 0, s));

@@ -44,6 +44,30 @@ __device__ __forceinline__ void for_each_item(const Launch& L, F&& body) {
   }
 }
 
+// Same, with the single-image / batched choice made at compile time
+// (BATCH = 1: the launch has a descriptor table).
+template <int KIND, int BATCH, typename F>
+__device__ __forceinline__ void for_each_item_t(const Launch& L, F&& body) {
+  const int G = gridDim.x, T = L.total;
+  int start = blockIdx.x, step = G, end = T;
+  if (G >= 8 && (G & 7) == 0) {
+    const int chunk = (T + 7) >> 3;
+    const int x = blockIdx.x & 7;
+    start = x * chunk + (blockIdx.x >> 3);
+    step = G >> 3;
+    end = min(T, (x + 1) * chunk);
+  }
+  for (int w = start; w < end; w += step) {
+    if constexpr (BATCH) {
+      int i = find_image(L, KIND, w);
+      const ImgDesc d = L.table[i];
+      body(d, w - d.woff[KIND]);
+    } else {
+      body(L.one, w);
+    }
+  }
+}
+
 // Reference coordinate along one axis: 0, s, 2s, ... clamped to the last
 // valid position (the clamp realises the extra last reference).
 __device__ inline int ref_coord(int i, int s, int n_valid) { return min(i * s, n_valid - 1); }

@@ -126,7 +126,7 @@ hipError_t launch_match_fallback(const Launch& L, int grid, hipStream_t s);
 hipError_t launch_reset_counters(const Launch& L, hipStream_t s);
 hipError_t launch_cov(const Launch& L, int grid, hipStream_t s);
 hipError_t launch_eig(const Launch& L, hipStream_t s);
-hipError_t launch_fbasis(const Launch& L, hipStream_t s);
+hipError_t launch_fbasis(const Launch& L, const float* U, const float* V, hipStream_t s);
 hipError_t launch_zero_accum(const Launch& L, int grid, hipStream_t s);
 hipError_t launch_filter(const Launch& L, int shape_ty, int shape_tx, int adjoint, int grid,
                          hipStream_t s);

@@ -241,13 +241,16 @@ __global__ __launch_bounds__(256) void k_eig(Launch L) {
 
 // Fourier slices (float) of the real basis tensors for the filter:
 // U_F(f) = sum_j U(:,:,j) exp(-2 pi i f j / c), evaluated in FP64.
-__global__ void k_fbasis(Launch L) {
+// U_ext / V_ext (single-image launches, nullable) replace the image's own
+// basis as the source.
+__global__ void k_fbasis(Launch L, const float* U_ext, const float* V_ext) {
   const int nimg = L.table ? L.n_img : 1;
   for (int im = blockIdx.x; im < nimg; im += gridDim.x) {
     const ImgDesc d = L.table ? L.table[im] : L.one;
     for (int e = threadIdx.x; e < 128; e += blockDim.x) {
       const int uv = e >> 6, ab = e & 63;
-      const float* T = d.basis + uv * L.C * 64;
+      const float* ext = uv ? V_ext : U_ext;
+      const float* T = ext ? ext : d.basis + uv * L.C * 64;
       if (L.C == 1) {
         d.fbasis[(uv ? FB_V0 : FB_U0) + ab] = T[ab];
       } else {
@@ -271,9 +274,9 @@ hipError_t launch_eig(const Launch& L, hipStream_t s) {
   hipLaunchKernelGGL(k_eig, dim3(n), dim3(256), 0, s, L);
   return hipGetLastError();
 }
-hipError_t launch_fbasis(const Launch& L, hipStream_t s) {
+hipError_t launch_fbasis(const Launch& L, const float* U, const float* V, hipStream_t s) {
   const int n = L.table ? L.n_img : 1;
-  hipLaunchKernelGGL(k_fbasis, dim3(n), dim3(128), 0, s, L);
+  hipLaunchKernelGGL(k_fbasis, dim3(n), dim3(128), 0, s, L, U, V);
   return hipGetLastError();
 }
 

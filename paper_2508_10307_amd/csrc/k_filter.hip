@@ -101,7 +101,7 @@ __device__ inline int haar_row(int k, int K) {
 }
 
 // MASKS = 1 exports the keep-masks (when d.masks is set).
-template <int C, int SPL, int ADJ, int MASKS>
+template <int C, int SPL, int ADJ, int MASKS, int BATCH>
 __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
   extern __shared__ __align__(16) float fsm[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
   unsigned long long* acc = (unsigned long long*)fsm;          // [NP][RA][CA] fixed point
   float* T = fsm + (2 * NP * RA * CA + 3) / 4 * 4 + wave * TSCRATCH;   // transpose scratch
 
-  for_each_item<W_FILT>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
+  for_each_item_t<W_FILT, BATCH>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
     const int ntx = (d.nrx + TX - 1) / TX;
     const int iy0 = (item / ntx) * TY, ix0 = (item % ntx) * TX;
     const int iy1 = min(d.nry, iy0 + TY) - 1, ix1 = min(d.nrx, ix0 + TX) - 1;
@@ -390,18 +390,18 @@ size_t filter_lds_bytes(int C, int K, int stride, int window, int ty, int tx) {
   return ((2 * C * RA * CA + 3) / 4 * 4 + 4 * TSCRATCH) * sizeof(float);
 }
 
-template <int C, int ADJ, int MASKS>
+template <int C, int ADJ, int MASKS, int BATCH>
 static hipError_t launch_filter_c(const Launch& L, int g, size_t lds, hipStream_t s) {
   switch (L.K) {
     case 2: case 4: case 8:
-      hipLaunchKernelGGL((k_filter<C, 1, ADJ, MASKS>), dim3(g), dim3(256), lds, s, L); break;
+      hipLaunchKernelGGL((k_filter<C, 1, ADJ, MASKS, BATCH>), dim3(g), dim3(256), lds, s, L); break;
     case 16:
-      hipLaunchKernelGGL((k_filter<C, 2, ADJ, MASKS>), dim3(g), dim3(256), lds, s, L); break;
+      hipLaunchKernelGGL((k_filter<C, 2, ADJ, MASKS, BATCH>), dim3(g), dim3(256), lds, s, L); break;
     case 32:
-      hipLaunchKernelGGL((k_filter<C, 4, ADJ, MASKS>), dim3(g), dim3(256), lds, s, L); break;
+      hipLaunchKernelGGL((k_filter<C, 4, ADJ, MASKS, BATCH>), dim3(g), dim3(256), lds, s, L); break;
     case 64:
       if constexpr (C == 1) {
-        hipLaunchKernelGGL((k_filter<C, 8, ADJ, MASKS>), dim3(g), dim3(256), lds, s, L);
+        hipLaunchKernelGGL((k_filter<C, 8, ADJ, MASKS, BATCH>), dim3(g), dim3(256), lds, s, L);
         break;
       } else {
         return hipErrorInvalidValue;
@@ -416,13 +416,18 @@ hipError_t launch_filter(const Launch& L, int ty, int tx, int adjoint, int grid,
   if (L.total <= 0) return hipSuccess;
   const int g = xcd_grid(grid > 0 && grid < L.total ? grid : L.total);
   const size_t lds = filter_lds_bytes(L.C, L.K, L.stride, L.window, ty, tx);
-  const bool masks = !L.table && L.one.masks;   // batched launches never export masks
+  // batched launches (descriptor table) never export masks nor run the adjoint
+  const bool batch = L.table != nullptr;
+  if (batch && adjoint) return hipErrorInvalidValue;
+  const bool masks = !batch && L.one.masks;
   if (L.C == 1) {
-    if (adjoint) return launch_filter_c<1, 1, 0>(L, g, lds, s);
-    return masks ? launch_filter_c<1, 0, 1>(L, g, lds, s) : launch_filter_c<1, 0, 0>(L, g, lds, s);
+    if (batch) return launch_filter_c<1, 0, 0, 1>(L, g, lds, s);
+    if (adjoint) return launch_filter_c<1, 1, 0, 0>(L, g, lds, s);
+    return masks ? launch_filter_c<1, 0, 1, 0>(L, g, lds, s) : launch_filter_c<1, 0, 0, 0>(L, g, lds, s);
   }
-  if (adjoint) return launch_filter_c<3, 1, 0>(L, g, lds, s);
-  return masks ? launch_filter_c<3, 0, 1>(L, g, lds, s) : launch_filter_c<3, 0, 0>(L, g, lds, s);
+  if (batch) return launch_filter_c<3, 0, 0, 1>(L, g, lds, s);
+  if (adjoint) return launch_filter_c<3, 1, 0, 0>(L, g, lds, s);
+  return masks ? launch_filter_c<3, 0, 1, 0>(L, g, lds, s) : launch_filter_c<3, 0, 0, 0>(L, g, lds, s);
 }
 
 // Stand-alone aggregation of precomputed group estimates (Eq. 2 numerator

@@ -78,7 +78,7 @@ __device__ inline int haar_row_m(int k, int K) {
 // AGPRs included) rather than spill to scratch.
 // MASKS = 1 exports the keep-masks (when d.masks is set); the variant
 // without the export keeps the ballots out of the register budget.
-template <int K, int ADJ, int MASKS>
+template <int K, int ADJ, int MASKS, int BATCH>
 __global__ __launch_bounds__(256, K >= 32 ? 1 : 2) void k_filter_mfma(Launch L) {
   constexpr int C = 3;
   constexpr int NB = K / 2;            // blocks of two slots
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256, K >= 32 ? 1 : 2) void k_filter_mfma(Launch L) 
   const bool swap40 = ((lane >> 5) & 1) != ((lane >> 3) & 1);
   const bool upper32 = lane >= 32;
 
-  for_each_item<W_FILT>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
+  for_each_item_t<W_FILT, BATCH>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
     const int ntx = (d.nrx + TX - 1) / TX;
     const int iy0 = (item / ntx) * TY, ix0 = (item % ntx) * TX;
     const int iy1 = min(d.nry, iy0 + TY) - 1, ix1 = min(d.nrx, ix0 + TX) - 1;
@@ -439,12 +439,16 @@ hipError_t launch_filter_mfma(const Launch& L, int ty, int tx, int adjoint, int 
   if (L.total <= 0) return hipSuccess;
   const int g = xcd_grid(grid > 0 && grid < L.total ? grid : L.total);
   const size_t lds = filter_mfma_lds_bytes(L.stride, L.window, ty, tx);
-  const bool masks = !L.table && L.one.masks;   // batched launches never export masks
-#define HTS_FM(KK)                                                                          \
-  case KK:                                                                                  \
-    if (adjoint) hipLaunchKernelGGL((k_filter_mfma<KK, 1, 0>), dim3(g), dim3(256), lds, s, L); \
-    else if (masks) hipLaunchKernelGGL((k_filter_mfma<KK, 0, 1>), dim3(g), dim3(256), lds, s, L); \
-    else hipLaunchKernelGGL((k_filter_mfma<KK, 0, 0>), dim3(g), dim3(256), lds, s, L);       \
+  // batched launches (descriptor table) never export masks nor run the adjoint
+  const bool batch = L.table != nullptr;
+  if (batch && adjoint) return hipErrorInvalidValue;
+  const bool masks = !batch && L.one.masks;
+#define HTS_FM(KK)                                                                             \
+  case KK:                                                                                     \
+    if (batch) hipLaunchKernelGGL((k_filter_mfma<KK, 0, 0, 1>), dim3(g), dim3(256), lds, s, L);   \
+    else if (adjoint) hipLaunchKernelGGL((k_filter_mfma<KK, 1, 0, 0>), dim3(g), dim3(256), lds, s, L); \
+    else if (masks) hipLaunchKernelGGL((k_filter_mfma<KK, 0, 1, 0>), dim3(g), dim3(256), lds, s, L); \
+    else hipLaunchKernelGGL((k_filter_mfma<KK, 0, 0, 0>), dim3(g), dim3(256), lds, s, L);      \
     break;
   switch (L.K) {
     HTS_FM(4)

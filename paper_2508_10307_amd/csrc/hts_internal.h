@@ -16,7 +16,7 @@ constexpr int MAX_WINDOW = 63;         // window-relative candidate index fits 1
 constexpr int MATCH_TY = 4;            // match tile: 4 x 4 references
 constexpr int MATCH_TX = 4;
 constexpr int SHORT_CAP = 128;         // certified shortlist capacity per reference
-constexpr int COV_REFS = 64;           // references per covariance partial block
+constexpr int COV_REFS = 256;          // references per covariance partial block
 constexpr int PIX_CHUNK = 2048;        // pixels per work item of the element-wise stages
 
 // Work kinds: each image contributes a number of work items of each kind;

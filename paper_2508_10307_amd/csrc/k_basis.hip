@@ -13,7 +13,7 @@
 
 namespace hts {
 
-constexpr int COV_SUB = 16;   // references staged in LDS at a time
+typedef double d4 __attribute__((ext_vector_type(4)));
 
 __device__ inline void dft3(double p0, double p1, double p2, double& f0, double& f1r, double& f1i) {
   // P^(0) = p0 + p1 + p2;  P^(1) = p0 + w p1 + w^2 p2, w = exp(-2 pi i / 3)
@@ -25,74 +25,82 @@ __device__ inline void dft3(double p0, double p1, double p2, double& f0, double&
 // Partial covariances of the references [item*COV_REFS, ...): layout per
 // item: C_U(0)[8][8], C_V(0)[8][8], then for c = 3 C_U(1), C_V(1) as
 // interleaved (re, im) [8][8][2].
+//
+// Every covariance is a Gram matrix summed over the references, computed
+// on FP64 MFMA (v_mfma_f64_16x16x4f64: lane l holds A(l%16, l/16) and
+// B(l/16, l%16); D(l/16 + 4v, l%16) in register v).  With one 16 x 8
+// operand Z per reference, Z Z^T needs Z both as A and as B^T, which is the
+// same register, two k-steps of 4 columns:
+//   C_U(1): Z = [Re P^(1); Im P^(1)]   -> Re = G11 + G22, Im = G21 - G12;
+//   C_V(1): Z = [Re P^(1)^T; Im P^(1)^T] -> Re = G11 + G22, Im = G12 - G21;
+//   C_U(0), C_V(0): Z = [P^(0); P^(0)] (resp. transposed) -> C = G11,
+// where Gxy are the 8 x 8 blocks of G = Z Z^T.  Each wavefront takes every
+// fourth reference of the item; the four partial Grams are added in LDS in
+// wavefront order.
 __global__ __launch_bounds__(256) void k_cov(Launch L) {
-  __shared__ double X0[COV_SUB][64];
-  __shared__ double X1r[COV_SUB][64];
-  __shared__ double X1i[COV_SUB][64];
-  const int tid = threadIdx.x;
+  __shared__ double red[4][4][4][64];   // [wavefront][gram][register][lane]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r16 = lane & 15, kq = lane >> 4, rr = r16 & 7;
+  const bool upper = r16 >= 8;          // rows 8..15 of Z
   const int nel = cov_elems(L.C);
   for_each_item<W_COV>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
     const int HW = d.H * d.W;
-    double acc[2] = {0.0, 0.0};  // elements tid and tid + 256
+    d4 gu1 = {0.0, 0.0, 0.0, 0.0}, gv1 = gu1, gu0 = gu1, gv0 = gu1;
     const int r_begin = item * COV_REFS;
     const int r_end = min(d.n_ref, r_begin + COV_REFS);
-    for (int r0 = r_begin; r0 < r_end; r0 += COV_SUB) {
-      const int nsub = min(COV_SUB, r_end - r0);
-      __syncthreads();
-      for (int e = tid; e < nsub * 64; e += 256) {
-        const int i = e >> 6, px = e & 63;
-        const int ref = r0 + i;
-        const int ry = ref_coord(ref / d.nrx, L.stride, d.Hp);
-        const int rx = ref_coord(ref % d.nrx, L.stride, d.Wp);
-        const int off = (ry + (px >> 3)) * d.W + rx + (px & 7);
+    for (int ref = r_begin + wave; ref < r_end; ref += 4) {
+      const int iy = ref / d.nrx;
+      const int ry = ref_coord(iy, L.stride, d.Hp);
+      const int rx = ref_coord(ref - iy * d.nrx, L.stride, d.Wp);
+      const float* base = d.img + ry * d.W + rx;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int ou = rr * d.W + kq + 4 * c;       // pixel (row rr, column kq + 4c): C_U operands
+        const int ov = (kq + 4 * c) * d.W + rr;     // pixel (row kq + 4c, column rr): C_V operands
         if (L.C == 1) {
-          X0[i][px] = (double)d.img[off];
+          const double zu = (double)base[ou], zv = (double)base[ov];
+          gu0 = __builtin_amdgcn_mfma_f64_16x16x4f64(zu, zu, gu0, 0, 0, 0);
+          gv0 = __builtin_amdgcn_mfma_f64_16x16x4f64(zv, zv, gv0, 0, 0, 0);
         } else {
-          double f0, f1r, f1i;
-          dft3((double)d.img[off], (double)d.img[HW + off], (double)d.img[2 * HW + off], f0, f1r, f1i);
-          X0[i][px] = f0;
-          X1r[i][px] = f1r;
-          X1i[i][px] = f1i;
+          double f0u, f1ru, f1iu, f0v, f1rv, f1iv;
+          dft3((double)base[ou], (double)base[HW + ou], (double)base[2 * HW + ou], f0u, f1ru, f1iu);
+          dft3((double)base[ov], (double)base[HW + ov], (double)base[2 * HW + ov], f0v, f1rv, f1iv);
+          const double zu = upper ? f1iu : f1ru, zv = upper ? f1iv : f1rv;
+          gu1 = __builtin_amdgcn_mfma_f64_16x16x4f64(zu, zu, gu1, 0, 0, 0);
+          gv1 = __builtin_amdgcn_mfma_f64_16x16x4f64(zv, zv, gv1, 0, 0, 0);
+          gu0 = __builtin_amdgcn_mfma_f64_16x16x4f64(f0u, f0u, gu0, 0, 0, 0);
+          gv0 = __builtin_amdgcn_mfma_f64_16x16x4f64(f0v, f0v, gv0, 0, 0, 0);
         }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int e = tid + 256 * h;
-        if (e >= nel) continue;
-        double s = 0.0;
-        if (e < 128) {
-          const int a = (e & 63) >> 3, b = e & 7;
-          const bool rowsp = e < 64;  // C_U: rows a, b ; C_V: columns a, b
-          for (int i = 0; i < nsub; ++i)
-#pragma unroll
-            for (int t = 0; t < 8; ++t)
-              s += rowsp ? X0[i][a * 8 + t] * X0[i][b * 8 + t] : X0[i][t * 8 + a] * X0[i][t * 8 + b];
-        } else {
-          const int q = e - 128;
-          const bool rowsp = q < 128;
-          const int qq = q & 127;
-          const int ab = qq >> 1, a = ab >> 3, b = ab & 7;
-          const bool im = qq & 1;
-          for (int i = 0; i < nsub; ++i)
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-              if (rowsp) {  // sum_t Z[a][t] conj(Z[b][t])
-                const double ar = X1r[i][a * 8 + t], ai = X1i[i][a * 8 + t];
-                const double br = X1r[i][b * 8 + t], bi = X1i[i][b * 8 + t];
-                s += im ? (ai * br - ar * bi) : (ar * br + ai * bi);
-              } else {      // sum_t conj(Z[t][a]) Z[t][b]
-                const double ar = X1r[i][t * 8 + a], ai = X1i[i][t * 8 + a];
-                const double br = X1r[i][t * 8 + b], bi = X1i[i][t * 8 + b];
-                s += im ? (ar * bi - ai * br) : (ar * br + ai * bi);
-              }
-            }
-        }
-        acc[h] += s;
       }
     }
-    if (tid < nel) d.cov_part[(size_t)item * nel + tid] = acc[0];
-    if (tid + 256 < nel) d.cov_part[(size_t)item * nel + tid + 256] = acc[1];
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      red[wave][0][v][lane] = gu0[v];
+      red[wave][1][v][lane] = gv0[v];
+      red[wave][2][v][lane] = gu1[v];
+      red[wave][3][v][lane] = gv1[v];
+    }
+    __syncthreads();
+    // G(i, j) of gram g summed over the wavefronts, in wavefront order
+    auto G = [&](int g, int i, int j) __attribute__((always_inline)) {
+      const int v = i >> 2, l = 16 * (i & 3) + j;
+      return ((red[0][g][v][l] + red[1][g][v][l]) + red[2][g][v][l]) + red[3][g][v][l];
+    };
+    for (int e = tid; e < nel; e += 256) {
+      double val;
+      if (e < 128) {
+        const int g = e < 64 ? 0 : 1, ab = e & 63, a = ab >> 3, b = ab & 7;
+        val = G(g, a, b);
+      } else {
+        const int q = e - 128, g = q < 128 ? 2 : 3, qq = q & 127;
+        const int ab = qq >> 1, a = ab >> 3, b = ab & 7;
+        if (!(qq & 1)) val = G(g, a, b) + G(g, 8 + a, 8 + b);
+        else if (g == 2) val = G(g, 8 + a, b) - G(g, a, 8 + b);
+        else val = G(g, a, 8 + b) - G(g, 8 + a, b);
+      }
+      d.cov_part[(size_t)item * nel + e] = val;
+    }
   });
 }
 

@@ -530,38 +530,57 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
 }
 
 // Exact scan of the whole window for references whose certified shortlist
-// overflowed: integer distances for every candidate, bitonic sort of
-// (distance, window index) keys in LDS, first K-1 after the reference.
+// overflowed: the window's guide pixels are staged in LDS, integer distances
+// are computed for every candidate, and (distance, window index) keys are
+// sorted bitonically in LDS; the first K-1 after the reference are kept.
+// The (image, entry) pairs of all images are dealt round-robin to the work
+// groups.
 __global__ __launch_bounds__(256) void k_match_fallback(Launch L) {
+  constexpr int WMAX = MAX_WINDOW + PS - 1;
   __shared__ unsigned long long keys[4096];
+  __shared__ int win[WMAX * WMAX];
   const int tid = threadIdx.x;
   const int r = (L.window - 1) / 2;
   const int K = L.K;
+  const int G = gridDim.x;
   const int nimg = L.table ? L.n_img : 1;
+  long long base = 0;   // global number of the image's first entry
   for (int im = 0; im < nimg; ++im) {
     const ImgDesc d = L.table ? L.table[im] : L.one;
     const int count = *d.fb_count;
-    for (int j = blockIdx.x; j < count; j += gridDim.x) {
+    const int j0 = (int)(((long long)blockIdx.x - base % G + G) % G);
+    base += count;
+    for (int j = j0; j < count; j += G) {
       const int ref = d.fb_list[j];
       const int ry = ref_coord(ref / d.nrx, L.stride, d.Hp);
       const int rx = ref_coord(ref % d.nrx, L.stride, d.Wp);
       const int y0 = max(0, ry - r), y1 = min(d.Hp - 1, ry + r);
       const int x0 = max(0, rx - r), x1 = min(d.Wp - 1, rx + r);
       const int wx = x1 - x0 + 1, nc = (y1 - y0 + 1) * wx;
+      const int pw = wx + PS - 1, ph = y1 - y0 + PS;   // staged pixel region
       const int plane = (L.C == 1 || d.green[ref]) ? 0 : 1;
       const int* g = d.gplanes + (size_t)plane * d.H * d.W;
+      __syncthreads();
+      for (int e = tid; e < ph * pw; e += 256) {
+        const int yy = e / pw, xx = e - yy * pw;
+        win[yy * WMAX + xx] = g[(y0 + yy) * d.W + x0 + xx];
+      }
+      __syncthreads();
+      const int* rp = win + (ry - y0) * WMAX + (rx - x0);
       for (int c = tid; c < 4096; c += 256) {
         unsigned long long key = ~0ull;
         if (c < nc) {
-          const int cy = y0 + c / wx, cx = x0 + c % wx;
-          if (cy != ry || cx != rx) {
+          const int cy = c / wx, cx = c - cy * wx;
+          if (cy + y0 != ry || cx + x0 != rx) {
+            const int* cp = win + cy * WMAX + cx;
             long long dd = 0;
             for (int a = 0; a < PS; ++a)
+#pragma unroll
               for (int b = 0; b < PS; ++b) {
-                const int df = g[(ry + a) * d.W + rx + b] - g[(cy + a) * d.W + cx + b];
+                const int df = rp[a * WMAX + b] - cp[a * WMAX + b];
                 dd += (long long)df * df;
               }
-            key = ((unsigned long long)dd << 12) | (unsigned)((cy - y0) * 64 + (cx - x0));
+            key = ((unsigned long long)dd << 12) | (unsigned)(cy * 64 + cx);
           }
         }
         keys[c] = key;
@@ -588,7 +607,6 @@ __global__ __launch_bounds__(256) void k_match_fallback(Launch L) {
         d.idx[(size_t)ref * K] = ry * d.W + rx;
         if (d.dist) d.dist[(size_t)ref * K] = 0;
       }
-      __syncthreads();
     }
   }
 }

@@ -108,7 +108,7 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
   const int kl = lane >> 3, a = lane & 7;
   const int K = L.K;
   const int NL = K < 8 ? K : 8;         // slot lanes in use
-  const bool active = kl < NL;
+  const bool active = SPL > 1 || kl < NL;   // K >= 16 keeps every lane busy
   const int r = (L.window - 1) / 2;
   const int s = L.stride;
   const int TY = L.fty, TX = L.ftx;
@@ -153,7 +153,8 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
 #pragma unroll
       for (int j = 0; j < SPL; ++j) {
         const int k = kl * SPL + j;
-        const int pos = active ? d.idx[(size_t)g * K + k] : 0;
+        // inactive lanes (K < 8) read slot 0 and drop it; loads stay unconditional
+        const int pos = d.idx[(size_t)g * K + (active ? k : 0)];
         // positions come from the caller's idx: clamp to valid patch corners
         split_pos(pos, d.W, rW, py[j], px[j]);
         py[j] = min(max(py[j], 0), d.Hp - 1);
@@ -162,7 +163,10 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
 #pragma unroll
         for (int ch = 0; ch < C; ++ch)
 #pragma unroll
-          for (int b = 0; b < 8; ++b) X[j][ch][b] = active ? src[ch * HW + b] : 0.f;
+          for (int b = 0; b < 8; ++b) {
+            const float v = src[ch * HW + b];
+            X[j][ch][b] = active ? v : 0.f;
+          }
       }
 
       // ---- t-SVD projection U^T * P * V per slot (Eq. 18, patch level) ----

@@ -64,7 +64,14 @@ struct ImgDesc {
 //   c = 1: U0[8][8], V0[8][8]
 //   c = 3: U0, V0 (f = 0, real), U1r, U1i, V1r, V1i (f = 1, complex)
 constexpr int FB_U0 = 0, FB_V0 = 64, FB_U1R = 128, FB_U1I = 192, FB_V1R = 256, FB_V1I = 320;
-constexpr int FB_SIZE = 384;
+// Row-major slices for the vector-ALU filter, whose products all read
+// matrix rows: transposes (suffix T) for the forward products, and the sums
+// or differences that the three-multiplication complex products use
+// (P: real + imaginary part, M: real - imaginary part).
+constexpr int FB_V0T = 384, FB_V1RT = 448, FB_V1IT = 512, FB_V1PT = 576;
+constexpr int FB_U0T = 640, FB_U1RT = 704, FB_U1IT = 768, FB_U1MT = 832;
+constexpr int FB_U1P = 896, FB_V1M = 960;
+constexpr int FB_SIZE = 1024;
 
 struct Launch {
   ImgDesc one;             // used when table == nullptr

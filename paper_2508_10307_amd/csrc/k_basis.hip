@@ -259,14 +259,26 @@ __global__ void k_fbasis(Launch L, const float* U_ext, const float* V_ext) {
       const int uv = e >> 6, ab = e & 63;
       const float* ext = uv ? V_ext : U_ext;
       const float* T = ext ? ext : d.basis + uv * L.C * 64;
+      const int tr = (ab & 7) * 8 + (ab >> 3);   // position of entry ab in the transpose
       if (L.C == 1) {
         d.fbasis[(uv ? FB_V0 : FB_U0) + ab] = T[ab];
+        d.fbasis[(uv ? FB_V0T : FB_U0T) + tr] = T[ab];
       } else {
         double f0, f1r, f1i;
         dft3((double)T[ab], (double)T[64 + ab], (double)T[128 + ab], f0, f1r, f1i);
         d.fbasis[(uv ? FB_V0 : FB_U0) + ab] = (float)f0;
         d.fbasis[(uv ? FB_V1R : FB_U1R) + ab] = (float)f1r;
         d.fbasis[(uv ? FB_V1I : FB_U1I) + ab] = (float)f1i;
+        d.fbasis[(uv ? FB_V0T : FB_U0T) + tr] = (float)f0;
+        d.fbasis[(uv ? FB_V1RT : FB_U1RT) + tr] = (float)f1r;
+        d.fbasis[(uv ? FB_V1IT : FB_U1IT) + tr] = (float)f1i;
+        if (uv) {
+          d.fbasis[FB_V1PT + tr] = (float)(f1r + f1i);
+          d.fbasis[FB_V1M + ab] = (float)(f1r - f1i);
+        } else {
+          d.fbasis[FB_U1MT + tr] = (float)(f1r - f1i);
+          d.fbasis[FB_U1P + ab] = (float)(f1r + f1i);
+        }
       }
     }
   }

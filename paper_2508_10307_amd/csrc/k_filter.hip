@@ -49,25 +49,49 @@ __device__ inline const cfloat* uniform_ptr(const float* p) {
 }
 
 // The pointer is passed through an empty asm so that the compiler cannot
-// hoist a slice's 64 scalar loads out of the group loop (it would then keep
-// all 384 coefficients live and spill SGPRs into VGPR lanes).
+// hoist scalar loads out of the group loop (it would then keep the
+// coefficients live and spill SGPRs into VGPR lanes).
 __device__ inline const cfloat* launder(const cfloat* p) {
   asm volatile("" : "+s"(p));
   return p;
 }
 
-// y[b] (+)= sgn * sum_t x[t] M[t*8 + b]   (TR = 0)
-// y[b] (+)= sgn * sum_t x[t] M[b*8 + t]   (TR = 1)
-// with one 8x8 basis slice (64 scalar operands) per call.
-template <int TR, bool ACC>
+// y[b] (+)= sgn * sum_t M[b*8 + t] x[t]: one 8x8 row-major basis slice,
+// consumed as two blocks of four rows (32 scalar operands live at a time).
+template <bool ACC>
 __device__ inline void mv(const float (&x)[8], const cfloat* M0, float sgn, float (&y)[8]) {
-  const cfloat* M = launder(M0);
 #pragma unroll
-  for (int b = 0; b < 8; ++b) {
-    float s = ACC ? y[b] : 0.f;
+  for (int h = 0; h < 2; ++h) {
+    const cfloat* M = launder(M0 + 32 * h);
 #pragma unroll
-    for (int t = 0; t < 8; ++t) s = fmaf(sgn * x[t], M[TR ? b * 8 + t : t * 8 + b], s);
-    y[b] = s;
+    for (int bb = 0; bb < 4; ++bb) {
+      const int b = 4 * h + bb;
+      float s = ACC ? y[b] : 0.f;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) s = fmaf(sgn * x[t], M[bb * 8 + t], s);
+      y[b] = s;
+    }
+  }
+}
+
+// Complex product with three real products (Gauss):
+// (yr + i yi) = (MR + i MI)(xr + i xi), given the slices MR, MI and
+// MP = MR + MI (all row-major):  A = MR xr, B = MI xi, C = MP (xr + xi);
+// yr = A - B, yi = C - A - B.  MI may be negated through sgn_i (with MP the
+// matching sum) to apply a conjugate.
+__device__ inline void cmv(const float (&xr)[8], const float (&xi)[8], const cfloat* MR,
+                           const cfloat* MI, float sgn_i, const cfloat* MP, float (&yr)[8],
+                           float (&yi)[8]) {
+  float a[8], b[8], xs[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) xs[t] = xr[t] + xi[t];
+  mv<false>(xr, MR, 1.f, a);
+  mv<false>(xi, MI, sgn_i, b);
+  mv<false>(xs, MP, 1.f, yi);
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    yr[t] = a[t] - b[t];
+    yi[t] = yi[t] - a[t] - b[t];
   }
 }
 
@@ -177,10 +201,10 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
 #pragma unroll
           for (int b = 0; b < 8; ++b) nf = fmaf(X[j][0][b], 0.f, nf);
           float y[8];
-          mv<0, false>(X[j][0], fb + FB_V0, 1.f, y);
+          mv<false>(X[j][0], fb + FB_V0T, 1.f, y);   // y[b] = sum_t x[t] V[t][b]
           transpose_rc(T, kl, a, y);
           float z[8];
-          mv<0, false>(y, fb + FB_U0, 1.f, z);   // z[i] = sum_r y[r] U[r][i]
+          mv<false>(y, fb + FB_U0T, 1.f, z);   // z[i] = sum_r y[r] U[r][i]
 #pragma unroll
           for (int i = 0; i < 8; ++i) X[j][0][i] = z[i];
         } else {
@@ -195,21 +219,17 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
           }
           float y0[8], y1r[8], y1i[8];
           // Y = P^ V_F: f = 0 real, f = 1 complex (one real slice per pass)
-          mv<0, false>(f0, fb + FB_V0, 1.f, y0);
-          mv<0, false>(f1r, fb + FB_V1R, 1.f, y1r);
-          mv<0, false>(f1i, fb + FB_V1R, 1.f, y1i);
-          mv<0, true>(f1i, fb + FB_V1I, -1.f, y1r);
-          mv<0, true>(f1r, fb + FB_V1I, 1.f, y1i);
+          mv<false>(f0, fb + FB_V0T, 1.f, y0);
+          // y1 = V_F(1)^T P^(1) per row: (V1R + i V1I)^T (f1r + i f1i)
+          cmv(f1r, f1i, fb + FB_V1RT, fb + FB_V1IT, 1.f, fb + FB_V1PT, y1r, y1i);
           transpose_rc(T, kl, a, y0);
           transpose_rc(T, kl, a, y1r);
           transpose_rc(T, kl, a, y1i);
           // Z = U_F^H Y: z[i] = sum_r conj(U[r][i]) y[r]
           float z0[8], z1r[8], z1i[8];
-          mv<0, false>(y0, fb + FB_U0, 1.f, z0);
-          mv<0, false>(y1r, fb + FB_U1R, 1.f, z1r);
-          mv<0, false>(y1i, fb + FB_U1R, 1.f, z1i);
-          mv<0, true>(y1i, fb + FB_U1I, 1.f, z1r);
-          mv<0, true>(y1r, fb + FB_U1I, -1.f, z1i);
+          mv<false>(y0, fb + FB_U0T, 1.f, z0);
+          // z1 = conj(U_F(1))^T y1: (U1R - i U1I)^T (y1r + i y1i)
+          cmv(y1r, y1i, fb + FB_U1RT, fb + FB_U1IT, -1.f, fb + FB_U1MT, z1r, z1i);
 #pragma unroll
           for (int i = 0; i < 8; ++i) {
             const float sr = z1r[i], si = z1i[i];
@@ -315,9 +335,9 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
         float out[C][8];
         if (C == 1) {
           float y[8];
-          mv<1, false>(X[j][0], fb + FB_U0, 1.f, y);   // y[r] = sum_i U[r][i] s[i]
+          mv<false>(X[j][0], fb + FB_U0, 1.f, y);   // y[r] = sum_i U[r][i] s[i]
           transpose_cr(T, kl, a, y);
-          mv<1, false>(y, fb + FB_V0, 1.f, out[0]);   // out[b] = sum_c y[c] V[b][c]
+          mv<false>(y, fb + FB_V0, 1.f, out[0]);    // out[b] = sum_c y[c] V[b][c]
 #pragma unroll
           for (int b = 0; b < 8; ++b) out[0][b] *= fxs;   // fixed-point scale (a power of two)
         } else {
@@ -331,21 +351,17 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
           }
           // Y = U_F S^: y[r] = sum_i U[r][i] s[i]
           float y0[8], y1r[8], y1i[8];
-          mv<1, false>(s0, fb + FB_U0, 1.f, y0);
-          mv<1, false>(s1r, fb + FB_U1R, 1.f, y1r);
-          mv<1, false>(s1i, fb + FB_U1R, 1.f, y1i);
-          mv<1, true>(s1i, fb + FB_U1I, -1.f, y1r);
-          mv<1, true>(s1r, fb + FB_U1I, 1.f, y1i);
+          mv<false>(s0, fb + FB_U0, 1.f, y0);
+          // y1 = U_F(1) s1: (U1R + i U1I)(s1r + i s1i)
+          cmv(s1r, s1i, fb + FB_U1R, fb + FB_U1I, 1.f, fb + FB_U1P, y1r, y1i);
           transpose_cr(T, kl, a, y0);
           transpose_cr(T, kl, a, y1r);
           transpose_cr(T, kl, a, y1i);
           // P^ = Y V_F^H: p[b] = sum_c y[c] conj(V[b][c])
           float p0[8], p1r[8], p1i[8];
-          mv<1, false>(y0, fb + FB_V0, 1.f, p0);
-          mv<1, false>(y1r, fb + FB_V1R, 1.f, p1r);
-          mv<1, false>(y1i, fb + FB_V1R, 1.f, p1i);
-          mv<1, true>(y1i, fb + FB_V1I, 1.f, p1r);
-          mv<1, true>(y1r, fb + FB_V1I, -1.f, p1i);
+          mv<false>(y0, fb + FB_V0, 1.f, p0);
+          // p1 = conj(V_F(1)) y1 per row: (V1R - i V1I)(y1r + i y1i)
+          cmv(y1r, y1i, fb + FB_V1R, fb + FB_V1I, -1.f, fb + FB_V1M, p1r, p1i);
 #pragma unroll
           for (int b = 0; b < 8; ++b) {
             const float sr = p1r[b], si = p1i[b];

@@ -2,8 +2,8 @@
 //
 // One work group per 4x4 tile of references.  For each guide plane the tile
 // uses, the pixel region covering the union of the 16 search windows is
-// staged in LDS (integer guide, centred by the tile mean, which leaves every
-// distance unchanged), then:
+// staged in LDS (integer guide, centred by an integer offset, which leaves
+// every distance unchanged), then:
 //
 //  1. distance tiles of 16 references x 16 candidates, either as
 //     |a|^2 + |b|^2 - 2 a.b with a.b on BF16 MFMA (FP32 accumulation; the
@@ -75,8 +75,6 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
   float* rnorm = (float*)(rinfo + 128);            // [16][2] |a|^2, |a|
   float* Tp = rnorm + 32;                          // [16]
   int* scount = (int*)(Tp + 16);                   // [16]
-  long long* red = (long long*)(scount + 16);      // [8]
-  int* shared_m = (int*)(red + 8);                 // [2]
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int kq = lane >> 4, n = lane & 15;
@@ -125,43 +123,40 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
       __syncthreads();  // the previous plane's re-rank still reads the LDS region
       const int* gsrc = d.gplanes + (size_t)p * d.H * d.W;
 
-      // ---- stage the region; centring offset m = floor(mean) ----
-      long long sum = 0, cntv = 0;
-      for (int e = tid; e < rows * cols; e += 256) {
-        const int y = e / cols, x = e - y * cols;
-        const int gx = X0 + x;
-        int v = 0;
-        if (gx < d.W) { v = gsrc[(Y0 + y) * d.W + gx]; sum += v; cntv += 1; }
-        gi[y * pitch + x] = v;
+      // ---- stage the region, centred by an integer offset m ----
+      // Any integer m leaves every distance unchanged; the floor of the mean
+      // of a 16 x 16 sample of the region keeps the centred values (and with
+      // them the error bounds) small.  Columns past the image read as 0.
+      int m;
+      {
+        const int sy = (tid >> 4) * rows / 16;
+        const int sx = min((tid & 15) * cols / 16, d.W - 1 - X0);
+        int v = gsrc[(Y0 + sy) * d.W + X0 + sx];   // |v| < 3 * 2^20: the sum fits int32
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        int* part = (int*)Tp;   // free until the threshold step
+        if (lane == 0) part[wave] = v;
+        __syncthreads();
+        m = (part[0] + part[1] + part[2] + part[3]) >> 8;   // floor(sum / 256)
       }
-      for (int o = 32; o > 0; o >>= 1) { sum += shfl_xor_u64(sum, o); cntv += shfl_xor_u64(cntv, o); }
-      __syncthreads();
-      if (lane == 0) { red[wave] = sum; red[4 + wave] = cntv; }
-      __syncthreads();
-      if (tid == 0) {
-        long long S = red[0] + red[1] + red[2] + red[3];
-        long long N = red[4] + red[5] + red[6] + red[7];
-        long long m = S / N;
-        if (m * N > S) --m;
-        shared_m[0] = (int)m;
-      }
-      __syncthreads();
-      const int m = shared_m[0];
-      for (int e = tid; e < rows * cols; e += 256) {
-        const int y = e / cols, x = e - y * cols;
-        const int gx = X0 + x;
-        const int v = gx < d.W ? gi[y * pitch + x] - m : 0;
-        gi[y * pitch + x] = v;
-        gb[y * pitch + x] = MODE == 0 ? split_pack((float)v) : __float_as_uint((float)v);
+      for (int y = wave; y < rows; y += 4) {
+        const int* srow = gsrc + (Y0 + y) * d.W + X0;
+        for (int x = lane; x < cols; x += 64) {
+          const int v = X0 + x < d.W ? srow[x] - m : 0;
+          gi[y * pitch + x] = v;
+          gb[y * pitch + x] = MODE == 0 ? split_pack((float)v) : __float_as_uint((float)v);
+        }
       }
       __syncthreads();
 
       // ---- exact candidate norms |b|^2 (norm+dot form only) ----
+      // One task per (column, 8 rows): row sums of v^2 over 8 columns, then
+      // a sliding sum down the rows, in FP64 (exact: |v| < 2^22, sums < 2^50).
       if (MODE == 0) {
         const int nseg = (RYc + 7) >> 3;
         for (int task = tid; task < RXP * nseg; task += 256) {
           const int cx = task % RXP, c0 = (task / RXP) * 8;
-          double rs[15];   // exact: |v| < 2^22, sums < 2^50
+          double rs[15];
 #pragma unroll
           for (int j = 0; j < 15; ++j) {
             const int y = c0 + j;
@@ -189,19 +184,13 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
             if (j < 7) nn += rs[j + 8] - rs[j];
           }
         }
+        __syncthreads();
       }
+      // reference norms: the reference is the candidate at its own position
       if (tid < 16) {
         const int* ri = rinfo + tid * 8;
         float na = 0.f;
-        if (ri[0] & (1 << p)) {
-          double a = 0.0;   // exact, as above
-          for (int py = 0; py < PS; ++py)
-            for (int px = 0; px < PS; ++px) {
-              const double v = (double)gi[(ri[1] + py) * pitch + ri[2] + px];
-              a = fma(v, v, a);
-            }
-          na = (float)a;
-        }
+        if (MODE == 0 && (ri[0] & (1 << p))) na = nbf[ri[1] * RXP + ri[2]];
         rnorm[2 * tid] = na;
         rnorm[2 * tid + 1] = sqrtf(na);
       }

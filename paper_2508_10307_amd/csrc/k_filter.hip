@@ -10,8 +10,9 @@
 //    through LDS;
 //  * the channel-mode DFT of the t-product (c = 3) is lane-local;
 //  * the Haar transform along the group mode (Eq. 9, fast form: pairwise
-//    sums and differences / sqrt 2) runs first on the slots of a lane, then
-//    across lanes with xor shuffles;
+//    sums and differences, unnormalised, with the scales moved into the
+//    thresholds and a power-of-two weight per kept coefficient) runs first
+//    on the slots of a lane, then across lanes with xor shuffles;
 //  * thresholding, masks and the inverse transforms follow the same layout;
 //  * estimates accumulate, in 64-bit fixed point, into an LDS tile covering
 //    every patch the tile's groups can touch, flushed once with atomics
@@ -23,7 +24,6 @@
 
 namespace hts {
 
-constexpr float RSQRT2 = 0.70710678118654752440f;
 constexpr float SQRT3 = 1.73205080756887729353f;
 constexpr float HALF_SQRT3 = 0.86602540378443864676f;
 constexpr int TPITCH = 9;                 // transpose scratch pitch (floats)
@@ -124,6 +124,24 @@ __device__ inline int haar_row(int k, int K) {
   return (K >> L) + (k >> L);
 }
 
+// The butterflies run unnormalised ((u + v, u - v), no 1/sqrt 2): the
+// forward transform is D H (H orthonormal, D = diag 2^(l/2), l = the level
+// of the coefficient left in slot k: ctz(k) + 1, log2 K for the DC row in
+// slot 0), so a coefficient is compared with tau 2^(l/2).  The unscaled
+// inverse butterflies apply H^T D; scaling each kept coefficient by 2^-l
+// (a power of two) first makes it H^T D^-1, the exact inverse.
+__device__ inline int haar_level(int k, int K) {
+  return k == 0 ? __builtin_ctz(K) : __builtin_ctz(k) + 1;
+}
+__device__ inline float haar_scale(int k, int K) {
+  const int l = haar_level(k, K);
+  const float p = (float)(1 << (l >> 1));
+  return (l & 1) ? p * 1.41421356237309504880f : p;
+}
+__device__ inline float haar_unscale(int k, int K) {
+  return 1.f / (float)(1 << haar_level(k, K));
+}
+
 // MASKS = 1 exports the keep-masks (when d.masks is set).
 template <int C, int SPL, int ADJ, int MASKS, int BATCH>
 __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
@@ -155,7 +173,14 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
     const float tau = d.tau;
     const float rW = 1.0f / (float)d.W;
     const float fxs = fx_scale(d);                 // fixed-point scale of the estimates
-    const float s3 = fxs * (1.f / 3.f), rfxs = 1.f / fxs;
+    const float rfxs = 1.f / fxs;
+    const float s3 = fxs * (1.f / 3.f);
+    float tauj[SPL], wj[SPL];                      // thresholds and inverse weights of this lane's slots
+#pragma unroll
+    for (int j = 0; j < SPL; ++j) {
+      tauj[j] = tau * haar_scale(kl * SPL + j, K);
+      wj[j] = haar_unscale(kl * SPL + j, K);
+    }
 
     __syncthreads();
     for (int e = tid; e < NP * RA * CA; e += 256) acc[e] = 0ull;
@@ -251,19 +276,19 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
               const float u = X[j][ch][i], v = X[j + st][ch][i];
-              X[j][ch][i] = (u + v) * RSQRT2;
-              X[j + st][ch][i] = (u - v) * RSQRT2;
+              X[j][ch][i] = u + v;
+              X[j + st][ch][i] = u - v;
             }
       // cross-lane levels on the running sums (slot lanes kl ^ m)
       for (int m = 1; m < NL; m <<= 1) {
         const bool part = (kl & (m - 1)) == 0;
-        const bool upper = (kl & m) != 0;
+        const float sg = (kl & m) ? -1.f : 1.f;   // upper lane: o - x, lower: x + o
 #pragma unroll
         for (int ch = 0; ch < C; ++ch)
 #pragma unroll
           for (int i = 0; i < 8; ++i) {
             const float o = __shfl_xor(X[0][ch][i], 8 * m, 64);
-            const float nv = upper ? (o - X[0][ch][i]) * RSQRT2 : (X[0][ch][i] + o) * RSQRT2;
+            const float nv = fmaf(sg, X[0][ch][i], o);
             X[0][ch][i] = part ? nv : X[0][ch][i];
           }
       }
@@ -284,13 +309,13 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
             }
 #pragma unroll
             for (int i = 0; i < 8; ++i)
-              if (!((bits >> (i * 8 + a)) & 1ull)) X[j][ch][i] = 0.f;
+              X[j][ch][i] = ((bits >> (i * 8 + a)) & 1ull) ? X[j][ch][i] * wj[j] : 0.f;
           } else {
             unsigned char mybyte = 0;
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-              const bool keep = fabsf(X[j][ch][i]) >= tau;
-              if (!keep) X[j][ch][i] = 0.f;
+              const bool keep = fabsf(X[j][ch][i]) >= tauj[j];
+              X[j][ch][i] = keep ? X[j][ch][i] * wj[j] : 0.f;
               if (MASKS && d.masks) {
                 const unsigned long long bal = __ballot(keep);
                 const unsigned char byte = (unsigned char)((bal >> (8 * kl)) & 0xFFu);
@@ -305,13 +330,13 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
       // ---- inverse Haar: cross-lane levels (coarse first), then in-lane ----
       for (int m = NL >> 1; m >= 1; m >>= 1) {
         const bool part = (kl & (m - 1)) == 0;
-        const bool upper = (kl & m) != 0;
+        const float sg = (kl & m) ? -1.f : 1.f;
 #pragma unroll
         for (int ch = 0; ch < C; ++ch)
 #pragma unroll
           for (int i = 0; i < 8; ++i) {
             const float o = __shfl_xor(X[0][ch][i], 8 * m, 64);
-            const float nv = upper ? (o - X[0][ch][i]) * RSQRT2 : (X[0][ch][i] + o) * RSQRT2;
+            const float nv = fmaf(sg, X[0][ch][i], o);
             X[0][ch][i] = part ? nv : X[0][ch][i];
           }
       }
@@ -324,8 +349,8 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
               const float u = X[j][ch][i], v = X[j + st][ch][i];
-              X[j][ch][i] = (u + v) * RSQRT2;
-              X[j + st][ch][i] = (u - v) * RSQRT2;
+              X[j][ch][i] = u + v;
+              X[j + st][ch][i] = u - v;
             }
 
       // ---- inverse t-SVD projection U * S * V^T (Eq. 20) and write-back ----

@@ -33,7 +33,6 @@ namespace {
 
 typedef __attribute__((ext_vector_type(4))) float f4;
 
-constexpr float RS2 = 0.70710678118654752440f;
 constexpr float SQ3 = 1.73205080756887729353f;
 constexpr float HSQ3 = 0.86602540378443864676f;
 // Transpose scratch: element (ro, s, r, b) at (s*8 + b)*TPB + r*2 + ro, so a
@@ -69,6 +68,19 @@ __device__ inline int haar_row_m(int k, int K) {
   if (k == 0) return 0;
   const int L = __builtin_ctz(k) + 1;
   return (K >> L) + (k >> L);
+}
+
+// Unnormalised butterflies ((u + v, u - v)): the forward transform is D H
+// (D = diag 2^(l/2), l = ctz(k) + 1 for slot k, log2 K for slot 0), so a
+// coefficient is compared with tau 2^(l/2); the unscaled inverse applies
+// H^T D, and scaling each kept coefficient by 2^-l first makes it exact.
+__device__ inline int haar_level_m(int k, int K) {
+  return k == 0 ? __builtin_ctz(K) : __builtin_ctz(k) + 1;
+}
+__device__ inline float haar_scale_m(int k, int K) {
+  const int l = haar_level_m(k, K);
+  const float p = (float)(1 << (l >> 1));
+  return (l & 1) ? p * 1.41421356237309504880f : p;
 }
 
 }  // namespace
@@ -110,6 +122,7 @@ __global__ __launch_bounds__(256, K >= 32 ? 1 : 2) void k_filter_mfma(Launch L) 
     const float rW = 1.0f / (float)d.W;
     const float fxs = fx_scale(d);                 // fixed-point scale of the estimates
     const float s3 = fxs * (1.f / 3.f), rfxs = 1.f / fxs;
+    const float sgl = s ? -1.f : 1.f;              // level-1 butterfly: odd slot o - v, even v + o
     const float* fb = d.fbasis;
 
     // ---- basis operands for the four products (see the header comment) ----
@@ -233,7 +246,7 @@ __global__ __launch_bounds__(256, K >= 32 ? 1 : 2) void k_filter_mfma(Launch L) 
 #pragma unroll
           for (int e = 0; e < 2; ++e) {
             const float v = S[b][c][e], o = xor8(v);
-            S[b][c][e] = s ? (o - v) * RS2 : (v + o) * RS2;
+            S[b][c][e] = fmaf(sgl, v, o);
           }
 #pragma unroll
       for (int w = 1; w < NB; w <<= 1)
@@ -244,8 +257,8 @@ __global__ __launch_bounds__(256, K >= 32 ? 1 : 2) void k_filter_mfma(Launch L) 
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
               const float u = S[b][c][e], v = S[b + w][c][e];
-              S[b][c][e] = s ? u : (u + v) * RS2;
-              S[b + w][c][e] = s ? v : (u - v) * RS2;
+              S[b][c][e] = s ? u : u + v;
+              S[b + w][c][e] = s ? v : u - v;
             }
 
       __builtin_amdgcn_sched_barrier(0);
@@ -262,15 +275,18 @@ __global__ __launch_bounds__(256, K >= 32 ? 1 : 2) void k_filter_mfma(Launch L) 
             const int row_s = haar_row_m(2 * b + s, K);
             const uint32_t* w = d.masks_in + 2 * (((size_t)grel * K + row_s) * C + c);
             const unsigned long long bits = (unsigned long long)w[0] | ((unsigned long long)w[1] << 32);
+            const float wgt = 1.f / (float)(1 << haar_level_m(2 * b + s, K));
 #pragma unroll
             for (int e = 0; e < 2; ++e)
-              if (!((bits >> ((2 * q + e) * 8 + n8)) & 1ull)) S[b][c][e] = 0.f;
+              S[b][c][e] = ((bits >> ((2 * q + e) * 8 + n8)) & 1ull) ? S[b][c][e] * wgt : 0.f;
           } else {
             unsigned long long bal[2];
+            const float thr = tau * (s ? 1.41421356237309504880f : haar_scale_m(2 * b, K));
+            const float wgt = s ? 0.5f : 1.f / (float)(1 << haar_level_m(2 * b, K));
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
-              const bool keep = fabsf(S[b][c][e]) >= tau;
-              S[b][c][e] = keep ? S[b][c][e] : 0.f;
+              const bool keep = fabsf(S[b][c][e]) >= thr;
+              S[b][c][e] = keep ? S[b][c][e] * wgt : 0.f;
               bal[e] = __ballot(keep);
             }
             if (MASKS && d.masks) {
@@ -314,8 +330,8 @@ __global__ __launch_bounds__(256, K >= 32 ? 1 : 2) void k_filter_mfma(Launch L) 
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
               const float u = S[b][c][e], v = S[b + w][c][e];
-              S[b][c][e] = s ? u : (u + v) * RS2;
-              S[b + w][c][e] = s ? v : (u - v) * RS2;
+              S[b][c][e] = s ? u : u + v;
+              S[b + w][c][e] = s ? v : u - v;
             }
 #pragma unroll
       for (int b = 0; b < NB; ++b)
@@ -324,7 +340,7 @@ __global__ __launch_bounds__(256, K >= 32 ? 1 : 2) void k_filter_mfma(Launch L) 
 #pragma unroll
           for (int e = 0; e < 2; ++e) {
             const float v = S[b][c][e], o = xor8(v);
-            S[b][c][e] = s ? (o - v) * RS2 : (v + o) * RS2;
+            S[b][c][e] = fmaf(sgl, v, o);
           }
 
       __builtin_amdgcn_sched_barrier(0);

@@ -195,12 +195,20 @@ Schedule schedule_for(const hts_params* p, int C) {
 
 #define HIPCHK(x) do { if ((x) != hipSuccess) return HTS_ERR_HIP; } while (0)
 
-hts_status run_match(const hts_params* p, int C, const Schedule& sc, ImgDesc d, hipStream_t s) {
-  HIPCHK(launch_reset_counters(make_launch(p, C, d, -1, sc.fty, sc.ftx), s));
-  HIPCHK(launch_quant(make_launch(p, C, d, W_PIX, sc.fty, sc.ftx), 0, s));
-  HIPCHK(launch_gcp(make_launch(p, C, d, W_REF, sc.fty, sc.ftx), 0, s));
-  HIPCHK(launch_match(make_launch(p, C, d, W_MATCH, sc.fty, sc.ftx), p->match_mode, sc.terms, 0, s));
-  HIPCHK(launch_match_fallback(make_launch(p, C, d, -1, sc.fty, sc.ftx), 256, s));
+// count_hist: the match also builds the coverage histogram (d.hist) of the
+// groups it forms.
+hts_status run_match(const hts_params* p, int C, const Schedule& sc, ImgDesc d, hipStream_t s,
+                     bool count_hist = false) {
+  auto LM = [&](int kind) {
+    Launch L = make_launch(p, C, d, kind, sc.fty, sc.ftx);
+    L.count_hist = count_hist ? 1 : 0;
+    return L;
+  };
+  HIPCHK(launch_reset_counters(LM(-1), s));
+  HIPCHK(launch_quant(LM(W_PIX), 0, s));
+  HIPCHK(launch_gcp(LM(W_REF), 0, s));
+  HIPCHK(launch_match(LM(W_MATCH), p->match_mode, sc.terms, 0, s));
+  HIPCHK(launch_match_fallback(LM(-1), 256, s));
   return HTS_OK;
 }
 
@@ -211,23 +219,28 @@ hts_status run_basis(const hts_params* p, int C, const Schedule& sc, ImgDesc d, 
 }
 
 // Coverage counts of references [ref_begin, ref_begin+ref_count) added into
-// d.cnt: histogram of the groups' patch corners, then its 8x8 box sum.
+// d.cnt: histogram of the groups' patch corners (unless the match already
+// built it), then its 8x8 box sum.
 hts_status run_count(const hts_params* p, int C, const Schedule& sc, const ImgDesc& d,
-                     bool zero_hist, hipStream_t s) {
-  if (zero_hist) HIPCHK(launch_zero_hist(make_launch(p, C, d, W_PIX, sc.fty, sc.ftx), 0, s));
-  HIPCHK(launch_count_hist(make_launch(p, C, d, W_REF, sc.fty, sc.ftx), 0, s));
+                     bool hist_ready, hipStream_t s) {
+  if (!hist_ready) {
+    HIPCHK(launch_zero_hist(make_launch(p, C, d, W_PIX, sc.fty, sc.ftx), 0, s));
+    HIPCHK(launch_count_hist(make_launch(p, C, d, W_REF, sc.fty, sc.ftx), 0, s));
+  }
   HIPCHK(launch_count_box(make_launch(p, C, d, W_BOX, sc.fty, sc.ftx), 0, s));
   return HTS_OK;
 }
 
 // U, V (nullable): a caller's basis to use instead of the workspace copy.
+// hist_ready: d.hist already holds the coverage histogram of these groups.
 hts_status run_filter(const hts_params* p, int C, const Schedule& sc, ImgDesc d, int adjoint,
-                      hipStream_t s, const float* U = nullptr, const float* V = nullptr) {
+                      hipStream_t s, const float* U = nullptr, const float* V = nullptr,
+                      bool hist_ready = false) {
   HIPCHK(launch_fbasis(make_launch(p, C, d, -1, sc.fty, sc.ftx), U, V, s));
   const Launch L = make_launch(p, C, d, W_FILT, sc.fty, sc.ftx);
   if (sc.valu) HIPCHK(launch_filter(L, sc.fty, sc.ftx, adjoint, 0, s));
   else HIPCHK(launch_filter_mfma(L, sc.fty, sc.ftx, adjoint, 0, s));
-  if (!adjoint && d.cnt) return run_count(p, C, sc, d, true, s);
+  if (!adjoint && d.cnt) return run_count(p, C, sc, d, hist_ready, s);
   return HTS_OK;
 }
 
@@ -353,16 +366,20 @@ hts_status enqueue_batch(const hts_params* p, int C, const BatchPlan& plan, cons
   const int cus = device_cus();
   const Schedule& sc = plan.sc;
   auto LK = [&](int kind) { return batch_launch(p, C, table, n, kind >= 0 ? plan.totals[kind] : 0, sc); };
+  auto LC = [&](int kind) {   // stages that also build the coverage histogram
+    Launch L = LK(kind);
+    L.count_hist = 1;
+    return L;
+  };
   HIPCHK(launch_reset_counters(LK(-1), s));
-  HIPCHK(launch_quant(LK(W_PIX), cus * 8, s));
+  HIPCHK(launch_quant(LC(W_PIX), cus * 8, s));
   HIPCHK(launch_gcp(LK(W_REF), cus * 8, s));
-  HIPCHK(launch_match(LK(W_MATCH), p->match_mode, sc.terms, cus * 2, s));
-  HIPCHK(launch_match_fallback(LK(-1), cus, s));
+  HIPCHK(launch_match(LC(W_MATCH), p->match_mode, sc.terms, cus * 2, s));
+  HIPCHK(launch_match_fallback(LC(-1), cus, s));
   HIPCHK(launch_cov(LK(W_COV), cus * 4, s));
   HIPCHK(launch_eig(LK(-1), s));
   HIPCHK(launch_fbasis(LK(-1), nullptr, nullptr, s));
   HIPCHK(launch_zero_accum(LK(W_PIX), cus * 8, s));
-  HIPCHK(launch_count_hist(LK(W_REF), cus * 8, s));
   HIPCHK(launch_count_box(LK(W_BOX), cus * 8, s));
   if (sc.valu) HIPCHK(launch_filter(LK(W_FILT), sc.fty, sc.ftx, 0, cus * 2, s));
   else HIPCHK(launch_filter_mfma(LK(W_FILT), sc.fty, sc.ftx, 0, cus * 2, s));
@@ -556,12 +573,12 @@ hts_status hts_denoise(const hts_params* p, const float* noisy, int32_t C, int32
   if (cnt_out) d.cnt = cnt_out;
   d.masks = masks_out;
   d.out = out;
-  st = run_match(p, C, sc, d, s);
+  st = run_match(p, C, sc, d, s, true);
   if (st != HTS_OK) return st;
   st = run_basis(p, C, sc, d, s);
   if (st != HTS_OK) return st;
   HIPCHK(launch_zero_accum(make_launch(p, C, d, W_PIX, sc.fty, sc.ftx), 0, s));
-  st = run_filter(p, C, sc, d, 0, s);
+  st = run_filter(p, C, sc, d, 0, s, nullptr, nullptr, true);
   if (st != HTS_OK) return st;
   HIPCHK(launch_finalize(make_launch(p, C, d, W_PIX, sc.fty, sc.ftx), 0, s));
   const size_t nb = (size_t)C * 64;

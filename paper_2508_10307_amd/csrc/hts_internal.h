@@ -67,7 +67,8 @@ constexpr int FB_U0 = 0, FB_V0 = 64, FB_U1R = 128, FB_U1I = 192, FB_V1R = 256, F
 // Row-major slices for the vector-ALU filter, whose products all read
 // matrix rows: transposes (suffix T) for the forward products, and the sums
 // or differences that the three-multiplication complex products use
-// (P: real + imaginary part, M: real - imaginary part).
+// (P: real + imaginary part, M: real - imaginary part).  For c = 3 the
+// transposed U slices are scaled by 1/3 (the inverse DFT that follows them).
 constexpr int FB_V0T = 384, FB_V1RT = 448, FB_V1IT = 512, FB_V1PT = 576;
 constexpr int FB_U0T = 640, FB_U1RT = 704, FB_U1IT = 768, FB_U1MT = 832;
 constexpr int FB_U1P = 896, FB_V1M = 960;
@@ -83,6 +84,8 @@ struct Launch {
   int32_t gcp_num, gcp_den;
   int32_t flags;
   int32_t fty, ftx;        // filter tile shape (references)
+  int32_t count_hist;      // 1: k_quant clears hist and the match adds every group's
+                           // slot corners to it (the coverage histogram)
 };
 
 // Match-kernel LDS geometry for a 4x4 reference tile at stride s and window

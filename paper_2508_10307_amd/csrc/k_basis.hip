@@ -48,30 +48,50 @@ __global__ __launch_bounds__(256) void k_cov(Launch L) {
     d4 gu1 = {0.0, 0.0, 0.0, 0.0}, gv1 = gu1, gu0 = gu1, gv0 = gu1;
     const int r_begin = item * COV_REFS;
     const int r_end = min(d.n_ref, r_begin + COV_REFS);
-    for (int ref = r_begin + wave; ref < r_end; ref += 4) {
-      const int iy = ref / d.nrx;
-      const int ry = ref_coord(iy, L.stride, d.Hp);
-      const int rx = ref_coord(ref - iy * d.nrx, L.stride, d.Wp);
-      const float* base = d.img + ry * d.W + rx;
+    // four references per round: their pixels are loaded before the MFMAs
+    // (a reference past the end reads the last one and contributes zero)
+    constexpr int RB = 4;
+    for (int r0 = r_begin + wave; r0 < r_end; r0 += 4 * RB) {
+      float pu[RB][2][3], pv[RB][2][3];
+      double live[RB];
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        const int ou = rr * d.W + kq + 4 * c;       // pixel (row rr, column kq + 4c): C_U operands
-        const int ov = (kq + 4 * c) * d.W + rr;     // pixel (row kq + 4c, column rr): C_V operands
-        if (L.C == 1) {
-          const double zu = (double)base[ou], zv = (double)base[ov];
-          gu0 = __builtin_amdgcn_mfma_f64_16x16x4f64(zu, zu, gu0, 0, 0, 0);
-          gv0 = __builtin_amdgcn_mfma_f64_16x16x4f64(zv, zv, gv0, 0, 0, 0);
-        } else {
-          double f0u, f1ru, f1iu, f0v, f1rv, f1iv;
-          dft3((double)base[ou], (double)base[HW + ou], (double)base[2 * HW + ou], f0u, f1ru, f1iu);
-          dft3((double)base[ov], (double)base[HW + ov], (double)base[2 * HW + ov], f0v, f1rv, f1iv);
-          const double zu = upper ? f1iu : f1ru, zv = upper ? f1iv : f1rv;
-          gu1 = __builtin_amdgcn_mfma_f64_16x16x4f64(zu, zu, gu1, 0, 0, 0);
-          gv1 = __builtin_amdgcn_mfma_f64_16x16x4f64(zv, zv, gv1, 0, 0, 0);
-          gu0 = __builtin_amdgcn_mfma_f64_16x16x4f64(f0u, f0u, gu0, 0, 0, 0);
-          gv0 = __builtin_amdgcn_mfma_f64_16x16x4f64(f0v, f0v, gv0, 0, 0, 0);
+      for (int u = 0; u < RB; ++u) {
+        const int ref = min(r0 + 4 * u, r_end - 1);
+        live[u] = r0 + 4 * u < r_end ? 1.0 : 0.0;
+        const int iy = ref / d.nrx;
+        const int ry = ref_coord(iy, L.stride, d.Hp);
+        const int rx = ref_coord(ref - iy * d.nrx, L.stride, d.Wp);
+        const float* base = d.img + ry * d.W + rx;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const int ou = rr * d.W + kq + 4 * c;       // pixel (row rr, column kq + 4c): C_U operands
+          const int ov = (kq + 4 * c) * d.W + rr;     // pixel (row kq + 4c, column rr): C_V operands
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch) {
+            pu[u][c][ch] = ch < L.C ? base[ch * HW + ou] : 0.f;
+            pv[u][c][ch] = ch < L.C ? base[ch * HW + ov] : 0.f;
+          }
         }
       }
+#pragma unroll
+      for (int u = 0; u < RB; ++u)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          if (L.C == 1) {
+            const double zu = live[u] * (double)pu[u][c][0], zv = live[u] * (double)pv[u][c][0];
+            gu0 = __builtin_amdgcn_mfma_f64_16x16x4f64(zu, zu, gu0, 0, 0, 0);
+            gv0 = __builtin_amdgcn_mfma_f64_16x16x4f64(zv, zv, gv0, 0, 0, 0);
+          } else {
+            double f0u, f1ru, f1iu, f0v, f1rv, f1iv;
+            dft3(live[u] * pu[u][c][0], live[u] * pu[u][c][1], live[u] * pu[u][c][2], f0u, f1ru, f1iu);
+            dft3(live[u] * pv[u][c][0], live[u] * pv[u][c][1], live[u] * pv[u][c][2], f0v, f1rv, f1iv);
+            const double zu = upper ? f1iu : f1ru, zv = upper ? f1iv : f1rv;
+            gu1 = __builtin_amdgcn_mfma_f64_16x16x4f64(zu, zu, gu1, 0, 0, 0);
+            gv1 = __builtin_amdgcn_mfma_f64_16x16x4f64(zv, zv, gv1, 0, 0, 0);
+            gu0 = __builtin_amdgcn_mfma_f64_16x16x4f64(f0u, f0u, gu0, 0, 0, 0);
+            gv0 = __builtin_amdgcn_mfma_f64_16x16x4f64(f0v, f0v, gv0, 0, 0, 0);
+          }
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -179,8 +199,17 @@ __global__ __launch_bounds__(256) void k_eig(Launch L) {
     const ImgDesc d = L.table ? L.table[im] : L.one;
     __syncthreads();
     for (int e = tid; e < nel; e += blockDim.x) {
+      // partials added in their order; eight loads in flight at a time
       double s = 0.0;
-      for (int j = 0; j < d.n_cov; ++j) s += d.cov_part[(size_t)j * nel + e];
+      int j = 0;
+      for (; j + 8 <= d.n_cov; j += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = d.cov_part[(size_t)(j + u) * nel + e];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+      }
+      for (; j < d.n_cov; ++j) s += d.cov_part[(size_t)j * nel + e];
       cov[e] = s;
     }
     __syncthreads();
@@ -269,14 +298,17 @@ __global__ void k_fbasis(Launch L, const float* U_ext, const float* V_ext) {
         d.fbasis[(uv ? FB_V0 : FB_U0) + ab] = (float)f0;
         d.fbasis[(uv ? FB_V1R : FB_U1R) + ab] = (float)f1r;
         d.fbasis[(uv ? FB_V1I : FB_U1I) + ab] = (float)f1i;
-        d.fbasis[(uv ? FB_V0T : FB_U0T) + tr] = (float)f0;
-        d.fbasis[(uv ? FB_V1RT : FB_U1RT) + tr] = (float)f1r;
-        d.fbasis[(uv ? FB_V1IT : FB_U1IT) + tr] = (float)f1i;
+        // the transposed U slices (the left products of the projection)
+        // carry the 1/c of the inverse DFT that follows them
+        const double q = uv ? 1.0 : 1.0 / 3.0;
+        d.fbasis[(uv ? FB_V0T : FB_U0T) + tr] = (float)(q * f0);
+        d.fbasis[(uv ? FB_V1RT : FB_U1RT) + tr] = (float)(q * f1r);
+        d.fbasis[(uv ? FB_V1IT : FB_U1IT) + tr] = (float)(q * f1i);
         if (uv) {
           d.fbasis[FB_V1PT + tr] = (float)(f1r + f1i);
           d.fbasis[FB_V1M + ab] = (float)(f1r - f1i);
         } else {
-          d.fbasis[FB_U1MT + tr] = (float)(f1r - f1i);
+          d.fbasis[FB_U1MT + tr] = (float)(q * (f1r - f1i));
           d.fbasis[FB_U1P + ab] = (float)(f1r + f1i);
         }
       }

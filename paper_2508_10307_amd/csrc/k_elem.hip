@@ -13,6 +13,7 @@ __global__ __launch_bounds__(256) void k_quant(Launch L) {
     const int p1 = min(HW, p0 + PIX_CHUNK);
     uint32_t mb = 0;   // bits of max |x| (sets the fixed-point scale of the aggregation)
     for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+      if (L.count_hist) d.hist[p] = 0;
       if (L.C == 1) {
         const float v = d.img[p];
         d.gplanes[p] = quantize(v);
@@ -71,9 +72,10 @@ __global__ void k_reset_counters(Launch L) {
 }
 
 // Accumulators to zero: the fixed-point numerator (or the float one when
-// the descriptor has none), cnt, the slot histogram and the poison plane (a
-// fill kernel rather than a memset so that the sequence stays valid inside
-// captured graphs).
+// the descriptor has none), cnt and the poison plane (a fill kernel rather
+// than a memset so that the sequence stays valid inside captured graphs).
+// The slot histogram is cleared where it is built (k_quant before a match
+// that counts, or k_zero_hist).
 __global__ __launch_bounds__(256) void k_zero_accum(Launch L) {
   for_each_item<W_PIX>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
     const int HW = d.H * d.W;
@@ -86,7 +88,6 @@ __global__ __launch_bounds__(256) void k_zero_accum(Launch L) {
         for (int c = 0; c < L.C; ++c) d.num[c * HW + p] = 0.0f;
       }
       if (d.cnt) d.cnt[p] = 0.0f;
-      if (d.hist) d.hist[p] = 0;
       if (d.poison) d.poison[p] = 0;
     }
   });

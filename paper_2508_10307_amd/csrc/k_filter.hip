@@ -48,21 +48,25 @@ __device__ inline const cfloat* uniform_ptr(const float* p) {
   return (const cfloat*)(((unsigned long long)hi << 32) | lo);
 }
 
-// The pointer is passed through an empty asm so that the compiler cannot
-// hoist scalar loads out of the group loop (it would then keep the
-// coefficients live and spill SGPRs into VGPR lanes).
+// The basis pointer is passed through an empty asm before every use so that
+// the compiler cannot hoist scalar loads out of the group loop (it would
+// then keep the coefficients live and spill SGPRs into VGPR lanes).  Only
+// the base is laundered: slice offsets are constants added afterwards, so
+// they fold into the loads' immediate offsets and no per-slice pointer
+// stays live.
 __device__ inline const cfloat* launder(const cfloat* p) {
   asm volatile("" : "+s"(p));
   return p;
 }
 
-// y[b] (+)= sgn * sum_t M[b*8 + t] x[t]: one 8x8 row-major basis slice,
-// consumed as two blocks of four rows (32 scalar operands live at a time).
+// y[b] (+)= sgn * sum_t M[b*8 + t] x[t], M = fb + off: one 8x8 row-major
+// basis slice, consumed as two blocks of four rows (32 scalar operands live
+// at a time).
 template <bool ACC>
-__device__ inline void mv(const float (&x)[8], const cfloat* M0, float sgn, float (&y)[8]) {
+__device__ inline void mv(const float (&x)[8], const cfloat* fb, int off, float sgn, float (&y)[8]) {
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const cfloat* M = launder(M0 + 32 * h);
+    const cfloat* M = launder(fb) + off + 32 * h;
 #pragma unroll
     for (int bb = 0; bb < 4; ++bb) {
       const int b = 4 * h + bb;
@@ -76,18 +80,18 @@ __device__ inline void mv(const float (&x)[8], const cfloat* M0, float sgn, floa
 
 // Complex product with three real products (Gauss):
 // (yr + i yi) = (MR + i MI)(xr + i xi), given the slices MR, MI and
-// MP = MR + MI (all row-major):  A = MR xr, B = MI xi, C = MP (xr + xi);
+// MP = MR + MI (all row-major, at offsets MR, MI, MP of fb):  A = MR xr,
+// B = MI xi, C = MP (xr + xi);
 // yr = A - B, yi = C - A - B.  MI may be negated through sgn_i (with MP the
 // matching sum) to apply a conjugate.
-__device__ inline void cmv(const float (&xr)[8], const float (&xi)[8], const cfloat* MR,
-                           const cfloat* MI, float sgn_i, const cfloat* MP, float (&yr)[8],
-                           float (&yi)[8]) {
+__device__ inline void cmv(const float (&xr)[8], const float (&xi)[8], const cfloat* fb, int MR,
+                           int MI, float sgn_i, int MP, float (&yr)[8], float (&yi)[8]) {
   float a[8], b[8], xs[8];
 #pragma unroll
   for (int t = 0; t < 8; ++t) xs[t] = xr[t] + xi[t];
-  mv<false>(xr, MR, 1.f, a);
-  mv<false>(xi, MI, sgn_i, b);
-  mv<false>(xs, MP, 1.f, yi);
+  mv<false>(xr, fb, MR, 1.f, a);
+  mv<false>(xi, fb, MI, sgn_i, b);
+  mv<false>(xs, fb, MP, 1.f, yi);
 #pragma unroll
   for (int t = 0; t < 8; ++t) {
     yr[t] = a[t] - b[t];
@@ -226,10 +230,10 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
 #pragma unroll
           for (int b = 0; b < 8; ++b) nf = fmaf(X[j][0][b], 0.f, nf);
           float y[8];
-          mv<false>(X[j][0], fb + FB_V0T, 1.f, y);   // y[b] = sum_t x[t] V[t][b]
+          mv<false>(X[j][0], fb, FB_V0T, 1.f, y);   // y[b] = sum_t x[t] V[t][b]
           transpose_rc(T, kl, a, y);
           float z[8];
-          mv<false>(y, fb + FB_U0T, 1.f, z);   // z[i] = sum_r y[r] U[r][i]
+          mv<false>(y, fb, FB_U0T, 1.f, z);   // z[i] = sum_r y[r] U[r][i]
 #pragma unroll
           for (int i = 0; i < 8; ++i) X[j][0][i] = z[i];
         } else {
@@ -244,24 +248,24 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
           }
           float y0[8], y1r[8], y1i[8];
           // Y = P^ V_F: f = 0 real, f = 1 complex (one real slice per pass)
-          mv<false>(f0, fb + FB_V0T, 1.f, y0);
+          mv<false>(f0, fb, FB_V0T, 1.f, y0);
           // y1 = V_F(1)^T P^(1) per row: (V1R + i V1I)^T (f1r + i f1i)
-          cmv(f1r, f1i, fb + FB_V1RT, fb + FB_V1IT, 1.f, fb + FB_V1PT, y1r, y1i);
+          cmv(f1r, f1i, fb, FB_V1RT, FB_V1IT, 1.f, FB_V1PT, y1r, y1i);
           transpose_rc(T, kl, a, y0);
           transpose_rc(T, kl, a, y1r);
           transpose_rc(T, kl, a, y1i);
           // Z = U_F^H Y: z[i] = sum_r conj(U[r][i]) y[r]
           float z0[8], z1r[8], z1i[8];
-          mv<false>(y0, fb + FB_U0T, 1.f, z0);
+          mv<false>(y0, fb, FB_U0T, 1.f, z0);
           // z1 = conj(U_F(1))^T y1: (U1R - i U1I)^T (y1r + i y1i)
-          cmv(y1r, y1i, fb + FB_U1RT, fb + FB_U1IT, -1.f, fb + FB_U1MT, z1r, z1i);
+          cmv(y1r, y1i, fb, FB_U1RT, FB_U1IT, -1.f, FB_U1MT, z1r, z1i);
 #pragma unroll
           for (int i = 0; i < 8; ++i) {
             const float sr = z1r[i], si = z1i[i];
-            // inverse DFT along the channel mode
-            X[j][0][i] = (z0[i] + 2.f * sr) * (1.f / 3.f);
-            X[j][1][i] = (z0[i] - sr - SQRT3 * si) * (1.f / 3.f);
-            X[j][2][i] = (z0[i] - sr + SQRT3 * si) * (1.f / 3.f);
+            // inverse DFT along the channel mode (its 1/3 is in the U slices)
+            X[j][0][i] = fmaf(2.f, sr, z0[i]);
+            X[j][1][i] = fmaf(-SQRT3, si, z0[i] - sr);
+            X[j][2][i] = fmaf(SQRT3, si, z0[i] - sr);
           }
         }
       }
@@ -360,9 +364,9 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
         float out[C][8];
         if (C == 1) {
           float y[8];
-          mv<false>(X[j][0], fb + FB_U0, 1.f, y);   // y[r] = sum_i U[r][i] s[i]
+          mv<false>(X[j][0], fb, FB_U0, 1.f, y);   // y[r] = sum_i U[r][i] s[i]
           transpose_cr(T, kl, a, y);
-          mv<false>(y, fb + FB_V0, 1.f, out[0]);    // out[b] = sum_c y[c] V[b][c]
+          mv<false>(y, fb, FB_V0, 1.f, out[0]);    // out[b] = sum_c y[c] V[b][c]
 #pragma unroll
           for (int b = 0; b < 8; ++b) out[0][b] *= fxs;   // fixed-point scale (a power of two)
         } else {
@@ -376,17 +380,17 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
           }
           // Y = U_F S^: y[r] = sum_i U[r][i] s[i]
           float y0[8], y1r[8], y1i[8];
-          mv<false>(s0, fb + FB_U0, 1.f, y0);
+          mv<false>(s0, fb, FB_U0, 1.f, y0);
           // y1 = U_F(1) s1: (U1R + i U1I)(s1r + i s1i)
-          cmv(s1r, s1i, fb + FB_U1R, fb + FB_U1I, 1.f, fb + FB_U1P, y1r, y1i);
+          cmv(s1r, s1i, fb, FB_U1R, FB_U1I, 1.f, FB_U1P, y1r, y1i);
           transpose_cr(T, kl, a, y0);
           transpose_cr(T, kl, a, y1r);
           transpose_cr(T, kl, a, y1i);
           // P^ = Y V_F^H: p[b] = sum_c y[c] conj(V[b][c])
           float p0[8], p1r[8], p1i[8];
-          mv<false>(y0, fb + FB_V0, 1.f, p0);
+          mv<false>(y0, fb, FB_V0, 1.f, p0);
           // p1 = conj(V_F(1)) y1 per row: (V1R - i V1I)(y1r + i y1i)
-          cmv(y1r, y1i, fb + FB_V1R, fb + FB_V1I, -1.f, fb + FB_V1M, p1r, p1i);
+          cmv(y1r, y1i, fb, FB_V1R, FB_V1I, -1.f, FB_V1M, p1r, p1i);
 #pragma unroll
           for (int b = 0; b < 8; ++b) {
             const float sr = p1r[b], si = p1i[b];

@@ -479,6 +479,7 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
           const unsigned loc = (unsigned)(key & 0xFFFu);
           const int cy = Y0 + ty0 + (int)(loc >> 6), cx = X0 + tx0 + (int)(loc & 63u);
           d.idx[(size_t)ref * K + 1 + g] = cy * d.W + cx;
+          if (L.count_hist) atomicAdd(d.hist + cy * d.W + cx, 1);
           if (d.dist) d.dist[(size_t)ref * K + 1 + g] = (long long)(key >> 12);
         };
         // Keys (distance << 12 | window index) are distinct: the rank of a
@@ -511,6 +512,7 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
         }
         if (lane == 0) {
           d.idx[(size_t)ref * K] = (Y0 + py0) * d.W + X0 + px0;
+          if (L.count_hist) atomicAdd(d.hist + (Y0 + py0) * d.W + X0 + px0, 1);
           if (d.dist) d.dist[(size_t)ref * K] = 0;
         }
       }
@@ -589,11 +591,14 @@ __global__ __launch_bounds__(256) void k_match_fallback(Launch L) {
         }
       for (int i = tid; i < K - 1; i += 256) {
         const unsigned loc = (unsigned)(keys[i] & 0xFFFu);
-        d.idx[(size_t)ref * K + 1 + i] = (y0 + (int)(loc >> 6)) * d.W + x0 + (int)(loc & 63u);
+        const int pos = (y0 + (int)(loc >> 6)) * d.W + x0 + (int)(loc & 63u);
+        d.idx[(size_t)ref * K + 1 + i] = pos;
+        if (L.count_hist) atomicAdd(d.hist + pos, 1);
         if (d.dist) d.dist[(size_t)ref * K + 1 + i] = (long long)(keys[i] >> 12);
       }
       if (tid == 0) {
         d.idx[(size_t)ref * K] = ry * d.W + rx;
+        if (L.count_hist) atomicAdd(d.hist + ry * d.W + rx, 1);
         if (d.dist) d.dist[(size_t)ref * K] = 0;
       }
     }

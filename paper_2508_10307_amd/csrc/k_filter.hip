@@ -61,7 +61,10 @@ __device__ inline const cfloat* launder(const cfloat* p) {
 
 // y[b] (+)= sgn * sum_t M[b*8 + t] x[t], M = fb + off: one 8x8 row-major
 // basis slice, consumed as two blocks of four rows (32 scalar operands live
-// at a time).
+// at a time).  Each block's four results pass through an empty asm: that
+// pins the block's FMAs between its own pointer launder and the next one,
+// so the compiler cannot gather the loads of several blocks ahead of their
+// FMAs (which would again spill coefficients into VGPR lanes).
 template <bool ACC>
 __device__ inline void mv(const float (&x)[8], const cfloat* fb, int off, float sgn, float (&y)[8]) {
 #pragma unroll
@@ -75,6 +78,7 @@ __device__ inline void mv(const float (&x)[8], const cfloat* fb, int off, float 
       for (int t = 0; t < 8; ++t) s = fmaf(sgn * x[t], M[bb * 8 + t], s);
       y[b] = s;
     }
+    asm volatile("" : "+v"(y[4 * h]), "+v"(y[4 * h + 1]), "+v"(y[4 * h + 2]), "+v"(y[4 * h + 3]));
   }
 }
 

@@ -76,10 +76,12 @@ __device__ inline int ref_coord(int i, int s, int n_valid) { return min(i * s, n
 // with 32 fractional bits: integer additions are exact, so sums do not
 // depend on the order in which work groups add them.  fx_from_float is
 // exact for |v| < 2^24 up to the 2^-32 step and saturates beyond +-2^31.
+// (integer part floor(v) by v_cvt_flr_i32_f32, fraction v - floor(v) by
+// v_fract_f32, which keeps it below 1)
 __device__ inline unsigned long long fx_from_float(float v) {
-  const float fl = floorf(v);
-  const int hi = (int)fl;
-  const unsigned lo = (unsigned)((v - fl) * 4294967296.0f);
+  int hi;
+  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(hi) : "v"(v));
+  const unsigned lo = (unsigned)(__builtin_amdgcn_fractf(v) * 4294967296.0f);
   return ((unsigned long long)(unsigned)hi << 32) + lo;
 }
 __device__ inline double fx_to_double(unsigned long long x) {

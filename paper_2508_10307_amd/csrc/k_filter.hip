@@ -125,6 +125,15 @@ __device__ inline void transpose_cr(float* T, int kl, int a, float (&v)[8]) {
   wave_sync();
 }
 
+// Value of the lane with slot lane kl ^ m (lane ^ 8m): a DPP rotation by 8
+// within each 16-lane row for m = 1, ds_bpermute beyond.
+__device__ inline float xor_slot_lane(float v, int m) {
+  if (m == 1)
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128 /* row_ror:8 */,
+                                                      0xF, 0xF, false));
+  return __shfl_xor(v, 8 * m, 64);
+}
+
 // Haar row (Eq. 9 ordering) of the coefficient produced for group slot k.
 __device__ inline int haar_row(int k, int K) {
   if (k == 0) return 0;
@@ -157,7 +166,7 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int kl = lane >> 3, a = lane & 7;
   const int K = L.K;
-  const int NL = K < 8 ? K : 8;         // slot lanes in use
+  const int NL = SPL > 1 ? 8 : (K < 8 ? K : 8);   // slot lanes in use (all eight for K >= 16)
   const bool active = SPL > 1 || kl < NL;   // K >= 16 keeps every lane busy
   const int r = (L.window - 1) / 2;
   const int s = L.stride;
@@ -288,17 +297,18 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
               X[j + st][ch][i] = u - v;
             }
       // cross-lane levels on the running sums (slot lanes kl ^ m)
+#pragma unroll
       for (int m = 1; m < NL; m <<= 1) {
         const bool part = (kl & (m - 1)) == 0;
         const float sg = (kl & m) ? -1.f : 1.f;   // upper lane: o - x, lower: x + o
+        // lanes outside the level keep their coefficients (exec mask, not a
+        // select); partners of active lanes are active
+        if (part) {
 #pragma unroll
-        for (int ch = 0; ch < C; ++ch)
+          for (int ch = 0; ch < C; ++ch)
 #pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            const float o = __shfl_xor(X[0][ch][i], 8 * m, 64);
-            const float nv = fmaf(sg, X[0][ch][i], o);
-            X[0][ch][i] = part ? nv : X[0][ch][i];
-          }
+            for (int i = 0; i < 8; ++i) X[0][ch][i] = fmaf(sg, X[0][ch][i], xor_slot_lane(X[0][ch][i], m));
+        }
       }
 
       // ---- hard threshold (Eq. 19) or frozen mask; optional mask export ----
@@ -336,17 +346,18 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
       }
 
       // ---- inverse Haar: cross-lane levels (coarse first), then in-lane ----
+#pragma unroll
       for (int m = NL >> 1; m >= 1; m >>= 1) {
         const bool part = (kl & (m - 1)) == 0;
         const float sg = (kl & m) ? -1.f : 1.f;
+        // lanes outside the level keep their coefficients (exec mask, not a
+        // select); partners of active lanes are active
+        if (part) {
 #pragma unroll
-        for (int ch = 0; ch < C; ++ch)
+          for (int ch = 0; ch < C; ++ch)
 #pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            const float o = __shfl_xor(X[0][ch][i], 8 * m, 64);
-            const float nv = fmaf(sg, X[0][ch][i], o);
-            X[0][ch][i] = part ? nv : X[0][ch][i];
-          }
+            for (int i = 0; i < 8; ++i) X[0][ch][i] = fmaf(sg, X[0][ch][i], xor_slot_lane(X[0][ch][i], m));
+        }
       }
 #pragma unroll
       for (int st = SPL >> 1; st >= 1; st >>= 1)

@@ -93,24 +93,26 @@ struct Launch {
 // blocks) and the pixel region they read.
 struct MatchGeom {
   int ryc, rxp, pitch, rows;   // max candidate rows, padded candidate cols, LDS pitch, pixel rows
-  int off_gi, off_gb, off_nb, off_sb, off_tl, off_sl, off_misc, bytes;
+  int rgn, nbsz, plane_bytes;  // bytes of one staged region, of one norm array, of one plane slot
+  int off_tl, off_misc, bytes;
 };
-__host__ __device__ inline MatchGeom match_geom(int s, int w) {
+// LDS of the match: npl plane slots of [gi][gb][|b|^2][|b|], then the
+// list values of pass 1, which the shortlist of pass 2 reuses (the lists
+// are dead once T is known), then per-reference data.
+__host__ __device__ inline MatchGeom match_geom(int s, int w, int npl) {
   MatchGeom g;
   int r = (w - 1) / 2;
   g.ryc = (MATCH_TY - 1) * s + 2 * r + 1;
   int rxc = (MATCH_TX - 1) * s + 2 * r + 1;
   g.rxp = (rxc + 15) / 16 * 16;
-  g.pitch = g.rxp + 8;
+  g.pitch = g.rxp + PS - 1;
   g.rows = g.ryc + PS - 1;
-  int rgn = g.rows * g.pitch * 4;
-  g.off_gi = 0;
-  g.off_gb = g.off_gi + rgn;
-  g.off_nb = g.off_gb + rgn;
-  g.off_sb = g.off_nb + g.ryc * g.rxp * 4;
-  g.off_tl = g.off_sb + g.ryc * g.rxp * 4;
-  g.off_sl = g.off_tl + 16 * 64 * 2 * 4;
-  g.off_misc = g.off_sl + 16 * SHORT_CAP * 4;
+  g.rgn = g.rows * g.pitch * 4;
+  g.nbsz = g.ryc * g.rxp * 4;
+  g.plane_bytes = 2 * g.rgn + 2 * g.nbsz;
+  g.off_tl = npl * g.plane_bytes;
+  const int lists = 16 * 64 * 2 * 4, shortlist = 16 * SHORT_CAP * 4;
+  g.off_misc = g.off_tl + (lists > shortlist ? lists : shortlist);
   g.bytes = g.off_misc + 1024;
   return g;
 }
@@ -156,6 +158,6 @@ hipError_t launch_filter_mfma(const Launch& L, int ty, int tx, int adjoint, int 
 
 // Filter LDS bytes for a tile shape.
 size_t filter_lds_bytes(int C, int K, int stride, int window, int ty, int tx);
-size_t match_lds_bytes(int stride, int window);
+size_t match_lds_bytes(int stride, int window);   // one plane slot: the minimum
 
 }  // namespace hts

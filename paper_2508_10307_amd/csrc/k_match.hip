@@ -61,16 +61,28 @@ __device__ inline unsigned split_pack(float v) {
 // two passes (CACHE = 1): 36 covers windows up to 39 at stride 2 or 3.
 constexpr int MAXBW = 36;
 
-template <int MODE, int TERMS, int CACHE>
+// NPL = 2 stages both guide planes of an RGB tile at once, so a tile whose
+// references use both planes runs the distance passes once (every reference
+// against its own plane: the A operand of a reference is zero in the
+// products of the other plane); NPL = 1 runs the planes one after the other
+// (windows too large for two plane slots in LDS).
+template <int MODE, int TERMS, int CACHE, int NPL>
 __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const MatchGeom G = match_geom(L.stride, L.window);
-  int* gi = (int*)(smem + G.off_gi);
-  unsigned* gb = (unsigned*)(smem + G.off_gb);
-  float* nbf = (float*)(smem + G.off_nb);
-  float* sbf = (float*)(smem + G.off_sb);
+  const MatchGeom G = match_geom(L.stride, L.window, NPL);
+  // plane slot q: staged guide (int), its bf16 split or float form, |b|^2, |b|
+  auto GI = [&](int q) __attribute__((always_inline)) { return (int*)(smem + q * G.plane_bytes); };
+  auto GB = [&](int q) __attribute__((always_inline)) {
+    return (unsigned*)(smem + q * G.plane_bytes + G.rgn);
+  };
+  auto NB = [&](int q) __attribute__((always_inline)) {
+    return (float*)(smem + q * G.plane_bytes + 2 * G.rgn);
+  };
+  auto SB = [&](int q) __attribute__((always_inline)) {
+    return (float*)(smem + q * G.plane_bytes + 2 * G.rgn + G.nbsz);
+  };
   float* tl = (float*)(smem + G.off_tl);
-  unsigned* sl = (unsigned*)(smem + G.off_sl);
+  unsigned* sl = (unsigned*)(smem + G.off_tl);     // reuses tl once T is known
   int* rinfo = (int*)(smem + G.off_misc);          // [16][8]
   float* rnorm = (float*)(rinfo + 128);            // [16][2] |a|^2, |a|
   float* Tp = rnorm + 32;                          // [16]
@@ -118,33 +130,49 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
 #pragma unroll
     for (int t = 0; t < 16; ++t) pmask |= rinfo[t * 8];
 
-    for (int p = 0; p < 2; ++p) {
-      if (!(pmask & (1 << p))) continue;
+    for (int p = 0; p < 2; p += NPL) {
+      // planes of this pass (bit q: guide plane q) and the slot of plane q
+      const int pm = __builtin_amdgcn_readfirstlane(pmask & (NPL == 2 ? 3 : 1 << p));
+      if (!pm) continue;
+      auto slot = [&](int q) __attribute__((always_inline)) { return NPL == 2 ? q : 0; };
       __syncthreads();  // the previous plane's re-rank still reads the LDS region
-      const int* gsrc = d.gplanes + (size_t)p * d.H * d.W;
 
-      // ---- stage the region, centred by an integer offset m ----
-      // Any integer m leaves every distance unchanged; the floor of the mean
-      // of a 16 x 16 sample of the region keeps the centred values (and with
-      // them the error bounds) small.  Columns past the image read as 0.
-      int m;
+      // ---- stage the region, centred by an integer offset per plane ----
+      // Any integer offset leaves every distance unchanged; the floor of the
+      // mean of a 16 x 16 sample of the region keeps the centred values (and
+      // with them the error bounds) small.  Columns past the image read as 0.
+      int moff[2] = {0, 0};
       {
         const int sy = (tid >> 4) * rows / 16;
         const int sx = min((tid & 15) * cols / 16, d.W - 1 - X0);
-        int v = gsrc[(Y0 + sy) * d.W + X0 + sx];   // |v| < 3 * 2^20: the sum fits int32
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
         int* part = (int*)Tp;   // free until the threshold step
-        if (lane == 0) part[wave] = v;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          if (!((pm >> q) & 1)) continue;
+          // |v| < 3 * 2^20: the sum fits int32
+          int v = d.gplanes[(size_t)q * d.H * d.W + (Y0 + sy) * d.W + X0 + sx];
+#pragma unroll
+          for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+          if (lane == 0) part[4 * q + wave] = v;
+        }
         __syncthreads();
-        m = (part[0] + part[1] + part[2] + part[3]) >> 8;   // floor(sum / 256)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+          moff[q] = (part[4 * q] + part[4 * q + 1] + part[4 * q + 2] + part[4 * q + 3]) >> 8;
       }
-      for (int y = wave; y < rows; y += 4) {
-        const int* srow = gsrc + (Y0 + y) * d.W + X0;
-        for (int x = lane; x < cols; x += 64) {
-          const int v = X0 + x < d.W ? srow[x] - m : 0;
-          gi[y * pitch + x] = v;
-          gb[y * pitch + x] = MODE == 0 ? split_pack((float)v) : __float_as_uint((float)v);
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        if (!((pm >> q) & 1)) continue;
+        const int* gsrc = d.gplanes + (size_t)q * d.H * d.W;
+        int* gi = GI(slot(q));
+        unsigned* gb = GB(slot(q));
+        for (int y = wave; y < rows; y += 4) {
+          const int* srow = gsrc + (Y0 + y) * d.W + X0;
+          for (int x = lane; x < cols; x += 64) {
+            const int v = X0 + x < d.W ? srow[x] - moff[q] : 0;
+            gi[y * pitch + x] = v;
+            gb[y * pitch + x] = MODE == 0 ? split_pack((float)v) : __float_as_uint((float)v);
+          }
         }
       }
       __syncthreads();
@@ -154,34 +182,41 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
       // a sliding sum down the rows, in FP64 (exact: |v| < 2^22, sums < 2^50).
       if (MODE == 0) {
         const int nseg = (RYc + 7) >> 3;
-        for (int task = tid; task < RXP * nseg; task += 256) {
-          const int cx = task % RXP, c0 = (task / RXP) * 8;
-          double rs[15];
 #pragma unroll
-          for (int j = 0; j < 15; ++j) {
-            const int y = c0 + j;
-            double a = 0.0;
-            if (y < rows) {
+        for (int q = 0; q < 2; ++q) {
+          if (!((pm >> q) & 1)) continue;
+          const int* gi = GI(slot(q));
+          float* nbf = NB(slot(q));
+          float* sbf = SB(slot(q));
+          for (int task = tid; task < RXP * nseg; task += 256) {
+            const int cx = task % RXP, c0 = (task / RXP) * 8;
+            double rs[15];
 #pragma unroll
-              for (int b = 0; b < PS; ++b) {
-                const double v = (double)gi[y * pitch + cx + b];
-                a = fma(v, v, a);
+            for (int j = 0; j < 15; ++j) {
+              const int y = c0 + j;
+              double a = 0.0;
+              if (y < rows) {
+#pragma unroll
+                for (int b = 0; b < PS; ++b) {
+                  const double v = (double)gi[y * pitch + cx + b];
+                  a = fma(v, v, a);
+                }
               }
+              rs[j] = a;
             }
-            rs[j] = a;
-          }
-          double nn = 0.0;
+            double nn = 0.0;
 #pragma unroll
-          for (int j = 0; j < 8; ++j) nn += rs[j];
+            for (int j = 0; j < 8; ++j) nn += rs[j];
 #pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const int cy = c0 + j;
-            if (cy < RYc) {
-              const float f = (float)nn;
-              nbf[cy * RXP + cx] = f;
-              sbf[cy * RXP + cx] = sqrtf(f);
+            for (int j = 0; j < 8; ++j) {
+              const int cy = c0 + j;
+              if (cy < RYc) {
+                const float f = (float)nn;
+                nbf[cy * RXP + cx] = f;
+                sbf[cy * RXP + cx] = sqrtf(f);
+              }
+              if (j < 7) nn += rs[j + 8] - rs[j];
             }
-            if (j < 7) nn += rs[j + 8] - rs[j];
           }
         }
         __syncthreads();
@@ -190,7 +225,7 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
       if (tid < 16) {
         const int* ri = rinfo + tid * 8;
         float na = 0.f;
-        if (MODE == 0 && (ri[0] & (1 << p))) na = nbf[ri[1] * RXP + ri[2]];
+        if (MODE == 0 && (ri[0] & pm)) na = NB(slot((ri[0] >> 1) & 1))[ri[1] * RXP + ri[2]];
         rnorm[2 * tid] = na;
         rnorm[2 * tid + 1] = sqrtf(na);
       }
@@ -199,8 +234,8 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
       // ---- per-lane reference state: references 4*kq + i, candidate column n ----
       // Reference 4*kq + i sits in tile row kq, so its window rows depend on
       // kq only; its window columns, as [wx0, wx0 + wxl) (wxl = 0 when the
-      // reference does not use this plane).
-      int rpx[4], wx0[4];
+      // reference uses neither plane of this pass); rq = the slot of its plane.
+      int rpx[4], wx0[4], rq[4];
       unsigned wxl[4];
       float na[4], sa[4];
       const int rpy = rinfo[(4 * kq) * 8 + 1];
@@ -211,29 +246,34 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
         const int* ri = rinfo + (4 * kq + i) * 8;
         rpx[i] = ri[2];
         wx0[i] = ri[5];
-        wxl[i] = ((ri[0] >> p) & 1) ? (unsigned)(ri[6] - ri[5] + 1) : 0u;
+        wxl[i] = (ri[0] & pm) ? (unsigned)(ri[6] - ri[5] + 1) : 0u;
+        rq[i] = slot((ri[0] >> 1) & 1);
         na[i] = rnorm[2 * (4 * kq + i)];
         sa[i] = rnorm[2 * (4 * kq + i) + 1];
       }
-      // A operand: reference n, patch rows 4h + kq (MFMA 16x16x32 layout).
-      bf16x8 Ahi[2], Alo[2];
+      // A operand per plane slot: reference n, patch rows 4h + kq (MFMA
+      // 16x16x32 layout); zero in the slot of the plane it does not use.
+      bf16x8 Ahi[NPL][2], Alo[NPL][2];
       if (MODE == 0) {
         const int* ri = rinfo + n * 8;
-        const bool ok = (ri[0] >> p) & 1;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const unsigned* src = gb + (ri[1] + 4 * h + kq) * pitch + ri[2];
-          unsigned w[8];
+        for (int sq = 0; sq < NPL; ++sq) {
+          const bool ok = (ri[0] & pm) && slot((ri[0] >> 1) & 1) == sq;
 #pragma unroll
-          for (int b = 0; b < 8; ++b) w[b] = ok ? src[b] : 0u;
-          uintx4 hi, lo;
+          for (int h = 0; h < 2; ++h) {
+            const unsigned* src = GB(sq) + (ri[1] + 4 * h + kq) * pitch + ri[2];
+            unsigned w[8];
 #pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            hi[b] = __builtin_amdgcn_perm(w[2 * b + 1], w[2 * b], 0x05040100u);
-            lo[b] = __builtin_amdgcn_perm(w[2 * b + 1], w[2 * b], 0x07060302u);
+            for (int b = 0; b < 8; ++b) w[b] = ok ? src[b] : 0u;
+            uintx4 hi, lo;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+              hi[b] = __builtin_amdgcn_perm(w[2 * b + 1], w[2 * b], 0x05040100u);
+              lo[b] = __builtin_amdgcn_perm(w[2 * b + 1], w[2 * b], 0x07060302u);
+            }
+            Ahi[sq][h] = __builtin_bit_cast(bf16x8, hi);
+            Alo[sq][h] = __builtin_bit_cast(bf16x8, lo);
           }
-          Ahi[h] = __builtin_bit_cast(bf16x8, hi);
-          Alo[h] = __builtin_bit_cast(bf16x8, lo);
         }
       }
 
@@ -243,42 +283,57 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
       auto tile_dist = [&](int cy, int cx, float (&dt)[4], float (&E)[4], bool (&ok)[4])
           __attribute__((always_inline)) {
         if (MODE == 0) {
+          // every reference against its own plane: the slots' products add
           floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+          float nbq[NPL], sbq[NPL];
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const unsigned* src = gb + (cy + 4 * h + kq) * pitch + cx;
-            unsigned w[8];
+          for (int sq = 0; sq < NPL; ++sq) {
+            nbq[sq] = sbq[sq] = 0.f;
+            if (NPL == 2 && !((pm >> sq) & 1)) continue;
 #pragma unroll
-            for (int b = 0; b < 8; ++b) w[b] = src[b];
-            uintx4 hi, lo;
+            for (int h = 0; h < 2; ++h) {
+              const unsigned* src = GB(sq) + (cy + 4 * h + kq) * pitch + cx;
+              unsigned w[8];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-              hi[b] = __builtin_amdgcn_perm(w[2 * b + 1], w[2 * b], 0x05040100u);
-              lo[b] = __builtin_amdgcn_perm(w[2 * b + 1], w[2 * b], 0x07060302u);
+              for (int b = 0; b < 8; ++b) w[b] = src[b];
+              uintx4 hi, lo;
+#pragma unroll
+              for (int b = 0; b < 4; ++b) {
+                hi[b] = __builtin_amdgcn_perm(w[2 * b + 1], w[2 * b], 0x05040100u);
+                lo[b] = __builtin_amdgcn_perm(w[2 * b + 1], w[2 * b], 0x07060302u);
+              }
+              const bf16x8 Bhi = __builtin_bit_cast(bf16x8, hi);
+              acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ahi[sq][h], Bhi, acc, 0, 0, 0);
+              if (TERMS == 3) {
+                const bf16x8 Blo = __builtin_bit_cast(bf16x8, lo);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ahi[sq][h], Blo, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Alo[sq][h], Bhi, acc, 0, 0, 0);
+              }
             }
-            const bf16x8 Bhi = __builtin_bit_cast(bf16x8, hi);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ahi[h], Bhi, acc, 0, 0, 0);
-            if (TERMS == 3) {
-              const bf16x8 Blo = __builtin_bit_cast(bf16x8, lo);
-              acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ahi[h], Blo, acc, 0, 0, 0);
-              acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Alo[h], Bhi, acc, 0, 0, 0);
-            }
+            nbq[sq] = NB(sq)[cy * RXP + cx];
+            sbq[sq] = SB(sq)[cy * RXP + cx];
           }
-          const float nb = nbf[cy * RXP + cx], sb = sbf[cy * RXP + cx];
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
+            const float nb = NPL == 2 && rq[i] ? nbq[NPL - 1] : nbq[0];
+            const float sb = NPL == 2 && rq[i] ? sbq[NPL - 1] : sbq[0];
             dt[i] = (na[i] + nb) - 2.0f * acc[i];
             E[i] = DotBound<TERMS>::C1 * sa[i] * sb + BOUND_C2 * (na[i] + nb) + BOUND_ABS;
           }
         } else {
           float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
           for (int py = 0; py < PS; ++py) {
 #pragma unroll
             for (int px = 0; px < PS; ++px) {
-              const float bv = __uint_as_float(gb[(cy + py) * pitch + cx + px]);
+              float bq[NPL];
+#pragma unroll
+              for (int sq = 0; sq < NPL; ++sq)
+                bq[sq] = __uint_as_float(GB(sq)[(cy + py) * pitch + cx + px]);
 #pragma unroll
               for (int i = 0; i < 4; ++i) {
-                const float av = __uint_as_float(gb[(rpy + py) * pitch + rpx[i] + px]);
+                const float bv = NPL == 2 && rq[i] ? bq[NPL - 1] : bq[0];
+                const float av = __uint_as_float(GB(rq[i])[(rpy + py) * pitch + rpx[i] + px]);
                 const float df = av - bv;
                 acc[i] = fmaf(df, df, acc[i]);
               }
@@ -362,7 +417,7 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
       // #{values < t} <= K-2, i.e. the (K-1)-th smallest value; it is built
       // bit by bit from the top, counting with ballots.
       for (int t = wv; t < 16; t += 4) {
-        if (!((rinfo[t * 8] >> p) & 1)) continue;
+        if (!(rinfo[t * 8] & pm)) continue;
         const unsigned v0 = __float_as_uint(tl[t * 128 + lane]);
         const unsigned v1 = __float_as_uint(tl[t * 128 + 64 + lane]);
         const int g = K - 2;
@@ -435,8 +490,9 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
       // product and partial sum (< 2^50) is an exact integer.
       for (int t = wv; t < 16; t += 4) {
         const int* ri = rinfo + t * 8;
-        if (!((ri[0] >> p) & 1)) continue;
+        if (!(ri[0] & pm)) continue;
         const int ref = ri[7];
+        const int* gi = GI(slot((ri[0] >> 1) & 1));   // the reference's guide plane
         const int nsl = __builtin_amdgcn_readfirstlane(scount[t]);
         if (nsl > SHORT_CAP || nsl < K - 1) {
           if (lane == 0) d.fb_list[atomicAdd(d.fb_count, 1)] = ref;
@@ -605,17 +661,29 @@ __global__ __launch_bounds__(256) void k_match_fallback(Launch L) {
   }
 }
 
-size_t match_lds_bytes(int stride, int window) { return (size_t)match_geom(stride, window).bytes; }
+size_t match_lds_bytes(int stride, int window) { return (size_t)match_geom(stride, window, 1).bytes; }
+
+// Two plane slots when the image has two guide planes and they fit beside
+// a second work group on the CU (160 KB of LDS).
+static int match_planes(int C, int stride, int window) {
+  return C == 3 && match_geom(stride, window, 2).bytes <= 80 * 1024 ? 2 : 1;
+}
 
 hipError_t launch_match(const Launch& L, int mode, int terms, int grid, hipStream_t s) {
   if (L.total <= 0) return hipSuccess;
   const int g = xcd_grid(grid > 0 && grid < L.total ? grid : L.total);
-  const size_t lds = match_lds_bytes(L.stride, L.window);
-  const MatchGeom G = match_geom(L.stride, L.window);
+  const int npl = match_planes(L.C, L.stride, L.window);
+  const MatchGeom G = match_geom(L.stride, L.window, npl);
+  const size_t lds = (size_t)G.bytes;
   const bool cache = (G.ryc * (G.rxp / 16) + 3) / 4 <= MAXBW;
-#define HTS_KM(M, T)                                                                      \
-  if (cache) hipLaunchKernelGGL((k_match<M, T, 1>), dim3(g), dim3(256), lds, s, L);       \
-  else hipLaunchKernelGGL((k_match<M, T, 0>), dim3(g), dim3(256), lds, s, L);
+#define HTS_KM(M, T)                                                                          \
+  if (npl == 2) {                                                                             \
+    if (cache) hipLaunchKernelGGL((k_match<M, T, 1, 2>), dim3(g), dim3(256), lds, s, L);      \
+    else hipLaunchKernelGGL((k_match<M, T, 0, 2>), dim3(g), dim3(256), lds, s, L);            \
+  } else {                                                                                    \
+    if (cache) hipLaunchKernelGGL((k_match<M, T, 1, 1>), dim3(g), dim3(256), lds, s, L);      \
+    else hipLaunchKernelGGL((k_match<M, T, 0, 1>), dim3(g), dim3(256), lds, s, L);            \
+  }
   if (mode == HTS_MATCH_FP32) {
     HTS_KM(1, 1)
   } else if (terms == 1) {

@@ -105,7 +105,7 @@ __host__ __device__ inline MatchGeom match_geom(int s, int w, int npl) {
   g.ryc = (MATCH_TY - 1) * s + 2 * r + 1;
   int rxc = (MATCH_TX - 1) * s + 2 * r + 1;
   g.rxp = (rxc + 15) / 16 * 16;
-  g.pitch = g.rxp + PS - 1;
+  g.pitch = g.rxp + PS;          // = 8 (mod 16): see the A/B operand rows of the match
   g.rows = g.ryc + PS - 1;
   g.rgn = g.rows * g.pitch * 4;
   g.nbsz = g.ryc * g.rxp * 4;
@@ -113,7 +113,7 @@ __host__ __device__ inline MatchGeom match_geom(int s, int w, int npl) {
   g.off_tl = npl * g.plane_bytes;
   const int lists = 16 * 64 * 2 * 4, shortlist = 16 * SHORT_CAP * 4;
   g.off_misc = g.off_tl + (lists > shortlist ? lists : shortlist);
-  g.bytes = g.off_misc + 1024;
+  g.bytes = g.off_misc + 768;    // rinfo [16][8], rnorm [16][2], Tp [16], scount [16]
   return g;
 }
 

@@ -251,8 +251,11 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
         na[i] = rnorm[2 * (4 * kq + i)];
         sa[i] = rnorm[2 * (4 * kq + i) + 1];
       }
-      // A operand per plane slot: reference n, patch rows 4h + kq (MFMA
-      // 16x16x32 layout); zero in the slot of the plane it does not use.
+      // A operand per plane slot: reference n, patch rows 2kq + h (MFMA
+      // 16x16x32 layout: k = 8 kq + column); zero in the slot of the plane it
+      // does not use.  Rows 2kq + h put the four kq lane groups 2 * pitch
+      // apart, which with pitch = 8 (mod 16) spreads their 16-word reads over
+      // disjoint LDS banks.
       bf16x8 Ahi[NPL][2], Alo[NPL][2];
       if (MODE == 0) {
         const int* ri = rinfo + n * 8;
@@ -261,7 +264,7 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
           const bool ok = (ri[0] & pm) && slot((ri[0] >> 1) & 1) == sq;
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
-            const unsigned* src = GB(sq) + (ri[1] + 4 * h + kq) * pitch + ri[2];
+            const unsigned* src = GB(sq) + (ri[1] + 2 * kq + h) * pitch + ri[2];
             unsigned w[8];
 #pragma unroll
             for (int b = 0; b < 8; ++b) w[b] = ok ? src[b] : 0u;
@@ -292,7 +295,7 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
             if (NPL == 2 && !((pm >> sq) & 1)) continue;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-              const unsigned* src = GB(sq) + (cy + 4 * h + kq) * pitch + cx;
+              const unsigned* src = GB(sq) + (cy + 2 * kq + h) * pitch + cx;
               unsigned w[8];
 #pragma unroll
               for (int b = 0; b < 8; ++b) w[b] = src[b];

@@ -104,11 +104,15 @@ __host__ __device__ inline MatchGeom match_geom(int s, int w, int npl) {
   int r = (w - 1) / 2;
   g.ryc = (MATCH_TY - 1) * s + 2 * r + 1;
   int rxc = (MATCH_TX - 1) * s + 2 * r + 1;
-  g.rxp = (rxc + 15) / 16 * 16;
-  g.pitch = g.rxp + PS;          // = 8 (mod 16): see the A/B operand rows of the match
-  g.rows = g.ryc + PS - 1;
+  g.rxp = (rxc + 7) / 8 * 8;           // candidate columns in blocks of 8
+  const int ry2 = (g.ryc + 1) / 2 * 2;  // candidate rows in blocks of 2
+  // pitch = 8 (mod 16), at least the staged columns: see the A/B operand
+  // rows of the match
+  g.pitch = g.rxp + PS - 1;
+  g.pitch += ((8 - g.pitch) % 16 + 16) % 16;
+  g.rows = ry2 + PS - 1;
   g.rgn = g.rows * g.pitch * 4;
-  g.nbsz = g.ryc * g.rxp * 4;
+  g.nbsz = ry2 * g.rxp * 4;
   g.plane_bytes = 2 * g.rgn + 2 * g.nbsz;
   g.off_tl = npl * g.plane_bytes;
   const int lists = 16 * 64 * 2 * 4, shortlist = 16 * SHORT_CAP * 4;

@@ -103,7 +103,8 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
     const int X0 = max(0, ref_coord(ix0, s, d.Wp) - r);
     const int X1 = min(d.Wp - 1, ref_coord(ix1, s, d.Wp) + r);
     const int RYc = Y1 - Y0 + 1, RXc = X1 - X0 + 1;
-    const int NXB = (RXc + 15) >> 4, RXP = NXB * 16;
+    // candidate blocks of 2 rows x 8 columns (one MFMA column each)
+    const int NYB = (RYc + 1) >> 1, NXB = (RXc + 7) >> 3, RXP = NXB * 8;
     const int rows = RYc + PS - 1, cols = RXP + PS - 1;
     const int pitch = G.pitch;
 
@@ -174,6 +175,14 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
             gb[y * pitch + x] = MODE == 0 ? split_pack((float)v) : __float_as_uint((float)v);
           }
         }
+        // the row below the region, read by the last block row when RYc is
+        // odd (then it lies inside the allocation, which has rows for an
+        // even number of candidate rows)
+        if (RYc & 1)
+          for (int x = tid; x < cols; x += 256) {
+            gi[rows * pitch + x] = 0;
+            gb[rows * pitch + x] = 0u;
+          }
       }
       __syncthreads();
 
@@ -355,16 +364,20 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
           ok[i] = cy_ok & ((unsigned)(cx - wx0[i]) < wxl[i]) & !(cy_self & (cx == rpx[i]));
       };
 
-      // Blocks (candidate row cy, 16-column block xb) are dealt round-robin to
-      // the wavefronts; (cy, xb) advance by 4 blocks without a division.
+      // Blocks (candidate rows 2yb, 2yb + 1 x columns 8xb .. 8xb + 7; lane n
+      // takes row 2yb + n / 8, column 8xb + n % 8) are dealt round-robin to
+      // the wavefronts; (yb, xb) advance by 4 blocks without a division.
+      // Blocks of 8 columns pad the candidate columns to a multiple of 8
+      // (40 at w = 31, s = 3) instead of 16.
       const int wv = __builtin_amdgcn_readfirstlane(wave);
-      const int nblocks = RYc * NXB;
+      const int nblocks = NYB * NXB;
       const int nbw = nblocks > wv ? (nblocks - wv + 3) >> 2 : 0;
-      const int cy0 = wv / NXB, xb0 = wv - cy0 * NXB;
-      auto step = [&](int& cy, int& xb) __attribute__((always_inline)) {
+      const int yb0 = wv / NXB, xb0 = wv - yb0 * NXB;
+      auto step = [&](int& yb, int& xb) __attribute__((always_inline)) {
         xb += 4;
-        while (xb >= NXB) { xb -= NXB; ++cy; }
+        while (xb >= NXB) { xb -= NXB; ++yb; }
       };
+      const int cyn = n >> 3, cxn = n & 7;   // this lane's candidate within a block
       constexpr unsigned INFB = 0x7f800000u;   // +inf
 
       // ---- pass 1: two smallest upper bounds per (lane, reference) ----
@@ -375,10 +388,10 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
       // register; 0xFFFF marks a non-candidate.
       unsigned m0[4] = {INFB, INFB, INFB, INFB}, m1[4] = {INFB, INFB, INFB, INFB};
       unsigned lbc[CACHE ? MAXBW : 1][2];
-      auto pass1 = [&](int cy, int xb, unsigned (&lbw)[2]) __attribute__((always_inline)) {
+      auto pass1 = [&](int yb, int xb, unsigned (&lbw)[2]) __attribute__((always_inline)) {
         float dt[4], E[4];
         bool ok[4];
-        tile_dist(cy, xb * 16 + n, dt, E, ok);
+        tile_dist(2 * yb + cyn, 8 * xb + cxn, dt, E, ok);
         unsigned lh[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -391,18 +404,18 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
         lbw[1] = lh[2] | (lh[3] << 16);
       };
       {
-        int cy = cy0, xb = xb0;
+        int yb = yb0, xb = xb0;
         if constexpr (CACHE) {
 #pragma unroll
           for (int j = 0; j < MAXBW; ++j) {
-            if (j < nbw) pass1(cy, xb, lbc[j]);
-            step(cy, xb);
+            if (j < nbw) pass1(yb, xb, lbc[j]);
+            step(yb, xb);
           }
         } else {
           for (int j = 0; j < nbw; ++j) {
             unsigned lbw[2];
-            pass1(cy, xb, lbw);
-            step(cy, xb);
+            pass1(yb, xb, lbw);
+            step(yb, xb);
           }
         }
       }
@@ -448,8 +461,8 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
         Ti[i] = Tp[4 * kq + i];
         Th[i] = wxl[i] ? __float_as_uint(Ti[i]) >> 16 : 0u;
       }
-      auto pass2 = [&](int cy, int xb, const bool (&h)[4]) __attribute__((always_inline)) {
-        const int cx = xb * 16 + n;
+      auto pass2 = [&](int yb, int xb, const bool (&h)[4]) __attribute__((always_inline)) {
+        const int cy = 2 * yb + cyn, cx = 8 * xb + cxn;
         if (h[0] | h[1] | h[2] | h[3]) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
@@ -462,7 +475,7 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
         }
       };
       {
-        int cy = cy0, xb = xb0;
+        int yb = yb0, xb = xb0;
         if constexpr (CACHE) {
 #pragma unroll
           for (int j = 0; j < MAXBW; ++j) {
@@ -470,19 +483,19 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
               bool h[4];
 #pragma unroll
               for (int i = 0; i < 4; ++i) h[i] = ((lbc[j][i >> 1] >> (16 * (i & 1))) & 0xFFFFu) <= Th[i];
-              pass2(cy, xb, h);
+              pass2(yb, xb, h);
             }
-            step(cy, xb);
+            step(yb, xb);
           }
         } else {
           for (int j = 0; j < nbw; ++j) {
             float dt[4], E[4];
             bool ok[4], h[4];
-            tile_dist(cy, xb * 16 + n, dt, E, ok);
+            tile_dist(2 * yb + cyn, 8 * xb + cxn, dt, E, ok);
 #pragma unroll
             for (int i = 0; i < 4; ++i) h[i] = ok[i] && dt[i] - E[i] <= Ti[i];
-            pass2(cy, xb, h);
-            step(cy, xb);
+            pass2(yb, xb, h);
+            step(yb, xb);
           }
         }
       }
@@ -678,7 +691,7 @@ hipError_t launch_match(const Launch& L, int mode, int terms, int grid, hipStrea
   const int npl = match_planes(L.C, L.stride, L.window);
   const MatchGeom G = match_geom(L.stride, L.window, npl);
   const size_t lds = (size_t)G.bytes;
-  const bool cache = (G.ryc * (G.rxp / 16) + 3) / 4 <= MAXBW;
+  const bool cache = ((G.ryc + 1) / 2 * (G.rxp / 8) + 3) / 4 <= MAXBW;
 #define HTS_KM(M, T)                                                                          \
   if (npl == 2) {                                                                             \
     if (cache) hipLaunchKernelGGL((k_match<M, T, 1, 2>), dim3(g), dim3(256), lds, s, L);      \

@@ -381,12 +381,16 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
       constexpr unsigned INFB = 0x7f800000u;   // +inf
 
       // ---- pass 1: two smallest upper bounds per (lane, reference) ----
-      // Bounds are non-negative floats, compared as their bit patterns.  With
-      // CACHE the lower bounds max(d~ - E, 0) stay in registers for pass 2 as
-      // the upper 16 bits of their float patterns (truncation only lowers a
-      // non-negative float, so pass 2 still shortlists a superset), two per
-      // register; 0xFFFF marks a non-candidate.
-      unsigned m0[4] = {INFB, INFB, INFB, INFB}, m1[4] = {INFB, INFB, INFB, INFB};
+      // Upper bounds d~ + E are at least the exact distance, so never
+      // negative (rounding is monotone).  With CACHE the lower bounds d~ - E
+      // stay in registers for pass 2 as the upper 16 bits of their float
+      // patterns, shifted arithmetically: a negative bound stays negative,
+      // and truncation only lowers a non-negative one, so pass 2 still
+      // shortlists a superset; two per register; 0x7FFF (above every
+      // threshold's 16 bits, at most 0x7F80) marks a non-candidate.
+      float m0[4], m1[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) m0[i] = m1[i] = __uint_as_float(INFB);
       unsigned lbc[CACHE ? MAXBW : 1][2];
       auto pass1 = [&](int yb, int xb, unsigned (&lbw)[2]) __attribute__((always_inline)) {
         float dt[4], E[4];
@@ -395,10 +399,10 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
         unsigned lh[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const unsigned hv = ok[i] ? __float_as_uint(fmaxf(dt[i] + E[i], 0.f)) : INFB;
-          m1[i] = min(m1[i], max(m0[i], hv));
-          m0[i] = min(m0[i], hv);
-          lh[i] = ok[i] ? __float_as_uint(fmaxf(dt[i] - E[i], 0.f)) >> 16 : 0xFFFFu;
+          const float hv = ok[i] ? dt[i] + E[i] : __uint_as_float(INFB);
+          m1[i] = __builtin_amdgcn_fmed3f(m0[i], m1[i], hv);   // m0 <= m1: min(m1, max(m0, hv))
+          m0[i] = fminf(m0[i], hv);
+          lh[i] = ok[i] ? (unsigned)(__float_as_int(dt[i] - E[i]) >> 16) & 0xFFFFu : 0x7FFFu;
         }
         lbw[0] = lh[0] | (lh[1] << 16);
         lbw[1] = lh[2] | (lh[3] << 16);
@@ -422,8 +426,8 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         float* dst = tl + ((4 * kq + i) * 64 + wave * 16 + n) * 2;
-        dst[0] = __uint_as_float(m0[i]);
-        dst[1] = __uint_as_float(m1[i]);
+        dst[0] = m0[i];
+        dst[1] = m1[i];
       }
       __syncthreads();
 
@@ -453,13 +457,13 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
       // ---- pass 2: shortlist every candidate with d~ - E <= T ----
       // Shortlist entries are packed (cy << 8) | cx.
       // Tp is only set for references on this plane: the others get Th = 0,
-      // which no non-candidate marker (0xFFFF) passes.
+      // which no non-candidate marker (0x7FFF) passes.
       float Ti[4];
-      unsigned Th[4];
+      int Th[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         Ti[i] = Tp[4 * kq + i];
-        Th[i] = wxl[i] ? __float_as_uint(Ti[i]) >> 16 : 0u;
+        Th[i] = wxl[i] ? (int)(__float_as_uint(Ti[i]) >> 16) : 0;
       }
       auto pass2 = [&](int yb, int xb, const bool (&h)[4]) __attribute__((always_inline)) {
         const int cy = 2 * yb + cyn, cx = 8 * xb + cxn;
@@ -482,7 +486,8 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
             if (j < nbw) {
               bool h[4];
 #pragma unroll
-              for (int i = 0; i < 4; ++i) h[i] = ((lbc[j][i >> 1] >> (16 * (i & 1))) & 0xFFFFu) <= Th[i];
+              for (int i = 0; i < 4; ++i)   // the 16-bit bound, sign-extended
+                h[i] = ((int)(lbc[j][i >> 1] << (16 - 16 * (i & 1))) >> 16) <= Th[i];
               pass2(yb, xb, h);
             }
             step(yb, xb);

@@ -63,7 +63,10 @@ hts_status make_geo(const hts_params* p, int C, int H, int W, Geo& g) {
   g.nry = ref_count_axis(g.Hp, p->stride);
   g.nrx = ref_count_axis(g.Wp, p->stride);
   g.n_ref = g.nry * g.nrx;
-  g.n_cov = (g.n_ref + COV_REFS - 1) / COV_REFS;
+  {
+    const int tr = cov_tile(p->stride);
+    g.n_cov = ((g.nry + tr - 1) / tr) * ((g.nrx + tr - 1) / tr);
+  }
   g.np = C == 1 ? 1 : 2;
   const int r = (p->window - 1) / 2;
   // every reference must have at least K candidates (the corner ones have fewest)

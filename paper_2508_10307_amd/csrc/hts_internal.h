@@ -16,7 +16,6 @@ constexpr int MAX_WINDOW = 63;         // window-relative candidate index fits 1
 constexpr int MATCH_TY = 4;            // match tile: 4 x 4 references
 constexpr int MATCH_TX = 4;
 constexpr int SHORT_CAP = 128;         // certified shortlist capacity per reference
-constexpr int COV_REFS = 256;          // references per covariance partial block
 constexpr int PIX_CHUNK = 2048;        // pixels per work item of the element-wise stages
 
 // Work kinds: each image contributes a number of work items of each kind;
@@ -132,6 +131,10 @@ inline int ref_count_axis(int n_valid, int s) {
 }
 
 __host__ __device__ inline int cov_elems(int C) { return C == 1 ? 2 * 64 : 2 * 64 + 2 * 128; }
+// Covariance partial blocks: tiles of cov_tile x cov_tile references, whose
+// pixel region (at most cov_region pixels square) is staged in LDS.
+__host__ __device__ inline int cov_tile(int s) { return s <= 4 ? 16 : 8; }
+__host__ __device__ inline int cov_region(int s) { return (cov_tile(s) - 1) * s + PS; }
 
 // Kernel launchers (defined in the .hip files).  Each returns hipSuccess or
 // the launch error.  `grid` = 0 means one work group per work item.

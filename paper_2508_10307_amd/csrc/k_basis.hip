@@ -22,7 +22,8 @@ __device__ inline void dft3(double p0, double p1, double p2, double& f0, double&
   f1i = 0.86602540378443864676 * (p2 - p1);
 }
 
-// Partial covariances of the references [item*COV_REFS, ...): layout per
+// Partial covariances of one tile of cov_tile x cov_tile references
+// (item = tile in row-major order over the reference grid): layout per
 // item: C_U(0)[8][8], C_V(0)[8][8], then for c = 3 C_U(1), C_V(1) as
 // interleaved (re, im) [8][8][2].
 //
@@ -34,42 +35,57 @@ __device__ inline void dft3(double p0, double p1, double p2, double& f0, double&
 //   C_U(1): Z = [Re P^(1); Im P^(1)]   -> Re = G11 + G22, Im = G21 - G12;
 //   C_V(1): Z = [Re P^(1)^T; Im P^(1)^T] -> Re = G11 + G22, Im = G12 - G21;
 //   C_U(0), C_V(0): Z = [P^(0); P^(0)] (resp. transposed) -> C = G11,
-// where Gxy are the 8 x 8 blocks of G = Z Z^T.  Each wavefront takes every
-// fourth reference of the item; the four partial Grams are added in LDS in
-// wavefront order.
+// where Gxy are the 8 x 8 blocks of G = Z Z^T.  The tile's pixel region is
+// staged in LDS first (overlapping patches read it many times over); each
+// wavefront takes every fourth reference of the tile; the four partial
+// Grams are added in LDS in wavefront order.
 __global__ __launch_bounds__(256) void k_cov(Launch L) {
+  extern __shared__ float px[];         // [C][RH][RW] pixel region of the tile
   __shared__ double red[4][4][4][64];   // [wavefront][gram][register][lane]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r16 = lane & 15, kq = lane >> 4, rr = r16 & 7;
   const bool upper = r16 >= 8;          // rows 8..15 of Z
   const int nel = cov_elems(L.C);
+  const int s = L.stride, TR = cov_tile(s);
   for_each_item<W_COV>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
     const int HW = d.H * d.W;
+    const int ntx = (d.nrx + TR - 1) / TR;
+    const int iy0 = (item / ntx) * TR, ix0 = (item % ntx) * TR;
+    const int ty = min(d.nry - iy0, TR), tx = min(d.nrx - ix0, TR);
+    const int Y0 = ref_coord(iy0, s, d.Hp), X0 = ref_coord(ix0, s, d.Wp);
+    const int RH = ref_coord(iy0 + ty - 1, s, d.Hp) + PS - Y0;   // <= cov_region(s)
+    const int RW = ref_coord(ix0 + tx - 1, s, d.Wp) + PS - X0;
+    const int RP = RH * RW;
+    __syncthreads();   // the previous item's references still read px
+    for (int e = tid; e < L.C * RP; e += 256) {
+      const int ch = e / RP, rem = e - ch * RP, y = rem / RW, x = rem - y * RW;
+      px[e] = d.img[ch * HW + (Y0 + y) * d.W + X0 + x];
+    }
+    __syncthreads();
     d4 gu1 = {0.0, 0.0, 0.0, 0.0}, gv1 = gu1, gu0 = gu1, gv0 = gu1;
-    const int r_begin = item * COV_REFS;
-    const int r_end = min(d.n_ref, r_begin + COV_REFS);
-    // four references per round: their pixels are loaded before the MFMAs
+    const int nt = ty * tx;
+    // four references per round: their pixels are read before the MFMAs
     // (a reference past the end reads the last one and contributes zero)
     constexpr int RB = 4;
-    for (int r0 = r_begin + wave; r0 < r_end; r0 += 4 * RB) {
+    for (int t0 = wave; t0 < nt; t0 += 4 * RB) {
       float pu[RB][2][3], pv[RB][2][3];
       double live[RB];
 #pragma unroll
       for (int u = 0; u < RB; ++u) {
-        const int ref = min(r0 + 4 * u, r_end - 1);
-        live[u] = r0 + 4 * u < r_end ? 1.0 : 0.0;
-        const int iy = ref / d.nrx;
-        const int ry = ref_coord(iy, L.stride, d.Hp);
-        const int rx = ref_coord(ref - iy * d.nrx, L.stride, d.Wp);
-        const float* base = d.img + ry * d.W + rx;
+        const int t = min(t0 + 4 * u, nt - 1);
+        live[u] = t0 + 4 * u < nt ? 1.0 : 0.0;
+        const int iy = t / tx;
+        const int ry = ref_coord(iy0 + iy, s, d.Hp) - Y0;
+        const int rx = ref_coord(ix0 + t - iy * tx, s, d.Wp) - X0;
+        const float* base = px + ry * RW + rx;
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-          const int ou = rr * d.W + kq + 4 * c;       // pixel (row rr, column kq + 4c): C_U operands
-          const int ov = (kq + 4 * c) * d.W + rr;     // pixel (row kq + 4c, column rr): C_V operands
+          const int ou = rr * RW + kq + 4 * c;       // pixel (row rr, column kq + 4c): C_U operands
+          const int ov = (kq + 4 * c) * RW + rr;     // pixel (row kq + 4c, column rr): C_V operands
 #pragma unroll
           for (int ch = 0; ch < 3; ++ch) {
-            pu[u][c][ch] = ch < L.C ? base[ch * HW + ou] : 0.f;
-            pv[u][c][ch] = ch < L.C ? base[ch * HW + ov] : 0.f;
+            pu[u][c][ch] = ch < L.C ? base[ch * RP + ou] : 0.f;
+            pv[u][c][ch] = ch < L.C ? base[ch * RP + ov] : 0.f;
           }
         }
       }
@@ -318,7 +334,9 @@ __global__ void k_fbasis(Launch L, const float* U_ext, const float* V_ext) {
 
 hipError_t launch_cov(const Launch& L, int grid, hipStream_t s) {
   if (L.total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cov, dim3(xcd_grid(grid > 0 && grid < L.total ? grid : L.total)), dim3(256), 0, s, L);
+  const int reg = cov_region(L.stride);
+  const size_t lds = (size_t)L.C * reg * reg * sizeof(float);
+  hipLaunchKernelGGL(k_cov, dim3(xcd_grid(grid > 0 && grid < L.total ? grid : L.total)), dim3(256), lds, s, L);
   return hipGetLastError();
 }
 hipError_t launch_eig(const Launch& L, hipStream_t s) {

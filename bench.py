@@ -87,7 +87,7 @@ TRAFFIC_SOURCES = ["paper_2508_10307_amd/csrc/k_filter.hip",
                    "paper_2508_10307_amd/csrc/hts_internal.h"]
 TRAFFIC = {    # kernel name -> (sources sha256, bytes per launch)
     "void hts::k_filter<3, 4, 0, 0, 0>(hts::Launch)":
-        ("7ed8a689e31fa7b694b8cace5503a8fe09e9b4330533135d742f608ba832ed05", 86963232),
+        ("7b3d98f47856dfea1824db214a3df045f79048166a589db7d9e41ea26079a86c", 57607421),
 }
 
 

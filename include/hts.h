@@ -182,6 +182,41 @@ hts_status hts_batch_workspace_size(const hts_params* p, const hts_image* imgs, 
 hts_status hts_denoise_batch(const hts_params* p, const hts_image* imgs, int32_t n,
                              void* ws, size_t ws_bytes, void* stream);
 
+/* A-Haar-tSVD noise-level adjustment (Sec. III-C, Eq. 21-22; Algorithm
+ * A-Haar-tSVD Step 1) for a caller-supplied sigma_est (the paper's CNN
+ * estimator is not part of this library).  For each sampled group (the
+ * reference indices samples[0..n_samples), device int32, drawn by the
+ * caller; out-of-range entries are clamped to the reference grid), with the
+ * K patches of its row of idx (device [n_ref][K], slot order as hts_match
+ * writes it): lambda_m = sum over the group's C*64 values of
+ * |DFT_K along the group mode|^2, m = 0..K-1, the eigenvalues of
+ * circ(G) circ(G)^T; a = 1 + #{m : lambda_m < lambda_{K/2}} (the rank of
+ * Eq. 21's alternating eigenvalue, ascending).  sigma_out (device float[1])
+ * receives sigma_est / beta when more than half of the sampled groups have
+ * a <= gamma (Eq. 22; paper values beta = 1.2, gamma = 13), else sigma_est.
+ * ranks (device int32[n_samples], nullable) receives each a.  FP64
+ * arithmetic; asynchronous on `stream`; no workspace.
+ * Errors: HTS_ERR_INVALID for null pointers, n_samples outside
+ * [1, 2^20], beta not positive and finite, sigma_est negative or not
+ * finite, and the parameter checks of hts_match. */
+hts_status hts_adapt_sigma(const hts_params* p, const float* noisy, int32_t C, int32_t H,
+                           int32_t W, const int32_t* idx, const int32_t* samples,
+                           int32_t n_samples, float sigma_est, float beta, int32_t gamma,
+                           int32_t* ranks, float* sigma_out, void* stream);
+
+/* A-Haar-tSVD over a batch (Algorithm A-Haar-tSVD): hts_denoise_batch where
+ * imgs[i].sigma is sigma_est of image i, and after the match of each image
+ * the adjustment of hts_adapt_sigma runs on its sampled groups
+ * (samples + i * n_samples); the filter then thresholds image i with
+ * tau = tau_mult * sigma_out[i], read on the device (no host round trip).
+ * Sub-images of one picture are passed as separate images.  ranks (nullable)
+ * and sigma_out are device arrays [n][n_samples] and [n].  Workspace as for
+ * hts_denoise_batch.  Errors as hts_denoise_batch and hts_adapt_sigma. */
+hts_status hts_denoise_batch_adaptive(const hts_params* p, const hts_image* imgs, int32_t n,
+                                      const int32_t* samples, int32_t n_samples, float beta,
+                                      int32_t gamma, int32_t* ranks, float* sigma_out,
+                                      void* ws, size_t ws_bytes, void* stream);
+
 /* Adjoint of hts_denoise with the match indices, threshold masks, basis and
  * coverage count held fixed (the map noisy -> denoised is then linear;
  * derived from Eq. 18-20 and Eq. 2):

@@ -230,6 +230,106 @@ def hts_denoise_batch(noisy: List[torch.Tensor], sigmas, p: Params, outs=None, w
     return outs
 
 
+def _samples(samples, n_rows: int, dev) -> torch.Tensor:
+    t = torch.as_tensor(samples, dtype=torch.int32)
+    if t.dim() == 1:
+        t = t.reshape(1, -1)
+    if t.shape[0] != n_rows or t.shape[1] < 1:
+        raise ValueError("samples must be [n_images, n_samples] reference indices")
+    return t.to(dev).contiguous()
+
+
+def hts_adapt_sigma(noisy: torch.Tensor, idx: torch.Tensor, samples, sigma_est: float,
+                    p: Params, beta: float = 1.2, gamma: int = 13):
+    """A-Haar-tSVD noise-level adjustment of one image (Eq. 21-22) for a
+    caller-supplied sigma_est: the sampled groups' eigenvalue ranks and the
+    voted sigma-hat.  Returns (sigma_hat [1] tensor, ranks [n_samples])."""
+    x = _img(noisy)
+    dev = x.device
+    C, H, W = x.shape
+    if not idx.is_cuda or idx.dtype != torch.int32:
+        raise ValueError("idx must be an int32 tensor on the GPU")
+    smp = _samples(samples, 1, dev)
+    n = smp.shape[1]
+    sig = torch.empty(1, dtype=torch.float32, device=dev)
+    ranks = torch.empty(n, dtype=torch.int32, device=dev)
+    pc = p.c()
+    L.check("hts_adapt_sigma", L.load().hts_adapt_sigma(
+        ctypes.byref(pc), _ptr(x), C, H, W, _ptr(idx.contiguous()), _ptr(smp), n,
+        float(sigma_est), float(beta), int(gamma), _ptr(ranks), _ptr(sig), _stream(dev)))
+    return sig, ranks
+
+
+def hts_denoise_batch_adaptive(noisy: List[torch.Tensor], sigma_est, samples, p: Params,
+                               beta: float = 1.2, gamma: int = 13, outs=None, ws=None):
+    """A-Haar-tSVD over a batch (each image, e.g. each sub-image of a
+    picture, adjusts its own sigma_est from its sampled groups, samples =
+    [n_images, n_samples] reference indices, then is denoised with it).
+    Returns (outputs, sigma_hat [n], ranks [n, n_samples])."""
+    xs = [_img(x) for x in noisy]
+    dev = xs[0].device
+    outs = [torch.empty_like(x) for x in xs] if outs is None else outs
+    if ws is None:
+        ws = torch.empty(batch_workspace_size(p, xs, outs, sigma_est), dtype=torch.uint8,
+                         device=dev)
+    smp = _samples(samples, len(xs), dev)
+    ns = smp.shape[1]
+    sig = torch.empty(len(xs), dtype=torch.float32, device=dev)
+    ranks = torch.empty(len(xs), ns, dtype=torch.int32, device=dev)
+    arr = _images(xs, outs, sigma_est)
+    pc = p.c()
+    L.check("hts_denoise_batch_adaptive", L.load().hts_denoise_batch_adaptive(
+        ctypes.byref(pc), arr, len(xs), _ptr(smp), ns, float(beta), int(gamma), _ptr(ranks),
+        _ptr(sig), _ptr(ws), ws.numel(), _stream(dev)))
+    return outs, sig, ranks
+
+
+def sub_images(H: int, W: int, sub_h: int, sub_w: int):
+    """Tiling of an H x W image into sub-images of about sub_h x sub_w
+    (Algorithm A-Haar-tSVD): max(1, H // sub_h) rows and max(1, W // sub_w)
+    columns of near-equal tiles, each at least sub_h x sub_w unless the image
+    is smaller.  Returns [(y0, x0, h, w)]."""
+    ny, nx = max(1, H // sub_h), max(1, W // sub_w)
+    ys = [round(i * H / ny) for i in range(ny + 1)]
+    xs = [round(j * W / nx) for j in range(nx + 1)]
+    return [(ys[i], xs[j], ys[i + 1] - ys[i], xs[j + 1] - xs[j])
+            for i in range(ny) for j in range(nx)]
+
+
+def draw_samples(subs, p: Params, n_samples: int, seed: int = 0):
+    """The random choice of the sampled groups (references drawn without
+    replacement, numpy generator seeded with [seed, sub-image]); an input of
+    the adjustment, so that a caller can reproduce it."""
+    import numpy as np
+    rows = []
+    for i, (_, _, h, w) in enumerate(subs):
+        ny, nx = ref_grid(h, w, p)
+        rng = np.random.default_rng([seed, i])
+        n = ny * nx
+        rows.append(rng.choice(n, size=n_samples, replace=n < n_samples).astype(np.int32))
+    return np.stack(rows)
+
+
+def a_haar_tsvd(x: torch.Tensor, sigma_est: float, sub=(256, 256), n_samples: int = 16,
+                seed: int = 0, beta: float = 1.2, gamma: int = 13, **params):
+    """A-Haar-tSVD of one [C, H, W] image with a caller-supplied sigma_est:
+    the image is split into sub-images, each adjusts sigma_est from its own
+    sampled groups and is denoised with it, all in one adaptive batch.
+    Returns (denoised image, sigma_hat per sub-image, sub-image list)."""
+    x = _img(x)
+    p = Params(**params)
+    C, H, W = x.shape
+    subs = sub_images(H, W, sub[0], sub[1])
+    parts = [x[:, y0:y0 + h, x0:x0 + w].contiguous() for (y0, x0, h, w) in subs]
+    smp = draw_samples(subs, p, n_samples, seed)
+    outs, sig, _ = hts_denoise_batch_adaptive(parts, [sigma_est] * len(parts), smp, p, beta,
+                                              gamma)
+    out = torch.empty_like(x)
+    for (y0, x0, h, w), o in zip(subs, outs):
+        out[:, y0:y0 + h, x0:x0 + w] = o
+    return out, sig, subs
+
+
 def hts_autotune(p: Params, C, H, W, cache_path: Optional[str] = None, device="cuda"):
     """Time the launch schedules for this shape on the GPU; returns the tune word."""
     size = workspace_size(p, C, H, W) + 2 * C * H * W * 4 + (H * W) * p.K * 4 + (1 << 20)

@@ -379,6 +379,7 @@ hts_status enqueue_batch(const hts_params* p, int C, const BatchPlan& plan, cons
   HIPCHK(launch_gcp(LK(W_REF), cus * 8, s));
   HIPCHK(launch_match(LC(W_MATCH), p->match_mode, sc.terms, cus * 2, s));
   HIPCHK(launch_match_fallback(LC(-1), cus, s));
+  if (plan.descs[0].n_samples > 0) HIPCHK(launch_vote(LK(-1), s));   // A-Haar-tSVD sigma
   HIPCHK(launch_cov(LK(W_COV), cus * 4, s));
   HIPCHK(launch_eig(LK(-1), s));
   HIPCHK(launch_fbasis(LK(-1), nullptr, nullptr, s));
@@ -403,15 +404,16 @@ std::mutex g_graph_mu;
 std::map<std::string, GraphEntry> g_graphs;
 hipStream_t g_capture_stream[64] = {nullptr};
 
-std::string graph_key(const hts_params* p, const hts_image* imgs, int n, const void* ws) {
-  std::string k;
+std::string graph_key(const hts_params* p, const hts_image* imgs, int n, const void* ws,
+                      bool adaptive) {
+  std::string k = adaptive ? "A|" : "|";
   char buf[128];
   int dev = 0;
   (void)hipGetDevice(&dev);
   std::snprintf(buf, sizeof(buf), "%d|%d %d %d %d %a %d %d %d %d %d|%p|", dev, p->ps, p->stride,
                 p->window, p->K, (double)p->tau_mult, p->gcp_num, p->gcp_den, p->match_mode,
                 p->flags, p->tune, ws);
-  k = buf;
+  k += buf;
   for (int i = 0; i < n; ++i) {
     std::snprintf(buf, sizeof(buf), "%dx%dx%d;", imgs[i].C, imgs[i].H, imgs[i].W);
     k += buf;
@@ -590,6 +592,41 @@ hts_status hts_denoise(const hts_params* p, const float* noisy, int32_t C, int32
   return HTS_OK;
 }
 
+static bool adapt_args_ok(int32_t n_samples, float beta) {
+  return n_samples >= 1 && n_samples <= (1 << 20) && beta > 0.f && std::isfinite(beta);
+}
+
+hts_status hts_adapt_sigma(const hts_params* p, const float* noisy, int32_t C, int32_t H,
+                           int32_t W, const int32_t* idx, const int32_t* samples,
+                           int32_t n_samples, float sigma_est, float beta, int32_t gamma,
+                           int32_t* ranks, float* sigma_out, void* stream) {
+  Geo g;
+  hts_status st = make_geo(p, C, H, W, g);
+  if (st != HTS_OK) return st;
+  if (!noisy || !idx || !samples || !sigma_out || !adapt_args_ok(n_samples, beta)) return HTS_ERR_INVALID;
+  if (!(sigma_est >= 0.f) || !std::isfinite(sigma_est)) return HTS_ERR_INVALID;
+  ImgDesc d;
+  std::memset(&d, 0, sizeof(d));
+  d.img = noisy;
+  d.idx = const_cast<int32_t*>(idx);
+  d.H = g.H; d.W = g.W; d.Hp = g.Hp; d.Wp = g.Wp;
+  d.nry = g.nry; d.nrx = g.nrx; d.n_ref = g.n_ref;
+  d.sigma = sigma_est;
+  d.samples = samples;
+  d.n_samples = n_samples;
+  d.beta = beta;
+  d.gamma = gamma;
+  d.ranks = ranks;
+  d.sigma_dev = sigma_out;
+  Launch L;
+  std::memset(&L, 0, sizeof(L));
+  L.one = d;
+  L.C = C; L.K = p->K; L.stride = p->stride; L.window = p->window;
+  L.tau_mult = p->tau_mult;
+  HIPCHK(launch_vote(L, (hipStream_t)stream));
+  return HTS_OK;
+}
+
 hts_status hts_denoise_backward(const hts_params* p, const float* grad_out, const int32_t* idx,
                                 const uint32_t* masks, const float* U, const float* V,
                                 const float* cnt, int32_t C, int32_t H, int32_t W, float* grad_in,
@@ -632,18 +669,39 @@ hts_status hts_batch_workspace_size(const hts_params* p, const hts_image* imgs, 
   return HTS_OK;
 }
 
-hts_status hts_denoise_batch(const hts_params* p, const hts_image* imgs, int32_t n, void* ws,
-                             size_t ws_bytes, void* stream) {
+// Sampled groups and adjusted sigma of every image for the adaptive variant.
+struct AdaptArgs {
+  const int32_t* samples;   // device [n][n_samples]
+  int32_t n_samples, gamma;
+  float beta;
+  int32_t* ranks;           // device [n][n_samples], nullable
+  float* sigma_out;         // device [n]
+};
+
+static hts_status denoise_batch_impl(const hts_params* p, const hts_image* imgs, int32_t n,
+                                     void* ws, size_t ws_bytes, void* stream,
+                                     const AdaptArgs* ad) {
   if (!ws) return HTS_ERR_INVALID;
   BatchPlan plan;
   hts_status st = plan_batch(p, imgs, n, (char*)ws, true, plan);
   if (st != HTS_OK) return st;
   if (ws_bytes < plan.bytes) return HTS_ERR_WORKSPACE;
+  if (ad) {
+    for (int i = 0; i < n; ++i) {
+      ImgDesc& d = plan.descs[i];
+      d.samples = ad->samples + (size_t)i * ad->n_samples;
+      d.n_samples = ad->n_samples;
+      d.gamma = ad->gamma;
+      d.beta = ad->beta;
+      d.ranks = ad->ranks ? ad->ranks + (size_t)i * ad->n_samples : nullptr;
+      d.sigma_dev = ad->sigma_out + i;
+    }
+  }
   hipStream_t s = (hipStream_t)stream;
   const int C = imgs[0].C;
   ImgDesc* table = (ImgDesc*)((char*)ws + plan.table_off);
   std::lock_guard<std::mutex> lk(g_graph_mu);
-  const std::string key = graph_key(p, imgs, n, ws);
+  const std::string key = graph_key(p, imgs, n, ws, ad != nullptr);
   if (g_graphs.size() >= 64 && !g_graphs.count(key)) {
     // bounded cache: drop every entry (after the device is idle) and start over
     HIPCHK(hipDeviceSynchronize());
@@ -685,6 +743,20 @@ hts_status hts_denoise_batch(const hts_params* p, const hts_image* imgs, int32_t
   }
   HIPCHK(hipGraphLaunch(e.exec, s));
   return HTS_OK;
+}
+
+hts_status hts_denoise_batch(const hts_params* p, const hts_image* imgs, int32_t n, void* ws,
+                             size_t ws_bytes, void* stream) {
+  return denoise_batch_impl(p, imgs, n, ws, ws_bytes, stream, nullptr);
+}
+
+hts_status hts_denoise_batch_adaptive(const hts_params* p, const hts_image* imgs, int32_t n,
+                                      const int32_t* samples, int32_t n_samples, float beta,
+                                      int32_t gamma, int32_t* ranks, float* sigma_out,
+                                      void* ws, size_t ws_bytes, void* stream) {
+  if (!samples || !sigma_out || !adapt_args_ok(n_samples, beta)) return HTS_ERR_INVALID;
+  const AdaptArgs ad{samples, n_samples, gamma, beta, ranks, sigma_out};
+  return denoise_batch_impl(p, imgs, n, ws, ws_bytes, stream, &ad);
 }
 
 hts_status hts_autotune(const hts_params* p, int32_t C, int32_t H, int32_t W,

@@ -55,6 +55,12 @@ struct ImgDesc {
   int32_t ref_begin, ref_count;   // filter range
   float sigma, tau;
   int32_t n_cov;           // covariance partial blocks
+  // noise-level adjustment (A-Haar-tSVD); n_samples = 0 when unused
+  const int32_t* samples;  // [n_samples] sampled reference indices
+  int32_t n_samples, gamma;
+  float beta;
+  int32_t* ranks;          // [n_samples] rank of each sampled group (nullable)
+  float* sigma_dev;        // [1] adjusted sigma; when set, the filter's tau is tau_mult * *sigma_dev
   int32_t woff[W_NKIND];   // first global work item of each kind (batched)
   int32_t wcnt[W_NKIND];   // work items of each kind
 };
@@ -145,6 +151,7 @@ hipError_t launch_match_fallback(const Launch& L, int grid, hipStream_t s);
 hipError_t launch_reset_counters(const Launch& L, hipStream_t s);
 hipError_t launch_cov(const Launch& L, int grid, hipStream_t s);
 hipError_t launch_eig(const Launch& L, hipStream_t s);
+hipError_t launch_vote(const Launch& L, hipStream_t s);
 hipError_t launch_fbasis(const Launch& L, const float* U, const float* V, hipStream_t s);
 hipError_t launch_zero_accum(const Launch& L, int grid, hipStream_t s);
 hipError_t launch_filter(const Launch& L, int shape_ty, int shape_tx, int adjoint, int grid,

@@ -187,7 +187,8 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
     const int AW = AX1 - AX0 + 1, AH = AY1 - AY0 + 1;
     const int HW = d.H * d.W;
     const cfloat* fb = uniform_ptr(d.fbasis);
-    const float tau = d.tau;
+    // adjusted noise level (A-Haar-tSVD) when the descriptor carries one
+    const float tau = d.sigma_dev ? L.tau_mult * *d.sigma_dev : d.tau;
     const float rW = 1.0f / (float)d.W;
     const float fxs = fx_scale(d);                 // fixed-point scale of the estimates
     const float rfxs = 1.f / fxs;

@@ -118,7 +118,8 @@ __global__ __launch_bounds__(256, K >= 32 ? 1 : 2) void k_filter_mfma(Launch L) 
     const int AX1 = min(d.Wp - 1, ref_coord(ix1, st, d.Wp) + r) + PS - 1;
     const int AW = AX1 - AX0 + 1, AH = AY1 - AY0 + 1;
     const int HW = d.H * d.W;
-    const float tau = d.tau;
+    // adjusted noise level (A-Haar-tSVD) when the descriptor carries one
+    const float tau = d.sigma_dev ? L.tau_mult * *d.sigma_dev : d.tau;
     const float rW = 1.0f / (float)d.W;
     const float fxs = fx_scale(d);                 // fixed-point scale of the estimates
     const float s3 = fxs * (1.f / 3.f), rfxs = 1.f / fxs;

@@ -36,6 +36,8 @@ def parse():
                     choices=["batch64", "rgb512", "gray256", "large24"])
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-path comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adaptive", action="store_true",
+                    help="skip the A-Haar-tSVD (adaptive sigma) batch timing")
     ap.add_argument("--batch-api", type=int, default=1,
                     help="1: hts_denoise_batch (one graph); 0: one hts_denoise per image")
     ap.add_argument("--tune", type=int, default=0)
@@ -233,6 +235,29 @@ def main():
         fp32 = {"value": mpix / (ms32 / 1e3), "ms_per_step": ms32, "psnr_db": psnr_fp32,
                 "outputs_bitwise_equal": same, "speedup_bf16_vs_fp32": ms32 / ms}
 
+    # ---- A-Haar-tSVD: the same batch with the noise-level vote per image ----
+    # (each image is its own sub-image, sigma_est = its noise level, 16 sampled
+    # groups per image drawn with seed 0; adds one vote kernel to the graph)
+    adaptive = None
+    if not args.no_adaptive and args.batch_api:
+        pa = params(L.HTS_MATCH_BF16)
+        subs = [(0, 0, x.shape[1], x.shape[2]) for x in xs]
+        smp = torch.from_numpy(api.draw_samples(subs, pa, 16, seed=0)).to(dev)
+        ws_a = torch.empty(api.batch_workspace_size(pa, xs, outs, sig), dtype=torch.uint8,
+                           device=dev)
+        res = {}
+
+        def run_ad():
+            res["r"] = api.hts_denoise_batch_adaptive(xs, sig, smp, pa, outs=outs, ws=ws_a)
+
+        msa = timed(run_ad, max(1, args.steps // 2), 1)
+        sh = res["r"][1].cpu().numpy()
+        adaptive = {"value": mpix / (msa / 1e3), "ms_per_step": round(msa, 3),
+                    "overhead_ms": round(msa - ms, 3), "n_samples": 16,
+                    "images_adjusted": int(sum(1 for a, b in zip(sh, sig)
+                                               if abs(float(a) - float(b)) > 0))}
+        del ws_a
+
     # ---- roofline of the dominant kernel: the fused filter, timed live ----
     # One eager launch per image (the same filter the batched graph runs, as
     # its single-image instantiation), timed with HIP events on its stream:
@@ -314,6 +339,7 @@ def main():
         "stage_ms": {"match_bf16_sum": round(mtime, 3), "match_fp32_sum": round(mtime32, 3),
                      "match_stage_speedup_bf16_vs_fp32": round(mtime32 / mtime, 3),
                      "filter_sum": round(ftime, 3)},
+        "adaptive": adaptive,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

@@ -59,18 +59,33 @@ def hard_threshold(S: np.ndarray, tau: float):
     return np.where(keep, S, 0.0), keep
 
 
-def aggregate(est: np.ndarray, idx: np.ndarray, C: int, H: int, W: int, ps: int):
-    """Step 3 / Eq. 2 with uniform weights ("averagely written back"):
-    num[p] = sum of all estimates covering p, cnt[p] = how many estimates
-    cover p.  est [n, K, C, ps, ps], idx [n, K].  Returns (num [C,H,W], cnt [H,W])."""
+def aggregate(est: np.ndarray, idx: np.ndarray, C: int, H: int, W: int, ps: int,
+              w: np.ndarray = None):
+    """Step 3 / Eq. 2.  Uniform weights ("averagely written back", the
+    default): num[p] = sum of all estimates covering p, cnt[p] = how many
+    estimates cover p.  With per-group weights w [n] (Eq. 2's w, every patch
+    of group g weighted w[g]): num[p] = sum w * estimate, cnt[p] = sum w.
+    est [n, K, C, ps, ps], idx [n, K].  Returns (num [C,H,W], cnt [H,W])."""
     num = np.zeros(C * H * W, dtype=np.float64)
     cnt = np.zeros(H * W, dtype=np.float64)
-    base = np.asarray(idx, dtype=np.int64).ravel()
+    idx = np.asarray(idx, dtype=np.int64)
+    base = idx.ravel()
+    wk = None if w is None else np.repeat(np.asarray(w, dtype=np.float64), idx.shape[1])
     for a in range(ps):
         for b in range(ps):
             pix = base + a * W + b
-            cnt += np.bincount(pix, minlength=H * W)
+            cnt += np.bincount(pix, weights=wk, minlength=H * W)
             for ch in range(C):
+                e = est[:, :, ch, a, b].ravel()
                 num[ch * H * W:(ch + 1) * H * W] += np.bincount(
-                    pix, weights=est[:, :, ch, a, b].ravel(), minlength=H * W)
+                    pix, weights=e if wk is None else wk * e, minlength=H * W)
     return num.reshape(C, H, W), cnt.reshape(H, W)
+
+
+def group_weights(keep: np.ndarray) -> np.ndarray:
+    """Reading W1 of Eq. 2's weights (the paper leaves them open; the
+    BM3D-style choice): w_g = 1 / max(1, number of coefficients of group g
+    kept by the hard threshold), over all K*C*ps*ps coefficients.
+    keep [n, K, C, ps, ps] bool -> w [n]."""
+    n = keep.reshape(keep.shape[0], -1).sum(axis=1)
+    return 1.0 / np.maximum(n, 1).astype(np.float64)

@@ -23,7 +23,7 @@ def unpack_masks(words: np.ndarray, n: int, K: int, C: int, ps: int = 8) -> np.n
 
 def denoise(y, sigma, ps=8, stride=3, window=21, K=16, tau_mult=2.7, gcp_num=6,
             gcp_den=5, idx=None, U=None, V=None, mask=None, return_mask=False,
-            chunk=2048):
+            chunk=2048, weighted=False):
     """Denoise y [C][H][W] with noise level sigma.
 
     idx      optional [n_ref, K] match indices (else Step 1 is run here);
@@ -31,6 +31,8 @@ def denoise(y, sigma, ps=8, stride=3, window=21, K=16, tau_mult=2.7, gcp_num=6,
     mask     optional bool keep-mask [n_ref, K, C, ps, ps] used instead of the
              oracle's own Eq. 19 decision; every position where it disagrees
              is reported with the oracle's margin | |S| - tau |.
+    weighted Eq. 2 with the group weights of filtering.group_weights (from
+             the keep-mask in use) instead of uniform ones.
     Returns a dict with out (= num / cnt), num, cnt, idx, U, V, UF, VF, and,
     when asked, the oracle's keep-mask and the override report."""
     y = np.asarray(y)
@@ -68,8 +70,10 @@ def denoise(y, sigma, ps=8, stride=3, window=21, K=16, tau_mult=2.7, gcp_num=6,
                 max_margin = max(max_margin, float(marg.max()))
                 over_margins.append(marg)
             St = np.where(mk, S, 0.0)
+            keep = mk
         est = _f.tsvd_inverse(_f.haar_group_inverse(St, K), UF, VF)
-        nn, cc = _f.aggregate(est, ic, C, H, W, ps)
+        wg = _f.group_weights(keep) if weighted else None
+        nn, cc = _f.aggregate(est, ic, C, H, W, ps, wg)
         num += nn
         cnt += cc
     res.update(out=num / cnt[None], num=num, cnt=cnt, idx=idx, U=U, V=V, UF=UF, VF=VF,

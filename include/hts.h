@@ -77,6 +77,16 @@ typedef enum {
   HTS_MATCH_FP32 = 1        /* plain FP32 SSD tiles on the vector ALUs (no MFMA) */
 } hts_match_mode;
 
+/* hts_params.flags: Eq. 2 with group weights w_g = 1 / max(1, number of
+ * coefficients of group g kept by the hard threshold) instead of uniform
+ * ones (the paper leaves the weights open; this is the BM3D-style choice):
+ * x = sum_g w_g * estimates / sum_g w_g per pixel.  Honoured by hts_denoise,
+ * hts_denoise_batch(_adaptive) and hts_filter (which then adds the weight
+ * sums into cnt instead of coverage counts; estimates into num are
+ * weighted); the vector-ALU filter runs.  hts_aggregate and
+ * hts_denoise_backward return HTS_ERR_UNSUPPORTED with it. */
+#define HTS_FLAG_WEIGHTED 1
+
 typedef struct {
   int32_t ps;          /* patch size; must be 8                                  */
   int32_t stride;      /* reference stride s, 1 <= s <= ps                        */
@@ -86,7 +96,7 @@ typedef struct {
   int32_t gcp_num;     /* gamma = gcp_num / gcp_den (Eq. 10; 6/5 = 1.2), 1..64    */
   int32_t gcp_den;
   int32_t match_mode;  /* hts_match_mode                                          */
-  int32_t flags;       /* reserved, must be 0                                     */
+  int32_t flags;       /* 0 or HTS_FLAG_WEIGHTED                                  */
   int32_t tune;        /* 0 = autotuned/default launch schedule, else a schedule id */
 } hts_params;
 

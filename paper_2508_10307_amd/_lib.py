@@ -17,6 +17,7 @@ HTS_ERR_WORKSPACE = 3
 HTS_ERR_HIP = 4
 HTS_MATCH_BF16 = 0
 HTS_MATCH_FP32 = 1
+HTS_FLAG_WEIGHTED = 1
 
 c_i32 = ctypes.c_int32
 c_f32 = ctypes.c_float

@@ -36,6 +36,8 @@ struct Geo {
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
+bool weighted(const hts_params* p) { return (p->flags & HTS_FLAG_WEIGHTED) != 0; }
+
 hts_status check_params(const hts_params* p, int C) {
   if (!p) return HTS_ERR_INVALID;
   if (p->ps != PS) return HTS_ERR_UNSUPPORTED;
@@ -47,9 +49,10 @@ hts_status check_params(const hts_params* p, int C) {
   if (!(p->tau_mult >= 0.f) || !std::isfinite(p->tau_mult)) return HTS_ERR_INVALID;
   if (p->gcp_num < 1 || p->gcp_num > 64 || p->gcp_den < 1 || p->gcp_den > 64) return HTS_ERR_INVALID;
   if (p->match_mode != HTS_MATCH_BF16 && p->match_mode != HTS_MATCH_FP32) return HTS_ERR_INVALID;
-  if (p->flags != 0) return HTS_ERR_INVALID;
+  if ((p->flags & ~HTS_FLAG_WEIGHTED) != 0) return HTS_ERR_INVALID;
   if ((size_t)match_lds_bytes(p->stride, p->window) > kLdsMax) return HTS_ERR_UNSUPPORTED;
-  if (filter_lds_bytes(C, p->K, p->stride, p->window, 1, 1) > kLdsMax) return HTS_ERR_UNSUPPORTED;
+  if (filter_lds_bytes(C, p->K, p->stride, p->window, 1, 1, weighted(p)) > kLdsMax)
+    return HTS_ERR_UNSUPPORTED;
   return HTS_OK;
 }
 
@@ -78,7 +81,7 @@ hts_status make_geo(const hts_params* p, int C, int H, int W, Geo& g) {
 // Workspace carve-up for one image.
 struct Carve {
   size_t gplanes, green, idx, fb_list, fb_count, cov, basis64, basis, fbasis, num, num64, cnt, hist,
-      poison, fxmax, total;
+      poison, fxmax, wsum64, total;
 };
 
 Carve carve(const Geo& g) {
@@ -99,6 +102,7 @@ Carve carve(const Geo& g) {
   c.num64 = o; o += al((size_t)g.C * g.H * g.W * 8);
   c.poison = o; o += al((size_t)g.H * g.W);
   c.fxmax = o; o += al(4);
+  c.wsum64 = o; o += al((size_t)g.H * g.W * 8);
   c.total = o;
   return c;
 }
@@ -134,6 +138,7 @@ ImgDesc make_desc(const Geo& g, const hts_params* p, char* ws, const Carve& c, c
   d.num64 = (unsigned long long*)(ws + c.num64);
   d.poison = (uint8_t*)(ws + c.poison);
   d.fxmax = (uint32_t*)(ws + c.fxmax);
+  d.wsum64 = weighted(p) ? (unsigned long long*)(ws + c.wsum64) : nullptr;
   d.H = g.H; d.W = g.W; d.Hp = g.Hp; d.Wp = g.Wp;
   d.nry = g.nry; d.nrx = g.nrx; d.n_ref = g.n_ref;
   d.ref_begin = 0; d.ref_count = g.n_ref;
@@ -171,7 +176,7 @@ int tuned_word(const hts_params* p, int C);
 // work group may take: the MFMA filter at K = 32 runs one work group per CU
 // (register bound), every other variant two.
 size_t filter_impl_lds(const hts_params* p, int C, bool valu, int ty, int tx) {
-  return valu ? filter_lds_bytes(C, p->K, p->stride, p->window, ty, tx)
+  return valu ? filter_lds_bytes(C, p->K, p->stride, p->window, ty, tx, weighted(p))
               : filter_mfma_lds_bytes(p->stride, p->window, ty, tx);
 }
 size_t filter_impl_budget(const hts_params* p, bool valu) {
@@ -181,7 +186,8 @@ size_t filter_impl_budget(const hts_params* p, bool valu) {
 Schedule schedule_for(const hts_params* p, int C) {
   Schedule s;
   const int tune = p->tune ? p->tune : tuned_word(p, C);
-  s.valu = ((tune >> 6) & 3) == 1 || !filter_mfma_supported(C, p->K);
+  // the weighted aggregation is built into the vector-ALU filter only
+  s.valu = ((tune >> 6) & 3) == 1 || !filter_mfma_supported(C, p->K) || weighted(p);
   int si = (tune & 15) - 1;
   if (si < 0 || si >= kNumShapes ||
       filter_impl_lds(p, C, s.valu, kShapes[si].ty, kShapes[si].tx) > kLdsMax) {
@@ -243,7 +249,9 @@ hts_status run_filter(const hts_params* p, int C, const Schedule& sc, ImgDesc d,
   const Launch L = make_launch(p, C, d, W_FILT, sc.fty, sc.ftx);
   if (sc.valu) HIPCHK(launch_filter(L, sc.fty, sc.ftx, adjoint, 0, s));
   else HIPCHK(launch_filter_mfma(L, sc.fty, sc.ftx, adjoint, 0, s));
-  if (!adjoint && d.cnt) return run_count(p, C, sc, d, hist_ready, s);
+  // weighted without a fixed-point weight plane: the filter adds the weight
+  // sums into cnt itself
+  if (!adjoint && d.cnt && !(weighted(p) && !d.wsum64)) return run_count(p, C, sc, d, hist_ready, s);
   return HTS_OK;
 }
 
@@ -276,8 +284,8 @@ std::string arch_name() {
 
 std::string tune_key(const hts_params* p, int C) {
   char buf[160];
-  std::snprintf(buf, sizeof(buf), "%s C=%d s=%d w=%d K=%d mode=%d", arch_name().c_str(), C,
-                p->stride, p->window, p->K, p->match_mode);
+  std::snprintf(buf, sizeof(buf), "%s C=%d s=%d w=%d K=%d mode=%d flags=%d", arch_name().c_str(), C,
+                p->stride, p->window, p->K, p->match_mode, p->flags);
   return buf;
 }
 
@@ -527,6 +535,7 @@ hts_status hts_filter(const hts_params* p, const float* noisy, int32_t C, int32_
   d.masks = masks;
   d.num64 = nullptr;      // estimates go to a float numerator (the caller's or scratch)
   d.poison = nullptr;
+  d.wsum64 = nullptr;     // weighted: the weight sums go to cnt
   if (num) {
     d.num = num;
     d.cnt = cnt;
@@ -542,6 +551,7 @@ hts_status hts_aggregate(const hts_params* p, const float* group_est, const int3
   Geo g;
   hts_status st = make_geo(p, C, H, W, g);
   if (st != HTS_OK) return st;
+  if (weighted(p)) return HTS_ERR_UNSUPPORTED;   // estimates carry no group weights
   if (!num || !cnt) return HTS_ERR_INVALID;
   if (group_est && !idx) return HTS_ERR_INVALID;
   if (ref_begin < 0 || ref_count < 0 || (long long)ref_begin + ref_count > g.n_ref) return HTS_ERR_INVALID;
@@ -634,6 +644,7 @@ hts_status hts_denoise_backward(const hts_params* p, const float* grad_out, cons
   Geo g;
   hts_status st = make_geo(p, C, H, W, g);
   if (st != HTS_OK) return st;
+  if (weighted(p)) return HTS_ERR_UNSUPPORTED;   // adjoint of the uniform average only
   if (!grad_out || !idx || !masks || !U || !V || !cnt || !grad_in || !ws) return HTS_ERR_INVALID;
   const Carve c = carve(g);
   if (ws_bytes < c.total) return HTS_ERR_WORKSPACE;
@@ -824,7 +835,7 @@ hts_status hts_autotune(const hts_params* p, int32_t C, int32_t H, int32_t W,
   // filter implementation and tile shape
   int best_shape = 0, best_valu = 0;
   float tf = 1e30f;
-  for (int valu = filter_mfma_supported(C, p->K) ? 0 : 1; valu <= 1; ++valu) {
+  for (int valu = filter_mfma_supported(C, p->K) && !weighted(p) ? 0 : 1; valu <= 1; ++valu) {
     for (int i = 0; i < kNumShapes; ++i) {
       if (filter_impl_lds(p, C, valu, kShapes[i].ty, kShapes[i].tx) > kLdsMax) continue;
       Schedule sc = base_sc;

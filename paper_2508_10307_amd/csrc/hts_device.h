@@ -156,15 +156,26 @@ __device__ inline void poison_group(const ImgDesc& d, const int* gidx, int grel,
 
 // Adds one LDS tile of fixed-point sums into the image numerator (exact
 // integer atomics, or float atomics into a float numerator).
+// Weighted aggregation: the weight plane (plane C of the tile) holds the
+// group weights times 2^16 in the same fixed point.
+constexpr float WEIGHT_SCALE = 65536.f;
+
 __device__ inline void flush_tile(const ImgDesc& d, const unsigned long long* acc, int C, int RA,
-                                  int CA, int AY0, int AX0, int AH, int AW) {
+                                  int CA, int AY0, int AX0, int AH, int AW, bool weighted = false) {
   const int HW = d.H * d.W;
-  for (int e = threadIdx.x; e < C * AH * AW; e += blockDim.x) {
+  const int NP = C + (weighted ? 1 : 0);
+  for (int e = threadIdx.x; e < NP * AH * AW; e += blockDim.x) {
     const int pl = e / (AH * AW), rem = e - pl * (AH * AW);
     const int y = rem / AW, x = rem - y * AW;
     const unsigned long long v = acc[(pl * RA + y) * CA + x];
     if (v != 0ull) {
-      const int gp = pl * HW + (AY0 + y) * d.W + AX0 + x;
+      const int pix = (AY0 + y) * d.W + AX0 + x;
+      if (pl == C) {   // weight sums
+        if (d.wsum64) atomicAdd(d.wsum64 + pix, v);
+        else if (d.cnt) atomicAdd(d.cnt + pix, (float)(fx_to_double(v) * (1.0 / WEIGHT_SCALE)));
+        continue;
+      }
+      const int gp = pl * HW + pix;
       if (d.num64) atomicAdd(d.num64 + gp, v);
       else atomicAdd(d.num + gp, (float)fx_to_double(v));
     }

@@ -61,6 +61,8 @@ struct ImgDesc {
   float beta;
   int32_t* ranks;          // [n_samples] rank of each sampled group (nullable)
   float* sigma_dev;        // [1] adjusted sigma; when set, the filter's tau is tau_mult * *sigma_dev
+  unsigned long long* wsum64; // [H][W] weight sums (fixed point, 2^-48 units) of the weighted
+                              // aggregation; nullable (then weights go to cnt, or are uniform)
   int32_t woff[W_NKIND];   // first global work item of each kind (batched)
   int32_t wcnt[W_NKIND];   // work items of each kind
 };
@@ -171,7 +173,7 @@ size_t filter_mfma_lds_bytes(int stride, int window, int ty, int tx);
 hipError_t launch_filter_mfma(const Launch& L, int ty, int tx, int adjoint, int grid, hipStream_t s);
 
 // Filter LDS bytes for a tile shape.
-size_t filter_lds_bytes(int C, int K, int stride, int window, int ty, int tx);
+size_t filter_lds_bytes(int C, int K, int stride, int window, int ty, int tx, bool weighted = false);
 size_t match_lds_bytes(int stride, int window);   // one plane slot: the minimum
 
 }  // namespace hts

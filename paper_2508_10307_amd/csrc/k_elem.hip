@@ -89,13 +89,15 @@ __global__ __launch_bounds__(256) void k_zero_accum(Launch L) {
       }
       if (d.cnt) d.cnt[p] = 0.0f;
       if (d.poison) d.poison[p] = 0;
+      if (d.wsum64) d.wsum64[p] = 0ull;
     }
   });
 }
 
-// Eq. 2 with uniform weights: out = num / cnt, from the fixed-point
-// numerator when the descriptor has one (scale divided out, one rounding,
-// in FP64), else from the float numerator.  Without cnt the numerator is
+// Eq. 2: out = num / cnt (uniform weights) or num / weight sum (weighted
+// aggregation, when the descriptor has the weight plane), from the
+// fixed-point numerator when the descriptor has one (scales divided out,
+// one rounding, in FP64), else from the float numerator.  Without cnt the numerator is
 // converted as it is (the adjoint's output).  Pixels marked in the poison
 // plane become NaN.
 __global__ __launch_bounds__(256) void k_finalize(Launch L) {
@@ -105,7 +107,9 @@ __global__ __launch_bounds__(256) void k_finalize(Launch L) {
     const int p1 = min(HW, p0 + PIX_CHUNK);
     for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
       if (d.num64) {
-        const double c = (d.cnt ? (double)d.cnt[p] : 1.0) * (double)fx_scale(d);
+        const double den = d.wsum64 ? fx_to_double(d.wsum64[p]) * (1.0 / WEIGHT_SCALE)
+                                    : (d.cnt ? (double)d.cnt[p] : 1.0);
+        const double c = den * (double)fx_scale(d);
         const bool bad = d.poison && d.poison[p];
         for (int ch = 0; ch < L.C; ++ch)
           d.out[ch * HW + p] = bad ? __builtin_nanf("") : (float)(fx_to_double(d.num64[ch * HW + p]) / c);

@@ -172,7 +172,10 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
   const int s = L.stride;
   const int TY = L.fty, TX = L.ftx;
   const int RA = (TY - 1) * s + 2 * r + PS, CA = (TX - 1) * s + 2 * r + PS;
-  const int NP = C;
+  // weighted aggregation (Eq. 2 with w_g = 1 / max(1, kept coefficients)):
+  // one more tile plane for the weight sums
+  const bool wtd = !ADJ && (L.flags & HTS_FLAG_WEIGHTED);
+  const int NP = C + (wtd ? 1 : 0);
   unsigned long long* acc = (unsigned long long*)fsm;          // [NP][RA][CA] fixed point
   float* T = fsm + (2 * NP * RA * CA + 3) / 4 * 4 + wave * TSCRATCH;   // transpose scratch
 
@@ -215,6 +218,7 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
       // nf stays 0 unless a gathered pixel or an estimate is not finite
       // (0 * inf and 0 * NaN are NaN)
       float nf = 0.f;
+      int nkeep = 0;   // kept coefficients of the group (weighted aggregation)
       float X[SPL][C][8];
       int py[SPL], px[SPL];
 #pragma unroll
@@ -335,6 +339,7 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
             for (int i = 0; i < 8; ++i) {
               const bool keep = fabsf(X[j][ch][i]) >= tauj[j];
               X[j][ch][i] = keep ? X[j][ch][i] * wj[j] : 0.f;
+              if (wtd) nkeep += __popcll(__ballot(keep && active));
               if (MASKS && d.masks) {
                 const unsigned long long bal = __ballot(keep);
                 const unsigned char byte = (unsigned char)((bal >> (8 * kl)) & 0xFFu);
@@ -373,6 +378,12 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
               X[j + st][ch][i] = u - v;
             }
 
+      // group weight (1 when uniform): scales the estimates, and is added to
+      // the weight plane for every pixel of the group's patches
+      const float wg = wtd ? 1.f / (float)max(nkeep, 1) : 1.f;
+      const unsigned long long fxw = wtd ? fx_from_float(wg * WEIGHT_SCALE) : 0ull;
+      const float sc1 = fxs * wg, sc3 = s3 * wg, rge = rfxs / wg;
+
       // ---- inverse t-SVD projection U * S * V^T (Eq. 20) and write-back ----
 #pragma unroll
       for (int j = 0; j < SPL; ++j) {
@@ -384,7 +395,7 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
           transpose_cr(T, kl, a, y);
           mv<false>(y, fb, FB_V0, 1.f, out[0]);    // out[b] = sum_c y[c] V[b][c]
 #pragma unroll
-          for (int b = 0; b < 8; ++b) out[0][b] *= fxs;   // fixed-point scale (a power of two)
+          for (int b = 0; b < 8; ++b) out[0][b] *= sc1;   // fixed-point scale (a power of two) x weight
         } else {
           float s0[8], s1r[8], s1i[8];
 #pragma unroll
@@ -410,9 +421,9 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
 #pragma unroll
           for (int b = 0; b < 8; ++b) {
             const float sr = p1r[b], si = p1i[b];
-            out[0][b] = (p0[b] + 2.f * sr) * s3;   // scaled by fxs (a power of two)
-            out[1][b] = (p0[b] - sr - SQRT3 * si) * s3;
-            out[2][b] = (p0[b] - sr + SQRT3 * si) * s3;
+            out[0][b] = (p0[b] + 2.f * sr) * sc3;   // scaled by fxs (a power of two) x weight
+            out[1][b] = (p0[b] - sr - SQRT3 * si) * sc3;
+            out[2][b] = (p0[b] - sr + SQRT3 * si) * sc3;
           }
         }
         const int ly = py[j] + a - AY0, lx = px[j] - AX0;
@@ -431,28 +442,34 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
 #pragma unroll
             for (int b = 0; b < 8; ++b) atomicAdd(rowp + b, fx_from_float(out[ch][b]));
           }
+          if (wtd) {
+            unsigned long long* wrow = acc + (C * RA + ly) * CA + lx;
+#pragma unroll
+            for (int b = 0; b < 8; ++b) atomicAdd(wrow + b, fxw);
+          }
           if (d.group_est) {
             float* ge = d.group_est + (((size_t)grel * K + k) * C) * PS2 + a * 8;
 #pragma unroll
             for (int ch = 0; ch < C; ++ch)
 #pragma unroll
-              for (int b = 0; b < 8; ++b) ge[ch * PS2 + b] = out[ch][b] * rfxs;
+              for (int b = 0; b < 8; ++b) ge[ch * PS2 + b] = out[ch][b] * rge;   // unweighted
           }
         }
       }
       if (__ballot(nf != 0.f)) poison_group(d, d.idx + (size_t)g * K, grel, K, C, rW, lane);
     }
     __syncthreads();
-    flush_tile(d, acc, C, RA, CA, AY0, AX0, AH, AW);
+    flush_tile(d, acc, C, RA, CA, AY0, AX0, AH, AW, wtd);
   });
 }
 
-size_t filter_lds_bytes(int C, int K, int stride, int window, int ty, int tx) {
+size_t filter_lds_bytes(int C, int K, int stride, int window, int ty, int tx, bool weighted) {
   (void)K;
   const int r = (window - 1) / 2;
   const size_t RA = (size_t)(ty - 1) * stride + 2 * r + PS;
   const size_t CA = (size_t)(tx - 1) * stride + 2 * r + PS;
-  return ((2 * C * RA * CA + 3) / 4 * 4 + 4 * TSCRATCH) * sizeof(float);
+  const size_t NP = C + (weighted ? 1 : 0);
+  return ((2 * NP * RA * CA + 3) / 4 * 4 + 4 * TSCRATCH) * sizeof(float);
 }
 
 template <int C, int ADJ, int MASKS, int BATCH>
@@ -480,7 +497,8 @@ static hipError_t launch_filter_c(const Launch& L, int g, size_t lds, hipStream_
 hipError_t launch_filter(const Launch& L, int ty, int tx, int adjoint, int grid, hipStream_t s) {
   if (L.total <= 0) return hipSuccess;
   const int g = xcd_grid(grid > 0 && grid < L.total ? grid : L.total);
-  const size_t lds = filter_lds_bytes(L.C, L.K, L.stride, L.window, ty, tx);
+  const size_t lds = filter_lds_bytes(L.C, L.K, L.stride, L.window, ty, tx,
+                                     !adjoint && (L.flags & HTS_FLAG_WEIGHTED));
   // batched launches (descriptor table) never export masks nor run the adjoint
   const bool batch = L.table != nullptr;
   if (batch && adjoint) return hipErrorInvalidValue;

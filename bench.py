@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-path comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adaptive", action="store_true",
-                    help="skip the A-Haar-tSVD (adaptive sigma) batch timing")
+                    help="skip the A-Haar-tSVD (adaptive sigma) and weighted-aggregation batch timings")
     ap.add_argument("--batch-api", type=int, default=1,
                     help="1: hts_denoise_batch (one graph); 0: one hts_denoise per image")
     ap.add_argument("--tune", type=int, default=0)
@@ -258,6 +258,19 @@ def main():
                                                if abs(float(a) - float(b)) > 0))}
         del ws_a
 
+    # ---- weighted aggregation (Eq. 2 with w_g = 1/max(1, kept coefficients)) ----
+    weighted = None
+    if not args.no_adaptive and args.batch_api:
+        pw = params(L.HTS_MATCH_BF16)
+        pw.flags = L.HTS_FLAG_WEIGHTED
+        ws_w = torch.empty(api.batch_workspace_size(pw, xs, outs, sig), dtype=torch.uint8,
+                           device=dev)
+        msw = timed(lambda: api.hts_denoise_batch(xs, sig, pw, outs=outs, ws=ws_w),
+                    max(1, args.steps // 2), 1)
+        weighted = {"value": mpix / (msw / 1e3), "ms_per_step": round(msw, 3),
+                    "psnr_db": round(psnr_all(), 4)}
+        del ws_w
+
     # ---- roofline of the dominant kernel: the fused filter, timed live ----
     # One eager launch per image (the same filter the batched graph runs, as
     # its single-image instantiation), timed with HIP events on its stream:
@@ -340,6 +353,7 @@ def main():
                      "match_stage_speedup_bf16_vs_fp32": round(mtime32 / mtime, 3),
                      "filter_sum": round(ftime, 3)},
         "adaptive": adaptive,
+        "weighted": weighted,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

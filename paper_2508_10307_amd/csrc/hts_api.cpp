@@ -189,8 +189,12 @@ Schedule schedule_for(const hts_params* p, int C) {
   // the weighted aggregation is built into the vector-ALU filter only
   s.valu = ((tune >> 6) & 3) == 1 || !filter_mfma_supported(C, p->K) || weighted(p);
   int si = (tune & 15) - 1;
+  // a tune word chosen without the weight plane may no longer fit beside a
+  // second work group: then the largest shape that does
   if (si < 0 || si >= kNumShapes ||
-      filter_impl_lds(p, C, s.valu, kShapes[si].ty, kShapes[si].tx) > kLdsMax) {
+      filter_impl_lds(p, C, s.valu, kShapes[si].ty, kShapes[si].tx) > kLdsMax ||
+      (weighted(p) &&
+       filter_impl_lds(p, C, s.valu, kShapes[si].ty, kShapes[si].tx) > filter_impl_budget(p, s.valu))) {
     si = kNumShapes - 1;
     for (int i = 0; i < kNumShapes; ++i)
       if (filter_impl_lds(p, C, s.valu, kShapes[i].ty, kShapes[i].tx) <= filter_impl_budget(p, s.valu)) { si = i; break; }

@@ -160,7 +160,9 @@ __device__ inline float haar_unscale(int k, int K) {
 }
 
 // MASKS = 1 exports the keep-masks (when d.masks is set).
-template <int C, int SPL, int ADJ, int MASKS, int BATCH>
+// WT = 1: weighted aggregation (a separate instantiation, so that the
+// uniform one keeps its register budget).
+template <int C, int SPL, int ADJ, int MASKS, int BATCH, int WT>
 __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
   extern __shared__ __align__(16) float fsm[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -174,8 +176,8 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
   const int RA = (TY - 1) * s + 2 * r + PS, CA = (TX - 1) * s + 2 * r + PS;
   // weighted aggregation (Eq. 2 with w_g = 1 / max(1, kept coefficients)):
   // one more tile plane for the weight sums
-  const bool wtd = !ADJ && (L.flags & HTS_FLAG_WEIGHTED);
-  const int NP = C + (wtd ? 1 : 0);
+  constexpr bool wtd = WT != 0 && !ADJ;
+  constexpr int NP = C + (wtd ? 1 : 0);
   unsigned long long* acc = (unsigned long long*)fsm;          // [NP][RA][CA] fixed point
   float* T = fsm + (2 * NP * RA * CA + 3) / 4 * 4 + wave * TSCRATCH;   // transpose scratch
 
@@ -472,18 +474,18 @@ size_t filter_lds_bytes(int C, int K, int stride, int window, int ty, int tx, bo
   return ((2 * NP * RA * CA + 3) / 4 * 4 + 4 * TSCRATCH) * sizeof(float);
 }
 
-template <int C, int ADJ, int MASKS, int BATCH>
+template <int C, int ADJ, int MASKS, int BATCH, int WT = 0>
 static hipError_t launch_filter_c(const Launch& L, int g, size_t lds, hipStream_t s) {
   switch (L.K) {
     case 2: case 4: case 8:
-      hipLaunchKernelGGL((k_filter<C, 1, ADJ, MASKS, BATCH>), dim3(g), dim3(256), lds, s, L); break;
+      hipLaunchKernelGGL((k_filter<C, 1, ADJ, MASKS, BATCH, WT>), dim3(g), dim3(256), lds, s, L); break;
     case 16:
-      hipLaunchKernelGGL((k_filter<C, 2, ADJ, MASKS, BATCH>), dim3(g), dim3(256), lds, s, L); break;
+      hipLaunchKernelGGL((k_filter<C, 2, ADJ, MASKS, BATCH, WT>), dim3(g), dim3(256), lds, s, L); break;
     case 32:
-      hipLaunchKernelGGL((k_filter<C, 4, ADJ, MASKS, BATCH>), dim3(g), dim3(256), lds, s, L); break;
+      hipLaunchKernelGGL((k_filter<C, 4, ADJ, MASKS, BATCH, WT>), dim3(g), dim3(256), lds, s, L); break;
     case 64:
       if constexpr (C == 1) {
-        hipLaunchKernelGGL((k_filter<C, 8, ADJ, MASKS, BATCH>), dim3(g), dim3(256), lds, s, L);
+        hipLaunchKernelGGL((k_filter<C, 8, ADJ, MASKS, BATCH, WT>), dim3(g), dim3(256), lds, s, L);
         break;
       } else {
         return hipErrorInvalidValue;
@@ -497,12 +499,20 @@ static hipError_t launch_filter_c(const Launch& L, int g, size_t lds, hipStream_
 hipError_t launch_filter(const Launch& L, int ty, int tx, int adjoint, int grid, hipStream_t s) {
   if (L.total <= 0) return hipSuccess;
   const int g = xcd_grid(grid > 0 && grid < L.total ? grid : L.total);
-  const size_t lds = filter_lds_bytes(L.C, L.K, L.stride, L.window, ty, tx,
-                                     !adjoint && (L.flags & HTS_FLAG_WEIGHTED));
+  const bool wt = !adjoint && (L.flags & HTS_FLAG_WEIGHTED);
+  const size_t lds = filter_lds_bytes(L.C, L.K, L.stride, L.window, ty, tx, wt);
   // batched launches (descriptor table) never export masks nor run the adjoint
   const bool batch = L.table != nullptr;
   if (batch && adjoint) return hipErrorInvalidValue;
   const bool masks = !batch && L.one.masks;
+  if (wt) {   // weighted aggregation: no adjoint
+    if (L.C == 1) {
+      if (batch) return launch_filter_c<1, 0, 0, 1, 1>(L, g, lds, s);
+      return masks ? launch_filter_c<1, 0, 1, 0, 1>(L, g, lds, s) : launch_filter_c<1, 0, 0, 0, 1>(L, g, lds, s);
+    }
+    if (batch) return launch_filter_c<3, 0, 0, 1, 1>(L, g, lds, s);
+    return masks ? launch_filter_c<3, 0, 1, 0, 1>(L, g, lds, s) : launch_filter_c<3, 0, 0, 0, 1>(L, g, lds, s);
+  }
   if (L.C == 1) {
     if (batch) return launch_filter_c<1, 0, 0, 1>(L, g, lds, s);
     if (adjoint) return launch_filter_c<1, 1, 0, 0>(L, g, lds, s);

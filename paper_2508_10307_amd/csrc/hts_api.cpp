@@ -373,6 +373,33 @@ Launch batch_launch(const hts_params* p, int C, const ImgDesc* table, int n, int
   return L;
 }
 
+// Second stream and fork/join events of the batch pipeline, per device,
+// created on first use (default priority); side == nullptr if creation
+// failed, and the pipeline then runs on one stream.  Callers hold
+// g_graph_mu.
+struct Branch {
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+Branch branch_for_device() {
+  static Branch br[64];
+  static bool tried[64] = {false};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return Branch();
+  if (!tried[dev]) {
+    tried[dev] = true;
+    Branch b;
+    if (hipStreamCreateWithFlags(&b.side, hipStreamNonBlocking) == hipSuccess &&
+        hipEventCreateWithFlags(&b.fork, hipEventDisableTiming) == hipSuccess &&
+        hipEventCreateWithFlags(&b.join, hipEventDisableTiming) == hipSuccess) {
+      br[dev] = b;
+    } else {
+      (void)hipGetLastError();
+    }
+  }
+  return br[dev];
+}
+
 // All stages of Algorithm 1 over the batch, as persistent launches sized to
 // the device (work groups loop over the global (image, item) list).
 hts_status enqueue_batch(const hts_params* p, int C, const BatchPlan& plan, const ImgDesc* table,
@@ -387,16 +414,28 @@ hts_status enqueue_batch(const hts_params* p, int C, const BatchPlan& plan, cons
     return L;
   };
   HIPCHK(launch_reset_counters(LK(-1), s));
+  // The basis (covariances, eigen-solve, Fourier slices) depends on the
+  // images only: it runs on a second stream beside quantisation and matching
+  // (a branch of the captured graph) and joins before the filter.
+  const Branch br = branch_for_device();
+  hipStream_t bs = s;
+  if (br.side) {
+    HIPCHK(hipEventRecord(br.fork, s));
+    HIPCHK(hipStreamWaitEvent(br.side, br.fork, 0));
+    bs = br.side;
+  }
   HIPCHK(launch_quant(LC(W_PIX), cus * 8, s));
   HIPCHK(launch_gcp(LK(W_REF), cus * 8, s));
   HIPCHK(launch_match(LC(W_MATCH), p->match_mode, sc.terms, cus * 2, s));
+  HIPCHK(launch_cov(LK(W_COV), cus * 4, bs));
+  HIPCHK(launch_eig(LK(-1), bs));
+  HIPCHK(launch_fbasis(LK(-1), nullptr, nullptr, bs));
+  if (br.side) HIPCHK(hipEventRecord(br.join, bs));
   HIPCHK(launch_match_fallback(LC(-1), cus, s));
   if (plan.descs[0].n_samples > 0) HIPCHK(launch_vote(LK(-1), s));   // A-Haar-tSVD sigma
-  HIPCHK(launch_cov(LK(W_COV), cus * 4, s));
-  HIPCHK(launch_eig(LK(-1), s));
-  HIPCHK(launch_fbasis(LK(-1), nullptr, nullptr, s));
   HIPCHK(launch_zero_accum(LK(W_PIX), cus * 8, s));
   HIPCHK(launch_count_box(LK(W_BOX), cus * 8, s));
+  if (br.side) HIPCHK(hipStreamWaitEvent(s, br.join, 0));
   if (sc.valu) HIPCHK(launch_filter(LK(W_FILT), sc.fty, sc.ftx, 0, cus * 2, s));
   else HIPCHK(launch_filter_mfma(LK(W_FILT), sc.fty, sc.ftx, 0, cus * 2, s));
   HIPCHK(launch_finalize(LK(W_PIX), cus * 8, s));

@@ -59,6 +59,35 @@ def hard_threshold(S: np.ndarray, tau: float):
     return np.where(keep, S, 0.0), keep
 
 
+def fourier_threshold(S: np.ndarray, tau: float, mask: np.ndarray = None):
+    """Hard threshold in the channel-Fourier domain (reading F1; the paper
+    thresholds the real core tensor, Eq. 19, and this variant keeps whole
+    conjugate pairs, so it does not depend on a sign or phase convention).
+    With F = DFT of S along the channel mode (c = 3): the f = 0 coefficient
+    has orthonormal magnitude |F_0| / sqrt(3), the pair (f = 1, f = 2 =
+    conj f = 1) the magnitude sqrt(2/3) |F_1| of its two real coordinates;
+    each is kept iff its magnitude >= tau.  For c = 1 this is Eq. 19.
+    S [..., C, ps, ps].  Returns (thresholded S, keep [..., C, ps, ps] with
+    channel f holding the decision of frequency f, magnitudes a)."""
+    C = S.shape[-3]
+    if C == 1:
+        a = np.abs(S)
+        keep = a >= tau if mask is None else np.asarray(mask, dtype=bool)
+        return np.where(keep, S, 0.0), keep, a
+    assert C == 3
+    F = np.fft.fft(S, axis=-3)
+    a = np.empty(S.shape)
+    a[..., 0, :, :] = np.abs(F[..., 0, :, :]) / np.sqrt(3.0)
+    a[..., 1, :, :] = np.sqrt(2.0 / 3.0) * np.abs(F[..., 1, :, :])
+    a[..., 2, :, :] = a[..., 1, :, :]
+    if mask is None:
+        keep = a >= tau
+    else:
+        mask = np.asarray(mask, dtype=bool)
+        keep = np.stack([mask[..., 0, :, :], mask[..., 1, :, :], mask[..., 1, :, :]], axis=-3)
+    return np.fft.ifft(np.where(keep, F, 0.0), axis=-3).real, keep, a
+
+
 def aggregate(est: np.ndarray, idx: np.ndarray, C: int, H: int, W: int, ps: int,
               w: np.ndarray = None):
     """Step 3 / Eq. 2.  Uniform weights ("averagely written back", the

@@ -23,7 +23,7 @@ def unpack_masks(words: np.ndarray, n: int, K: int, C: int, ps: int = 8) -> np.n
 
 def denoise(y, sigma, ps=8, stride=3, window=21, K=16, tau_mult=2.7, gcp_num=6,
             gcp_den=5, idx=None, U=None, V=None, mask=None, return_mask=False,
-            chunk=2048, weighted=False):
+            chunk=2048, weighted=False, fourier=False):
     """Denoise y [C][H][W] with noise level sigma.
 
     idx      optional [n_ref, K] match indices (else Step 1 is run here);
@@ -33,6 +33,9 @@ def denoise(y, sigma, ps=8, stride=3, window=21, K=16, tau_mult=2.7, gcp_num=6,
              is reported with the oracle's margin | |S| - tau |.
     weighted Eq. 2 with the group weights of filtering.group_weights (from
              the keep-mask in use) instead of uniform ones.
+    fourier  threshold in the channel-Fourier domain (filtering.
+             fourier_threshold) instead of Eq. 19 on the real core tensor;
+             masks then hold the decision of frequency f in channel f.
     Returns a dict with out (= num / cnt), num, cnt, idx, U, V, UF, VF, and,
     when asked, the oracle's keep-mask and the override report."""
     y = np.asarray(y)
@@ -58,18 +61,25 @@ def denoise(y, sigma, ps=8, stride=3, window=21, K=16, tau_mult=2.7, gcp_num=6,
         ic = idx[c0:c0 + chunk]
         G = _f.gather_groups(y, ic, ps)
         S = _f.haar_group(_f.tsvd_forward(G, UF, VF), K)
-        St, keep = _f.hard_threshold(S, tau)
+        if fourier:
+            St, keep, mag = _f.fourier_threshold(S, tau)
+        else:
+            St, keep = _f.hard_threshold(S, tau)
+            mag = np.abs(S)
         if return_mask:
             own_masks.append(keep)
         if mask is not None:
             mk = np.asarray(mask[c0:c0 + chunk], dtype=bool)
+            if fourier:
+                St, mk, _ = _f.fourier_threshold(S, tau, mk)
+            else:
+                St = np.where(mk, S, 0.0)
             diff = mk != keep
             if diff.any():
-                marg = np.abs(np.abs(S[diff]) - tau)
+                marg = np.abs(mag[diff] - tau)
                 n_over += int(diff.sum())
                 max_margin = max(max_margin, float(marg.max()))
                 over_margins.append(marg)
-            St = np.where(mk, S, 0.0)
             keep = mk
         est = _f.tsvd_inverse(_f.haar_group_inverse(St, K), UF, VF)
         wg = _f.group_weights(keep) if weighted else None

@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-path comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adaptive", action="store_true",
-                    help="skip the A-Haar-tSVD (adaptive sigma) and weighted-aggregation batch timings")
+                    help="skip the A-Haar-tSVD, weighted-aggregation and Fourier-threshold batch timings")
     ap.add_argument("--batch-api", type=int, default=1,
                     help="1: hts_denoise_batch (one graph); 0: one hts_denoise per image")
     ap.add_argument("--tune", type=int, default=0)
@@ -259,7 +259,7 @@ def main():
         del ws_a
 
     # ---- weighted aggregation (Eq. 2 with w_g = 1/max(1, kept coefficients)) ----
-    weighted = None
+    weighted = fourier = None
     if not args.no_adaptive and args.batch_api:
         pw = params(L.HTS_MATCH_BF16)
         pw.flags = L.HTS_FLAG_WEIGHTED
@@ -270,6 +270,16 @@ def main():
         weighted = {"value": mpix / (msw / 1e3), "ms_per_step": round(msw, 3),
                     "psnr_db": round(psnr_all(), 4)}
         del ws_w
+        # channel-Fourier magnitude threshold (whole conjugate pairs)
+        pf = params(L.HTS_MATCH_BF16)
+        pf.flags = L.HTS_FLAG_FOURIER_THRESHOLD
+        ws_f = torch.empty(api.batch_workspace_size(pf, xs, outs, sig), dtype=torch.uint8,
+                           device=dev)
+        msf = timed(lambda: api.hts_denoise_batch(xs, sig, pf, outs=outs, ws=ws_f),
+                    max(1, args.steps // 2), 1)
+        fourier = {"value": mpix / (msf / 1e3), "ms_per_step": round(msf, 3),
+                   "psnr_db": round(psnr_all(), 4)}
+        del ws_f
 
     # ---- roofline of the dominant kernel: the fused filter, timed live ----
     # One eager launch per image (the same filter the batched graph runs, as
@@ -354,6 +364,7 @@ def main():
                      "filter_sum": round(ftime, 3)},
         "adaptive": adaptive,
         "weighted": weighted,
+        "fourier_threshold": fourier,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

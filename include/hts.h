@@ -86,6 +86,16 @@ typedef enum {
  * weighted); the vector-ALU filter runs.  hts_aggregate and
  * hts_denoise_backward return HTS_ERR_UNSUPPORTED with it. */
 #define HTS_FLAG_WEIGHTED 1
+/* hts_params.flags: threshold in the channel-Fourier domain (c = 3) instead
+ * of Eq. 19 on the real core tensor: in the Haar domain of each group, the
+ * f = 0 coefficient F_0 (DFT along the channel mode) is kept iff
+ * |F_0| / sqrt(3) >= tau and the conjugate pair f = 1, 2 iff
+ * sqrt(2/3) |F_1| >= tau (their orthonormal magnitudes), so whole pairs are
+ * kept or dropped.  Exported masks then hold the decision of frequency f in
+ * channel f.  No effect for c = 1.  Honoured by hts_denoise,
+ * hts_denoise_batch(_adaptive) and hts_filter (vector-ALU filter);
+ * hts_denoise_backward returns HTS_ERR_UNSUPPORTED with it. */
+#define HTS_FLAG_FOURIER_THRESHOLD 2
 
 typedef struct {
   int32_t ps;          /* patch size; must be 8                                  */
@@ -96,7 +106,7 @@ typedef struct {
   int32_t gcp_num;     /* gamma = gcp_num / gcp_den (Eq. 10; 6/5 = 1.2), 1..64    */
   int32_t gcp_den;
   int32_t match_mode;  /* hts_match_mode                                          */
-  int32_t flags;       /* 0 or HTS_FLAG_WEIGHTED                                  */
+  int32_t flags;       /* 0 or HTS_FLAG_WEIGHTED | HTS_FLAG_FOURIER_THRESHOLD       */
   int32_t tune;        /* 0 = autotuned/default launch schedule, else a schedule id */
 } hts_params;
 

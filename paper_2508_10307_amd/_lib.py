@@ -18,6 +18,7 @@ HTS_ERR_HIP = 4
 HTS_MATCH_BF16 = 0
 HTS_MATCH_FP32 = 1
 HTS_FLAG_WEIGHTED = 1
+HTS_FLAG_FOURIER_THRESHOLD = 2
 
 c_i32 = ctypes.c_int32
 c_f32 = ctypes.c_float

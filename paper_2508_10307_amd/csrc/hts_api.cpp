@@ -37,6 +37,7 @@ struct Geo {
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 bool weighted(const hts_params* p) { return (p->flags & HTS_FLAG_WEIGHTED) != 0; }
+bool fourier(const hts_params* p, int C) { return C == 3 && (p->flags & HTS_FLAG_FOURIER_THRESHOLD) != 0; }
 
 hts_status check_params(const hts_params* p, int C) {
   if (!p) return HTS_ERR_INVALID;
@@ -49,7 +50,7 @@ hts_status check_params(const hts_params* p, int C) {
   if (!(p->tau_mult >= 0.f) || !std::isfinite(p->tau_mult)) return HTS_ERR_INVALID;
   if (p->gcp_num < 1 || p->gcp_num > 64 || p->gcp_den < 1 || p->gcp_den > 64) return HTS_ERR_INVALID;
   if (p->match_mode != HTS_MATCH_BF16 && p->match_mode != HTS_MATCH_FP32) return HTS_ERR_INVALID;
-  if ((p->flags & ~HTS_FLAG_WEIGHTED) != 0) return HTS_ERR_INVALID;
+  if ((p->flags & ~(HTS_FLAG_WEIGHTED | HTS_FLAG_FOURIER_THRESHOLD)) != 0) return HTS_ERR_INVALID;
   if ((size_t)match_lds_bytes(p->stride, p->window) > kLdsMax) return HTS_ERR_UNSUPPORTED;
   if (filter_lds_bytes(C, p->K, p->stride, p->window, 1, 1, weighted(p)) > kLdsMax)
     return HTS_ERR_UNSUPPORTED;
@@ -186,8 +187,10 @@ size_t filter_impl_budget(const hts_params* p, bool valu) {
 Schedule schedule_for(const hts_params* p, int C) {
   Schedule s;
   const int tune = p->tune ? p->tune : tuned_word(p, C);
-  // the weighted aggregation is built into the vector-ALU filter only
-  s.valu = ((tune >> 6) & 3) == 1 || !filter_mfma_supported(C, p->K) || weighted(p);
+  // the weighted aggregation and the Fourier threshold are built into the
+  // vector-ALU filter only
+  s.valu = ((tune >> 6) & 3) == 1 || !filter_mfma_supported(C, p->K) || weighted(p) ||
+           fourier(p, C);
   int si = (tune & 15) - 1;
   // a tune word chosen without the weight plane may no longer fit beside a
   // second work group: then the largest shape that does
@@ -688,6 +691,7 @@ hts_status hts_denoise_backward(const hts_params* p, const float* grad_out, cons
   hts_status st = make_geo(p, C, H, W, g);
   if (st != HTS_OK) return st;
   if (weighted(p)) return HTS_ERR_UNSUPPORTED;   // adjoint of the uniform average only
+  if (fourier(p, C)) return HTS_ERR_UNSUPPORTED;  // masks of the real-domain threshold only
   if (!grad_out || !idx || !masks || !U || !V || !cnt || !grad_in || !ws) return HTS_ERR_INVALID;
   const Carve c = carve(g);
   if (ws_bytes < c.total) return HTS_ERR_WORKSPACE;
@@ -878,7 +882,8 @@ hts_status hts_autotune(const hts_params* p, int32_t C, int32_t H, int32_t W,
   // filter implementation and tile shape
   int best_shape = 0, best_valu = 0;
   float tf = 1e30f;
-  for (int valu = filter_mfma_supported(C, p->K) && !weighted(p) ? 0 : 1; valu <= 1; ++valu) {
+  for (int valu = filter_mfma_supported(C, p->K) && !weighted(p) && !fourier(p, C) ? 0 : 1;
+       valu <= 1; ++valu) {
     for (int i = 0; i < kNumShapes; ++i) {
       if (filter_impl_lds(p, C, valu, kShapes[i].ty, kShapes[i].tx) > kLdsMax) continue;
       Schedule sc = base_sc;

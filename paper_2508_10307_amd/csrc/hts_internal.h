@@ -174,6 +174,9 @@ hipError_t launch_filter_mfma(const Launch& L, int ty, int tx, int adjoint, int 
 
 // Filter LDS bytes for a tile shape.
 size_t filter_lds_bytes(int C, int K, int stride, int window, int ty, int tx, bool weighted = false);
+// channel-Fourier threshold variant of the vector-ALU filter (c = 3)
+hipError_t launch_filter_ft(const Launch& L, int g, size_t lds, bool batch, bool masks, bool wt,
+                            hipStream_t s);
 size_t match_lds_bytes(int stride, int window);   // one plane slot: the minimum
 
 }  // namespace hts

@@ -86,7 +86,8 @@ def _ws_status(lib, C=1, H=64, W=64, **kw):
     ({"tau_mult": float("nan")}, 1, (64, 64), L.HTS_ERR_INVALID),
     ({"gcp_num": 0}, 3, (64, 64), L.HTS_ERR_INVALID),
     ({"match_mode": 7}, 1, (64, 64), L.HTS_ERR_INVALID),
-    ({"flags": 2}, 1, (64, 64), L.HTS_ERR_INVALID),
+    ({"flags": 4}, 1, (64, 64), L.HTS_ERR_INVALID),
+    ({"flags": 3}, 3, (64, 64), L.HTS_OK),
     ({"flags": 1}, 1, (64, 64), L.HTS_OK),
 ])
 def test_parameter_validation(lib, kw, C, HW, status):

@@ -190,6 +190,25 @@ typedef struct {
   float sigma;
 } hts_image;
 
+/* Surrogate derivative of a loss with respect to tau_mult (an adjoint
+ * extension: the hard threshold of Eq. 19 has a zero derivative almost
+ * everywhere, so hts_denoise_backward returns 0 for it).  The keep-mask is
+ * relaxed to m(s) = logistic((|s| - tau) / eps), eps = kappa * sigma, and with
+ * idx, U, V and cnt (as hts_denoise saves them) frozen:
+ *   grad_tau_mult[0] = sigma * sum over groups and coefficients of
+ *                      r * s * (-logistic'(u) / eps),  u = (|s| - tau) / eps,
+ * where s and r are the orthonormal Haar / t-SVD coefficients (Eq. 18) of
+ * the groups of noisy and of grad_out / cnt (device [C][H][W]).  FP64 sums,
+ * added in a fixed order (the same bits on every run); device float out.
+ * sigma = 0 gives 0.  Errors: HTS_ERR_INVALID for null pointers, sigma < 0,
+ * kappa <= 0 or non-finite; HTS_ERR_UNSUPPORTED with flags set; the
+ * parameter and workspace checks of hts_denoise. */
+hts_status hts_denoise_grad_tau(const hts_params* p, const float* noisy, const float* grad_out,
+                                const int32_t* idx, const float* U, const float* V,
+                                const float* cnt, int32_t C, int32_t H, int32_t W, float sigma,
+                                float kappa, float* grad_tau_mult, void* ws, size_t ws_bytes,
+                                void* stream);
+
 /* Workspace bytes for hts_denoise_batch over these n images (host array). */
 hts_status hts_batch_workspace_size(const hts_params* p, const hts_image* imgs, int32_t n,
                                     size_t* bytes);

@@ -56,6 +56,8 @@ SIGNATURES = {
     "hts_batch_workspace_size": (c_i32, [P, ctypes.POINTER(HtsImage), c_i32,
                                          ctypes.POINTER(c_sz)]),
     "hts_denoise_batch": (c_i32, [P, ctypes.POINTER(HtsImage), c_i32, c_vp, c_sz, c_vp]),
+    "hts_denoise_grad_tau": (c_i32, [P, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_i32, c_i32,
+                                     c_f32, c_f32, c_vp, c_vp, c_sz, c_vp]),
     "hts_adapt_sigma": (c_i32, [P, c_vp, c_i32, c_i32, c_i32, c_vp, c_vp, c_i32, c_f32, c_f32,
                                 c_i32, c_vp, c_vp, c_vp]),
     "hts_denoise_batch_adaptive": (c_i32, [P, ctypes.POINTER(HtsImage), c_i32, c_vp, c_i32,

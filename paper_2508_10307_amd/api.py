@@ -342,25 +342,54 @@ def hts_autotune(p: Params, C, H, W, cache_path: Optional[str] = None, device="c
     return out.value
 
 
+def hts_denoise_grad_tau(noisy, grad_out, st, sigma: float, p: Params, kappa: float = 0.1,
+                         ws=None):
+    """Surrogate derivative of a loss with respect to tau_mult (logistic
+    relaxation of the keep-mask, width kappa * sigma), with the grouping,
+    basis and coverage count st of hts_denoise(save=True) frozen.  Returns a
+    device scalar tensor [1]."""
+    x = _img(noisy)
+    g = _img(grad_out, "grad_out")
+    C, H, W = x.shape
+    dev = x.device
+    out = torch.empty(1, dtype=torch.float32, device=dev)
+    ws = workspace(p, C, H, W, dev) if ws is None else ws
+    pc = p.c()
+    L.check("hts_denoise_grad_tau", L.load().hts_denoise_grad_tau(
+        ctypes.byref(pc), _ptr(x), _ptr(g), _ptr(st["idx"]), _ptr(st["U"]), _ptr(st["V"]),
+        _ptr(st["cnt"]), C, H, W, float(sigma), float(kappa), _ptr(out), _ptr(ws), ws.numel(),
+        _stream(dev)))
+    return out
+
+
 class HaarTSVD(torch.autograd.Function):
     """Differentiable Haar-tSVD denoiser: forward = hts_denoise; backward =
     the hand-written adjoint kernel with match indices, threshold masks,
-    basis and coverage counts frozen at the forward pass.  The gradient with
-    respect to the threshold multiplier is zero (it only moves the frozen
-    masks)."""
+    basis and coverage counts frozen at the forward pass.  The exact
+    gradient with respect to the threshold multiplier is zero (it only moves
+    the frozen masks); with tau_kappa > 0 the backward returns instead the
+    surrogate derivative of hts_denoise_grad_tau (relaxation width
+    tau_kappa * sigma)."""
 
     @staticmethod
-    def forward(ctx, noisy, sigma, tau_mult, p: Params):
+    def forward(ctx, noisy, sigma, tau_mult, p: Params, tau_kappa: float = 0.0):
         q = Params(**{**p.__dict__, "tau_mult": float(tau_mult)})
-        out, st = hts_denoise(noisy.detach(), float(sigma), q, save=True)
+        x = noisy.detach()
+        out, st = hts_denoise(x, float(sigma), q, save=True)
         ctx.st = st
         ctx.p = q
+        ctx.sigma = float(sigma)
+        ctx.kappa = float(tau_kappa)
+        ctx.noisy = x if ctx.kappa > 0 else None
         return out
 
     @staticmethod
     def backward(ctx, grad):
-        gin, gtau = hts_denoise_backward(grad.contiguous(), ctx.st, ctx.p)
-        return gin, None, gtau.reshape(()), None
+        g = grad.contiguous()
+        gin, gtau = hts_denoise_backward(g, ctx.st, ctx.p)
+        if ctx.kappa > 0:
+            gtau = hts_denoise_grad_tau(ctx.noisy, g, ctx.st, ctx.sigma, ctx.p, ctx.kappa)
+        return gin, None, gtau.reshape(()), None, None
 
 
 def denoise(x: torch.Tensor, sigma: float, **params) -> torch.Tensor:

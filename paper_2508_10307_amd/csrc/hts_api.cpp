@@ -717,6 +717,36 @@ hts_status hts_denoise_backward(const hts_params* p, const float* grad_out, cons
   return HTS_OK;
 }
 
+hts_status hts_denoise_grad_tau(const hts_params* p, const float* noisy, const float* grad_out,
+                                const int32_t* idx, const float* U, const float* V,
+                                const float* cnt, int32_t C, int32_t H, int32_t W, float sigma,
+                                float kappa, float* grad_tau_mult, void* ws, size_t ws_bytes,
+                                void* stream) {
+  Geo g;
+  hts_status st = make_geo(p, C, H, W, g);
+  if (st != HTS_OK) return st;
+  if (!noisy || !grad_out || !idx || !U || !V || !cnt || !grad_tau_mult || !ws) return HTS_ERR_INVALID;
+  if (!(sigma >= 0.f) || !std::isfinite(sigma)) return HTS_ERR_INVALID;
+  if (!(kappa > 0.f) || !std::isfinite(kappa)) return HTS_ERR_INVALID;
+  if (weighted(p) || fourier(p, C)) return HTS_ERR_UNSUPPORTED;
+  const Carve c = carve(g);
+  if (ws_bytes < c.total) return HTS_ERR_WORKSPACE;
+  const Schedule sc = schedule_for(p, C);
+  hipStream_t s = (hipStream_t)stream;
+  if (sigma == 0.f) {   // tau = 0 and a zero-width relaxation: no defined surrogate slope
+    HIPCHK(launch_fill(grad_tau_mult, 1, 0.f, s));
+    return HTS_OK;
+  }
+  ImgDesc d = make_desc(g, p, (char*)ws, c, noisy, sigma, sc.fty, sc.ftx);
+  d.idx = const_cast<int32_t*>(idx);
+  d.cnt = const_cast<float*>(cnt);
+  HIPCHK(launch_fbasis(make_launch(p, C, d, -1, sc.fty, sc.ftx), U, V, s));
+  // the fixed-point numerator plane (>= 8 * n_ref bytes) holds the per-group partials
+  HIPCHK(launch_taugrad(make_launch(p, C, d, -1, sc.fty, sc.ftx), grad_out, (double*)d.num64, kappa,
+                        grad_tau_mult, device_cus() * 8, s));
+  return HTS_OK;
+}
+
 hts_status hts_batch_workspace_size(const hts_params* p, const hts_image* imgs, int32_t n,
                                     size_t* bytes) {
   if (!bytes) return HTS_ERR_INVALID;

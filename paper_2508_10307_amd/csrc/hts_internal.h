@@ -154,6 +154,9 @@ hipError_t launch_reset_counters(const Launch& L, hipStream_t s);
 hipError_t launch_cov(const Launch& L, int grid, hipStream_t s);
 hipError_t launch_eig(const Launch& L, hipStream_t s);
 hipError_t launch_vote(const Launch& L, hipStream_t s);
+// surrogate threshold derivative: partial[n_ref] (scratch), out[0] = dL/dlambda
+hipError_t launch_taugrad(const Launch& L, const float* g, double* partial, float kappa, float* out,
+                          int grid, hipStream_t s);
 hipError_t launch_fbasis(const Launch& L, const float* U, const float* V, hipStream_t s);
 hipError_t launch_zero_accum(const Launch& L, int grid, hipStream_t s);
 hipError_t launch_filter(const Launch& L, int shape_ty, int shape_tx, int adjoint, int grid,

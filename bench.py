@@ -74,7 +74,7 @@ def kernel_name(C, K, valu):
     """rocprofv3 name of the single-image (eager) forward filter launch."""
     if valu:
         spl = {2: 1, 4: 1, 8: 1, 16: 2, 32: 4, 64: 8}[K]
-        return f"void hts::k_filter<{C}, {spl}, 0, 0, 0>(hts::Launch)"
+        return f"void hts::k_filter<{C}, {spl}, 0, 0, 0, 0, 0>(hts::Launch)"
     return f"void hts::k_filter_mfma<{K}, 0, 0, 0>(hts::Launch)"
 
 

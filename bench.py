@@ -84,12 +84,13 @@ def kernel_name(C, K, valu):
 # counters give for a plain device copy of known size.  Valid only for the
 # kernel sources they were taken on (SHA-256 over the files below).
 TRAFFIC_SOURCES = ["paper_2508_10307_amd/csrc/k_filter.hip",
+                   "paper_2508_10307_amd/csrc/filter_valu.h",
                    "paper_2508_10307_amd/csrc/k_filter_mfma.hip",
                    "paper_2508_10307_amd/csrc/hts_device.h",
                    "paper_2508_10307_amd/csrc/hts_internal.h"]
 TRAFFIC = {    # kernel name -> (sources sha256, bytes per launch)
-    "void hts::k_filter<3, 4, 0, 0, 0>(hts::Launch)":
-        ("7b3d98f47856dfea1824db214a3df045f79048166a589db7d9e41ea26079a86c", 57607421),
+    "void hts::k_filter<3, 4, 0, 0, 0, 0, 0>(hts::Launch)":
+        ("eede9109030988bab2861379c862de2d82fc0f296ea2c91708f344b8eaafec92", 58501355),
 }
 
 

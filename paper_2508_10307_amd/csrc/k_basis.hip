@@ -186,7 +186,7 @@ __device__ void jacobi_herm8_group(double (*mr)[8][8], double (*mi)[8][8], doubl
       if (act) {
         const double br = mr[m][lo][hi], bi = mi[m][lo][hi];
         const double mag = sqrt(br * br + bi * bi);
-        if (mag > tiny) {
+        if (!(mag <= tiny)) {   // a NaN rotates too, so it reaches every entry
           rotated = 1;
           const double zeta = (mr[m][hi][hi] - mr[m][lo][lo]) / (2.0 * mag);
           const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));

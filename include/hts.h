@@ -209,6 +209,35 @@ hts_status hts_denoise_grad_tau(const hts_params* p, const float* noisy, const f
                                 float kappa, float* grad_tau_mult, void* ws, size_t ws_bytes,
                                 void* stream);
 
+/* Derivative through the learned basis (adjoint extension).  Alg. 1
+ * Step 2(1) learns U, V from the noisy image itself (Eq. 11-12: the
+ * eigenvectors of the per-frequency patch second moments C_U(f), C_V(f),
+ * phase-normalised), so with idx, masks and cnt frozen dL/dnoisy has, beside
+ * hts_denoise_backward's frozen-basis term, a term through U(noisy),
+ * V(noisy).  This call ADDS that term into grad_in (device [C][H][W],
+ * in/out):
+ *   A_U(f) = sum over group slots of R^ V_F T'^^H + P^ V_F D^^H,
+ *   A_V(f) = sum of R^^H U_F T'^ + P^^H U_F D^  (P / R: the slot's patch of
+ *   noisy / of grad_out / cnt; T', D: their projections (Eq. 18) through the
+ *   frozen mask and back; ^: DFT along the channel mode),
+ * then per eigenproblem the first-order eigenvector perturbation (distinct
+ * eigenvalues) with the phase convention's gauge term, and
+ * dL/dP^_i = 2 Cbar_U P^_i + 2 P^_i Cbar_V added back at every reference
+ * patch i.  noisy, grad_out: device [C][H][W]; idx, masks, cnt as
+ * hts_denoise saves them; U64, V64 [C][ps][ps] and eig [2][C/2+1][ps]: the
+ * FP64 basis and eigenvalues of hts_basis for noisy.  FP64 sums in a fixed
+ * order (the same bits on every run).  Near-equal eigenvalues make the term
+ * large (1 / (l_k - l_j)), as the eigenvectors themselves are then
+ * ill-conditioned.  Errors: HTS_ERR_INVALID for null pointers;
+ * HTS_ERR_UNSUPPORTED with flags set; the parameter and workspace checks of
+ * hts_denoise. */
+hts_status hts_denoise_backward_basis(const hts_params* p, const float* noisy,
+                                      const float* grad_out, const int32_t* idx,
+                                      const uint32_t* masks, const double* U64, const double* V64,
+                                      const double* eig, const float* cnt, int32_t C, int32_t H,
+                                      int32_t W, float* grad_in, void* ws, size_t ws_bytes,
+                                      void* stream);
+
 /* Workspace bytes for hts_denoise_batch over these n images (host array). */
 hts_status hts_batch_workspace_size(const hts_params* p, const hts_image* imgs, int32_t n,
                                     size_t* bytes);

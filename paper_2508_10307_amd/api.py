@@ -362,17 +362,41 @@ def hts_denoise_grad_tau(noisy, grad_out, st, sigma: float, p: Params, kappa: fl
     return out
 
 
+def hts_denoise_backward_basis(noisy, grad_out, st, p: Params, grad_in, basis64=None, ws=None):
+    """Adds into grad_in the derivative through the learned basis (with the
+    grouping, masks and counts of st frozen): the part of dL/dnoisy that
+    flows through U(noisy), V(noisy).  basis64 = (U64, V64, eig) of
+    hts_basis(noisy, p, want_fp64=True), computed here when None.  Returns
+    grad_in."""
+    x = _img(noisy)
+    g = _img(grad_out, "grad_out")
+    C, H, W = x.shape
+    dev = x.device
+    if basis64 is None:
+        basis64 = hts_basis(x, p, want_fp64=True)[2:]
+    U64, V64, eig = basis64
+    ws = workspace(p, C, H, W, dev) if ws is None else ws
+    pc = p.c()
+    L.check("hts_denoise_backward_basis", L.load().hts_denoise_backward_basis(
+        ctypes.byref(pc), _ptr(x), _ptr(g), _ptr(st["idx"]), _ptr(st["masks"]), _ptr(U64),
+        _ptr(V64), _ptr(eig), _ptr(st["cnt"]), C, H, W, _ptr(grad_in), _ptr(ws), ws.numel(),
+        _stream(dev)))
+    return grad_in
+
+
 class HaarTSVD(torch.autograd.Function):
     """Differentiable Haar-tSVD denoiser: forward = hts_denoise; backward =
     the hand-written adjoint kernel with match indices, threshold masks,
-    basis and coverage counts frozen at the forward pass.  The exact
-    gradient with respect to the threshold multiplier is zero (it only moves
-    the frozen masks); with tau_kappa > 0 the backward returns instead the
-    surrogate derivative of hts_denoise_grad_tau (relaxation width
-    tau_kappa * sigma)."""
+    basis and coverage counts frozen at the forward pass; with
+    basis_grad=True it adds the derivative through the learned basis
+    (hts_denoise_backward_basis).  The exact gradient with respect to the
+    threshold multiplier is zero (it only moves the frozen masks); with
+    tau_kappa > 0 the backward returns instead the surrogate derivative of
+    hts_denoise_grad_tau (relaxation width tau_kappa * sigma)."""
 
     @staticmethod
-    def forward(ctx, noisy, sigma, tau_mult, p: Params, tau_kappa: float = 0.0):
+    def forward(ctx, noisy, sigma, tau_mult, p: Params, tau_kappa: float = 0.0,
+                basis_grad: bool = False):
         q = Params(**{**p.__dict__, "tau_mult": float(tau_mult)})
         x = noisy.detach()
         out, st = hts_denoise(x, float(sigma), q, save=True)
@@ -380,16 +404,19 @@ class HaarTSVD(torch.autograd.Function):
         ctx.p = q
         ctx.sigma = float(sigma)
         ctx.kappa = float(tau_kappa)
-        ctx.noisy = x if ctx.kappa > 0 else None
+        ctx.basis_grad = bool(basis_grad)
+        ctx.noisy = x if (ctx.kappa > 0 or ctx.basis_grad) else None
         return out
 
     @staticmethod
     def backward(ctx, grad):
         g = grad.contiguous()
         gin, gtau = hts_denoise_backward(g, ctx.st, ctx.p)
+        if ctx.basis_grad:
+            hts_denoise_backward_basis(ctx.noisy, g, ctx.st, ctx.p, gin)
         if ctx.kappa > 0:
             gtau = hts_denoise_grad_tau(ctx.noisy, g, ctx.st, ctx.sigma, ctx.p, ctx.kappa)
-        return gin, None, gtau.reshape(()), None, None
+        return gin, None, gtau.reshape(()) if ctx.needs_input_grad[2] else None, None, None, None
 
 
 def denoise(x: torch.Tensor, sigma: float, **params) -> torch.Tensor:

@@ -82,7 +82,7 @@ hts_status make_geo(const hts_params* p, int C, int H, int W, Geo& g) {
 // Workspace carve-up for one image.
 struct Carve {
   size_t gplanes, green, idx, fb_list, fb_count, cov, basis64, basis, fbasis, num, num64, cnt, hist,
-      poison, fxmax, wsum64, total;
+      poison, fxmax, wsum64, gbasis, total;
 };
 
 Carve carve(const Geo& g) {
@@ -104,6 +104,7 @@ Carve carve(const Geo& g) {
   c.poison = o; o += al((size_t)g.H * g.W);
   c.fxmax = o; o += al(4);
   c.wsum64 = o; o += al((size_t)g.H * g.W * 8);
+  c.gbasis = o; o += al((size_t)4 * 128 * 8);   // covariance cotangents of the basis derivative
   c.total = o;
   return c;
 }
@@ -744,6 +745,37 @@ hts_status hts_denoise_grad_tau(const hts_params* p, const float* noisy, const f
   // the fixed-point numerator plane (>= 8 * n_ref bytes) holds the per-group partials
   HIPCHK(launch_taugrad(make_launch(p, C, d, -1, sc.fty, sc.ftx), grad_out, (double*)d.num64, kappa,
                         grad_tau_mult, device_cus() * 8, s));
+  return HTS_OK;
+}
+
+hts_status hts_denoise_backward_basis(const hts_params* p, const float* noisy,
+                                      const float* grad_out, const int32_t* idx,
+                                      const uint32_t* masks, const double* U64, const double* V64,
+                                      const double* eig, const float* cnt, int32_t C, int32_t H,
+                                      int32_t W, float* grad_in, void* ws, size_t ws_bytes,
+                                      void* stream) {
+  Geo g;
+  hts_status st = make_geo(p, C, H, W, g);
+  if (st != HTS_OK) return st;
+  if (!noisy || !grad_out || !idx || !masks || !U64 || !V64 || !eig || !cnt || !grad_in || !ws)
+    return HTS_ERR_INVALID;
+  if (weighted(p) || fourier(p, C)) return HTS_ERR_UNSUPPORTED;
+  const Carve c = carve(g);
+  if (ws_bytes < c.total) return HTS_ERR_WORKSPACE;
+  const Schedule sc = schedule_for(p, C);
+  hipStream_t s = (hipStream_t)stream;
+  ImgDesc d = make_desc(g, p, (char*)ws, c, noisy, 0.f, sc.fty, sc.ftx);
+  d.idx = const_cast<int32_t*>(idx);
+  d.cnt = const_cast<float*>(cnt);
+  d.masks_in = masks;
+  // one FP64 partial (2 x (C/2+1) complex 8x8) per work group, in the
+  // fixed-point numerator plane
+  const int nm = 2 * (C / 2 + 1);
+  const size_t per = (size_t)nm * 128 * sizeof(double);
+  const int grid = (int)std::max<size_t>(
+      1, std::min<size_t>({(size_t)device_cus() * 8, (size_t)g.n_ref, (size_t)C * H * W * 8 / per}));
+  HIPCHK(launch_gbasis(make_launch(p, C, d, -1, sc.fty, sc.ftx), grad_out, U64, V64, eig,
+                       (double*)d.num64, grid, (double*)((char*)ws + c.gbasis), grad_in, s));
   return HTS_OK;
 }
 

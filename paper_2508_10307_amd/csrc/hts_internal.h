@@ -158,6 +158,9 @@ hipError_t launch_vote(const Launch& L, hipStream_t s);
 hipError_t launch_taugrad(const Launch& L, const float* g, double* partial, float kappa, float* out,
                           int grid, hipStream_t s);
 hipError_t launch_fbasis(const Launch& L, const float* U, const float* V, hipStream_t s);
+hipError_t launch_gbasis(const Launch& L, const float* g, const double* U64, const double* V64,
+                         const double* eig, double* partial, int grid, double* M, float* grad,
+                         hipStream_t s);
 hipError_t launch_zero_accum(const Launch& L, int grid, hipStream_t s);
 hipError_t launch_filter(const Launch& L, int shape_ty, int shape_tx, int adjoint, int grid,
                          hipStream_t s);

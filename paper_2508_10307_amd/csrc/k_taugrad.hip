@@ -14,35 +14,9 @@
 // runs in the lane's registers.  Each group's sum (FP64, fixed butterfly across the
 // wavefront) goes to partial[g]; k_taugrad_sum adds the partials in order, so
 // the result is the same on every run.
-#include "hts_device.h"
+#include "group_proj.h"
 
 namespace hts {
-
-namespace {
-
-constexpr double TG_SQ3_2 = 0.86602540378443864676;   // sqrt(3) / 2
-
-// Y = P V (if right) or Z = U^H P (else) for one 8x8 complex slice held one
-// element per lane: element (a, b) of the product from the LDS copy of P.
-// B is the basis slice pair (re, im) in row-major [r][c] order (im nullable).
-__device__ inline void slice_product(float (*lr)[8], float (*li)[8], int a, int b, const float* Br,
-                                     const float* Bi, bool right, double& outr, double& outi) {
-  double yr = 0.0, yi = 0.0;
-#pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    // right: sum_t P[a][t] V[t][b];  left: sum_t conj(U[t][a]) P[t][b]
-    const double pr = right ? lr[a][t] : lr[t][b];
-    const double pi = right ? li[a][t] : li[t][b];
-    const double br = right ? Br[t * 8 + b] : Br[t * 8 + a];
-    const double bi = Bi ? (right ? Bi[t * 8 + b] : -(double)Bi[t * 8 + a]) : 0.0;
-    yr = fma(pr, br, fma(-pi, bi, yr));
-    yi = fma(pr, bi, fma(pi, br, yi));
-  }
-  outr = yr;
-  outi = yi;
-}
-
-}  // namespace
 
 template <int K, int C>
 __global__ __launch_bounds__(64) void k_taugrad(Launch L, const float* g, double* partial,
@@ -68,52 +42,13 @@ __global__ __launch_bounds__(64) void k_taugrad(Launch L, const float* g, double
       const float rc = 1.0f / d.cnt[pix];
 #pragma unroll
       for (int which = 0; which < 2; ++which) {
-        float p[C];
+        float p[C], t[C];
 #pragma unroll
         for (int ch = 0; ch < C; ++ch)
           p[ch] = which == 0 ? d.img[ch * HW + pix] : g[ch * HW + pix] * rc;
-        double z0 = 0.0, z1r = 0.0, z1i = 0.0;
-        // f = 0 (real) and, for c = 3, f = 1 (complex): Z = U_F^H (P^ V_F)
+        project_patch<C>(lr, li, a, b, fb, p, t);
 #pragma unroll
-        for (int f = 0; f < (C == 3 ? 2 : 1); ++f) {
-          double pr, pi;
-          if (C == 1) {
-            pr = p[0];
-            pi = 0.0;
-          } else if (f == 0) {
-            pr = (double)p[0] + (double)p[1] + (double)p[2];
-            pi = 0.0;
-          } else {
-            pr = (double)p[0] - 0.5 * ((double)p[1] + (double)p[2]);
-            pi = TG_SQ3_2 * ((double)p[2] - (double)p[1]);
-          }
-          __syncthreads();
-          lr[a][b] = (float)pr;
-          li[a][b] = (float)pi;
-          __syncthreads();
-          double yr, yi;
-          slice_product(lr, li, a, b, fb + (f ? FB_V1R : FB_V0), f ? fb + FB_V1I : nullptr, true,
-                        yr, yi);
-          __syncthreads();
-          lr[a][b] = (float)yr;
-          li[a][b] = (float)yi;
-          __syncthreads();
-          double zr, zi;
-          slice_product(lr, li, a, b, fb + (f ? FB_U1R : FB_U0), f ? fb + FB_U1I : nullptr, false,
-                        zr, zi);
-          if (f == 0) z0 = zr;
-          else { z1r = zr; z1i = zi; }
-        }
-        // inverse DFT along the channel mode: T_j = (Z_0 + 2 Re(Z_1 e^{2 pi i j / 3})) / 3
-#pragma unroll
-        for (int ch = 0; ch < C; ++ch) {
-          double t;
-          if (C == 1) t = z0;
-          else if (ch == 0) t = (z0 + 2.0 * z1r) / 3.0;
-          else if (ch == 1) t = (z0 - z1r - 2.0 * TG_SQ3_2 * z1i) / 3.0;
-          else t = (z0 - z1r + 2.0 * TG_SQ3_2 * z1i) / 3.0;
-          core[which][k][ch][lane] = (float)t;
-        }
+        for (int ch = 0; ch < C; ++ch) core[which][k][ch][lane] = t[ch];
       }
     }
     // real core tensors of y (ts) and of r = g / cnt (tr): [slot][channel]
@@ -125,21 +60,10 @@ __global__ __launch_bounds__(64) void k_taugrad(Launch L, const float* g, double
         ts[k][ch] = core[0][k][ch][lane];
         tr[k][ch] = core[1][k][ch][lane];
       }
-    // orthonormal Haar along the group (pairs of running sums, 1/sqrt 2 per
-    // level); the coefficient order does not enter the sum below
-#pragma unroll
-    for (int st = 1; st < K; st <<= 1)
-#pragma unroll
-      for (int k = 0; k < K; k += 2 * st)
-#pragma unroll
-        for (int ch = 0; ch < C; ++ch) {
-          const float us = ts[k][ch], vs = ts[k + st][ch];
-          ts[k][ch] = (us + vs) * 0.70710678118654752440f;
-          ts[k + st][ch] = (us - vs) * 0.70710678118654752440f;
-          const float ur = tr[k][ch], vr = tr[k + st][ch];
-          tr[k][ch] = (ur + vr) * 0.70710678118654752440f;
-          tr[k + st][ch] = (ur - vr) * 0.70710678118654752440f;
-        }
+    // orthonormal Haar along the group; the coefficient order does not
+    // enter the sum below
+    haar_forward_slots<K, C>(ts);
+    haar_forward_slots<K, C>(tr);
     double acc = 0.0;
 #pragma unroll
     for (int k = 0; k < K; ++k)

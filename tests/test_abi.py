@@ -127,6 +127,14 @@ def test_calls_reject_null_pointers_and_small_workspace(lib):
     assert lib.hts_denoise_backward(bp, FAKE, FAKE, None, FAKE, FAKE, FAKE, 1, 64, 64, FAKE, None,
                                     FAKE, need, None) == L.HTS_ERR_INVALID
     assert lib.hts_aggregate(bp, None, None, 0, 0, 1, 64, 64, None, FAKE, FAKE, None) == L.HTS_ERR_INVALID
+    assert lib.hts_denoise_backward_basis(bp, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, None, FAKE, 1, 64,
+                                          64, FAKE, FAKE, need, None) == L.HTS_ERR_INVALID
+    assert lib.hts_denoise_backward_basis(bp, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, 1, 64,
+                                          64, FAKE, FAKE, need - 1, None) == L.HTS_ERR_WORKSPACE
+    wt = api.Params(flags=L.HTS_FLAG_WEIGHTED).c()
+    assert lib.hts_denoise_backward_basis(ctypes.byref(wt), FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE,
+                                          FAKE, 1, 64, 64, FAKE, FAKE, need,
+                                          None) == L.HTS_ERR_UNSUPPORTED
     bad = api.Params(K=12).c()
     assert lib.hts_match(ctypes.byref(bad), FAKE, 1, 64, 64, FAKE, None, None, FAKE, need,
                          None) == L.HTS_ERR_INVALID

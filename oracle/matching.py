@@ -25,15 +25,31 @@ def quantize(y: np.ndarray) -> np.ndarray:
     return np.clip(q, -QMAX, QMAX).astype(np.int64)
 
 
+def band_mean(q: np.ndarray) -> np.ndarray:
+    """The mean of the quantised bands on the same grid, rounded half to
+    even, in exact integer arithmetic: round(sum_j q_j / c)."""
+    c = q.shape[0]
+    s = q.sum(axis=0)
+    fl = np.floor_divide(s, c)
+    r = s - fl * c                       # 0 <= r < c
+    up = (2 * r > c) | ((2 * r == c) & (fl % 2 == 1))
+    return fl + up.astype(np.int64)
+
+
 def guide_planes(q: np.ndarray):
     """Guide planes from the quantised channels [C][H][W].
 
     c = 1: the channel itself.  c = 3: (G, R+G+B).  The channel sum is three
-    times the RGB average of Eq. 10 and ranks candidates identically."""
+    times the RGB average of Eq. 10 and ranks candidates identically.
+
+    Reading H1 (other band counts, the spectral tubes of HSI): the GCP test
+    of Eq. 10 is an RGB rule, so the guide is the band mean (band_mean), the
+    quantity the paper's HSI noise estimate also works on; it stays on the
+    2^-8 grid within the clamp, so distances stay exact integers."""
     if q.shape[0] == 1:
         return [q[0]]
     if q.shape[0] != 3:
-        raise ValueError("GCP matching is defined for 1 or 3 channels")
+        return [band_mean(q)]
     return [q[1], q[0] + q[1] + q[2]]
 
 
@@ -44,7 +60,7 @@ def gcp_green(q: np.ndarray, ys, xs, ps: int, num: int, den: int) -> np.ndarray:
     evaluated on the reference patch only.  Squared and cleared of the
     fraction: num^2 * ||qG||^2 >= den^2 * max(||qR||^2, ||qB||^2), exact in int64."""
     out = np.zeros(len(ys), dtype=bool)
-    if q.shape[0] == 1:
+    if q.shape[0] != 3:
         return out
     for n, (y, x) in enumerate(zip(ys, xs)):
         nr = int((q[0, y:y + ps, x:x + ps] ** 2).sum())
@@ -81,7 +97,7 @@ def match(y: np.ndarray, ps: int, stride: int, window_w: int, K: int,
     dist = np.zeros((n_ref, K), dtype=np.int64)
     for n in range(n_ref):
         ry, rx = int(ys[n]), int(xs[n])
-        plane = 0 if (C == 1 or green[n]) else 1
+        plane = 0 if (C != 3 or green[n]) else 1
         v = views[plane]
         ref = v[ry, rx]
         y0, y1, x0, x1 = window(ry, rx, Hp, Wp, window_w)

@@ -13,7 +13,11 @@
  *
  * Conventions shared by every entry point
  *  - Images are planar float32 [C][H][W], contiguous, in device memory.
- *    C is 1 or 3; ps must be 8.
+ *    C is 1 (grey), 3 (RGB) or, for the spectral tubes of HSI (Sec. IV: a
+ *    ps x ps x N_bands patch, other parameters unchanged), 2 and 4..256 with
+ *    K <= 32 and no flags; ps must be 8.  The band counts other than 1 and 3
+ *    run through hts_denoise, hts_match and hts_basis (the other entry
+ *    points return HTS_ERR_UNSUPPORTED for them).
  *  - Reference grid: top-left corners 0, s, 2s, ... along each axis plus the
  *    last valid position H-ps (resp. W-ps); references are numbered
  *    row-major over that grid (n_ref = n_ref_y * n_ref_x).
@@ -24,7 +28,8 @@
  *    q = round_half_even(256*y) clamped to |q| <= 2^20-1; for C = 3 the guide
  *    of a reference is its green channel when
  *    gcp_num^2*|qG|^2 >= gcp_den^2*max(|qR|^2,|qB|^2) (Eq. 10 with
- *    gamma = gcp_num/gcp_den) and R+G+B otherwise.
+ *    gamma = gcp_num/gcp_den) and R+G+B otherwise; for other C it is the band
+ *    mean on the same grid, round_half_even(sum_j q_j / C), exact integers.
  *  - Basis tensors U, V are float32 [C][ps][ps] (frontal slice j = U(:,:,j)).
  *  - Threshold masks are bit-packed: bit ((g*K + k)*C + ch)*64 + i*8 + j of a
  *    little-endian uint32 stream is 1 when Haar-t-SVD coefficient (k, ch, i, j)
@@ -67,7 +72,7 @@ extern "C" {
 typedef enum {
   HTS_OK = 0,
   HTS_ERR_INVALID = 1,      /* bad argument (null pointer, sizes, K, window...) */
-  HTS_ERR_UNSUPPORTED = 2,  /* valid per the paper but not built (C not 1/3, ps != 8) */
+  HTS_ERR_UNSUPPORTED = 2,  /* valid per the paper but not built (ps != 8, C > 256, ...) */
   HTS_ERR_WORKSPACE = 3,    /* workspace too small */
   HTS_ERR_HIP = 4           /* a HIP runtime call or launch failed */
 } hts_status;

@@ -42,7 +42,7 @@ bool fourier(const hts_params* p, int C) { return C == 3 && (p->flags & HTS_FLAG
 hts_status check_params(const hts_params* p, int C) {
   if (!p) return HTS_ERR_INVALID;
   if (p->ps != PS) return HTS_ERR_UNSUPPORTED;
-  if (C != 1 && C != 3) return HTS_ERR_UNSUPPORTED;
+  if (C < 1 || C > GEN_CMAX) return HTS_ERR_UNSUPPORTED;
   if (!is_pow2(p->K) || p->K < 2 || p->K > 64) return HTS_ERR_INVALID;
   if (C == 3 && p->K > 32) return HTS_ERR_UNSUPPORTED;
   if (p->stride < 1 || p->stride > PS) return HTS_ERR_INVALID;
@@ -52,6 +52,11 @@ hts_status check_params(const hts_params* p, int C) {
   if (p->match_mode != HTS_MATCH_BF16 && p->match_mode != HTS_MATCH_FP32) return HTS_ERR_INVALID;
   if ((p->flags & ~(HTS_FLAG_WEIGHTED | HTS_FLAG_FOURIER_THRESHOLD)) != 0) return HTS_ERR_INVALID;
   if ((size_t)match_lds_bytes(p->stride, p->window) > kLdsMax) return HTS_ERR_UNSUPPORTED;
+  if (general_c(C)) {   // spectral tubes: uniform Eq. 2 and Eq. 19 only
+    if (p->K > GEN_KMAX || p->flags) return HTS_ERR_UNSUPPORTED;
+    if (filter_gen_lds_bytes(C) > kLdsMax || cov_gen_lds_bytes(C) > kLdsMax) return HTS_ERR_UNSUPPORTED;
+    return HTS_OK;
+  }
   if (filter_lds_bytes(C, p->K, p->stride, p->window, 1, 1, weighted(p)) > kLdsMax)
     return HTS_ERR_UNSUPPORTED;
   return HTS_OK;
@@ -71,7 +76,7 @@ hts_status make_geo(const hts_params* p, int C, int H, int W, Geo& g) {
     const int tr = cov_tile(p->stride);
     g.n_cov = ((g.nry + tr - 1) / tr) * ((g.nrx + tr - 1) / tr);
   }
-  g.np = C == 1 ? 1 : 2;
+  g.np = C == 3 ? 2 : 1;
   const int r = (p->window - 1) / 2;
   // every reference must have at least K candidates (the corner ones have fewest)
   if ((long long)std::min(g.Hp, r + 1) * std::min(g.Wp, r + 1) < p->K) return HTS_ERR_INVALID;
@@ -82,7 +87,7 @@ hts_status make_geo(const hts_params* p, int C, int H, int W, Geo& g) {
 // Workspace carve-up for one image.
 struct Carve {
   size_t gplanes, green, idx, fb_list, fb_count, cov, basis64, basis, fbasis, num, num64, cnt, hist,
-      poison, fxmax, wsum64, gbasis, total;
+      poison, fxmax, wsum64, gbasis, ufg, gscratch, total;
 };
 
 Carve carve(const Geo& g) {
@@ -96,7 +101,7 @@ Carve carve(const Geo& g) {
   c.cov = o; o += al((size_t)g.n_cov * cov_elems(g.C) * 8);
   c.basis64 = o; o += al((size_t)(2 * g.C * 64 + 2 * (g.C / 2 + 1) * 8) * 8);
   c.basis = o; o += al((size_t)2 * g.C * 64 * 4);
-  c.fbasis = o; o += al((size_t)FB_SIZE * 4);
+  c.fbasis = o; o += al((size_t)std::max(FB_SIZE, 2 * n_freq(g.C) * 128) * 4);
   c.num = o; o += al((size_t)g.C * g.H * g.W * 4);
   c.cnt = o; o += al((size_t)g.H * g.W * 4);
   c.hist = o; o += al((size_t)g.H * g.W * 4);
@@ -105,6 +110,10 @@ Carve carve(const Geo& g) {
   c.fxmax = o; o += al(4);
   c.wsum64 = o; o += al((size_t)g.H * g.W * 8);
   c.gbasis = o; o += al((size_t)4 * 128 * 8);   // covariance cotangents of the basis derivative
+  const bool gen = general_c(g.C);
+  c.ufg = o; o += gen ? al((size_t)2 * n_freq(g.C) * 128 * 8) : 0;
+  c.gscratch = o;
+  o += gen ? al((size_t)std::min(g.n_ref, GEN_GRID) * g.K * g.C * 64 * 4) : 0;
   c.total = o;
   return c;
 }
@@ -141,6 +150,8 @@ ImgDesc make_desc(const Geo& g, const hts_params* p, char* ws, const Carve& c, c
   d.poison = (uint8_t*)(ws + c.poison);
   d.fxmax = (uint32_t*)(ws + c.fxmax);
   d.wsum64 = weighted(p) ? (unsigned long long*)(ws + c.wsum64) : nullptr;
+  d.ufg = general_c(g.C) ? (double*)(ws + c.ufg) : nullptr;
+  d.gscratch = general_c(g.C) ? (float*)(ws + c.gscratch) : nullptr;
   d.H = g.H; d.W = g.W; d.Hp = g.Hp; d.Wp = g.Wp;
   d.nry = g.nry; d.nrx = g.nrx; d.n_ref = g.n_ref;
   d.ref_begin = 0; d.ref_count = g.n_ref;
@@ -230,6 +241,10 @@ hts_status run_match(const hts_params* p, int C, const Schedule& sc, ImgDesc d, 
 }
 
 hts_status run_basis(const hts_params* p, int C, const Schedule& sc, ImgDesc d, hipStream_t s) {
+  if (general_c(C)) {
+    HIPCHK(launch_basis_gen(make_launch(p, C, d, -1, sc.fty, sc.ftx), s));
+    return HTS_OK;
+  }
   HIPCHK(launch_cov(make_launch(p, C, d, W_COV, sc.fty, sc.ftx), 0, s));
   HIPCHK(launch_eig(make_launch(p, C, d, -1, sc.fty, sc.ftx), s));
   return HTS_OK;
@@ -253,6 +268,14 @@ hts_status run_count(const hts_params* p, int C, const Schedule& sc, const ImgDe
 hts_status run_filter(const hts_params* p, int C, const Schedule& sc, ImgDesc d, int adjoint,
                       hipStream_t s, const float* U = nullptr, const float* V = nullptr,
                       bool hist_ready = false) {
+  if (general_c(C)) {   // the spectral-tube filter: fixed-point numerator, own basis only
+    if (adjoint || U || V || !d.num64) return HTS_ERR_UNSUPPORTED;
+    HIPCHK(launch_fbasis_gen(make_launch(p, C, d, -1, sc.fty, sc.ftx), s));
+    HIPCHK(launch_filter_gen(make_launch(p, C, d, W_FILT, sc.fty, sc.ftx),
+                             std::min(d.ref_count, GEN_GRID), s));
+    if (d.cnt) return run_count(p, C, sc, d, hist_ready, s);
+    return HTS_OK;
+  }
   HIPCHK(launch_fbasis(make_launch(p, C, d, -1, sc.fty, sc.ftx), U, V, s));
   const Launch L = make_launch(p, C, d, W_FILT, sc.fty, sc.ftx);
   if (sc.valu) HIPCHK(launch_filter(L, sc.fty, sc.ftx, adjoint, 0, s));
@@ -333,6 +356,7 @@ hts_status plan_batch(const hts_params* p, const hts_image* imgs, int n, char* b
   const int C = imgs[0].C;
   hts_status st = check_params(p, C);
   if (st != HTS_OK) return st;
+  if (general_c(C)) return HTS_ERR_UNSUPPORTED;   // spectral tubes: single-image calls only
   plan.sc = schedule_for(p, C);
   plan.descs.assign(n, ImgDesc());
   for (int k = 0; k < W_NKIND; ++k) plan.totals[k] = 0;
@@ -565,6 +589,7 @@ hts_status hts_filter(const hts_params* p, const float* noisy, int32_t C, int32_
   Geo g;
   hts_status st = make_geo(p, C, H, W, g);
   if (st != HTS_OK) return st;
+  if (general_c(C)) return HTS_ERR_UNSUPPORTED;   // spectral tubes: hts_denoise, hts_match, hts_basis
   if (!noisy || !idx || !U || !V || !ws) return HTS_ERR_INVALID;
   if ((num == nullptr) != (cnt == nullptr)) return HTS_ERR_INVALID;
   if (!(sigma >= 0.f) || !std::isfinite(sigma)) return HTS_ERR_INVALID;
@@ -598,6 +623,7 @@ hts_status hts_aggregate(const hts_params* p, const float* group_est, const int3
   Geo g;
   hts_status st = make_geo(p, C, H, W, g);
   if (st != HTS_OK) return st;
+  if (general_c(C)) return HTS_ERR_UNSUPPORTED;   // spectral tubes: hts_denoise, hts_match, hts_basis
   if (weighted(p)) return HTS_ERR_UNSUPPORTED;   // estimates carry no group weights
   if (!num || !cnt) return HTS_ERR_INVALID;
   if (group_est && !idx) return HTS_ERR_INVALID;
@@ -660,6 +686,7 @@ hts_status hts_adapt_sigma(const hts_params* p, const float* noisy, int32_t C, i
   Geo g;
   hts_status st = make_geo(p, C, H, W, g);
   if (st != HTS_OK) return st;
+  if (general_c(C)) return HTS_ERR_UNSUPPORTED;   // spectral tubes: hts_denoise, hts_match, hts_basis
   if (!noisy || !idx || !samples || !sigma_out || !adapt_args_ok(n_samples, beta)) return HTS_ERR_INVALID;
   if (!(sigma_est >= 0.f) || !std::isfinite(sigma_est)) return HTS_ERR_INVALID;
   ImgDesc d;
@@ -691,6 +718,7 @@ hts_status hts_denoise_backward(const hts_params* p, const float* grad_out, cons
   Geo g;
   hts_status st = make_geo(p, C, H, W, g);
   if (st != HTS_OK) return st;
+  if (general_c(C)) return HTS_ERR_UNSUPPORTED;   // spectral tubes: hts_denoise, hts_match, hts_basis
   if (weighted(p)) return HTS_ERR_UNSUPPORTED;   // adjoint of the uniform average only
   if (fourier(p, C)) return HTS_ERR_UNSUPPORTED;  // masks of the real-domain threshold only
   if (!grad_out || !idx || !masks || !U || !V || !cnt || !grad_in || !ws) return HTS_ERR_INVALID;
@@ -726,6 +754,7 @@ hts_status hts_denoise_grad_tau(const hts_params* p, const float* noisy, const f
   Geo g;
   hts_status st = make_geo(p, C, H, W, g);
   if (st != HTS_OK) return st;
+  if (general_c(C)) return HTS_ERR_UNSUPPORTED;   // spectral tubes: hts_denoise, hts_match, hts_basis
   if (!noisy || !grad_out || !idx || !U || !V || !cnt || !grad_tau_mult || !ws) return HTS_ERR_INVALID;
   if (!(sigma >= 0.f) || !std::isfinite(sigma)) return HTS_ERR_INVALID;
   if (!(kappa > 0.f) || !std::isfinite(kappa)) return HTS_ERR_INVALID;
@@ -757,6 +786,7 @@ hts_status hts_denoise_backward_basis(const hts_params* p, const float* noisy,
   Geo g;
   hts_status st = make_geo(p, C, H, W, g);
   if (st != HTS_OK) return st;
+  if (general_c(C)) return HTS_ERR_UNSUPPORTED;   // spectral tubes: hts_denoise, hts_match, hts_basis
   if (!noisy || !grad_out || !idx || !masks || !U64 || !V64 || !eig || !cnt || !grad_in || !ws)
     return HTS_ERR_INVALID;
   if (weighted(p) || fourier(p, C)) return HTS_ERR_UNSUPPORTED;
@@ -885,6 +915,7 @@ hts_status hts_autotune(const hts_params* p, int32_t C, int32_t H, int32_t W,
   Geo g;
   hts_status st = make_geo(p, C, H, W, g);
   if (st != HTS_OK) return st;
+  if (general_c(C)) return HTS_ERR_UNSUPPORTED;   // spectral tubes: hts_denoise, hts_match, hts_basis
   if (!tune_out || !ws) return HTS_ERR_INVALID;
   const std::string key = tune_key(p, C);
   {

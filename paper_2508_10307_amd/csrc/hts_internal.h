@@ -17,6 +17,14 @@ constexpr int MATCH_TY = 4;            // match tile: 4 x 4 references
 constexpr int MATCH_TX = 4;
 constexpr int SHORT_CAP = 128;         // certified shortlist capacity per reference
 constexpr int PIX_CHUNK = 2048;        // pixels per work item of the element-wise stages
+// General band counts (c other than 1 and 3: the spectral tubes of HSI)
+constexpr int GEN_CMAX = 256;          // bands
+constexpr int GEN_KMAX = 32;           // group size
+constexpr int GEN_FC = 8;              // frequencies per covariance work item
+constexpr int GEN_EIG_M = 16;          // eigenproblems per work group
+constexpr int GEN_GRID = 1024;         // filter work groups (each with its own scratch)
+__host__ __device__ inline bool general_c(int C) { return C != 1 && C != 3; }
+__host__ __device__ inline int n_freq(int C) { return C / 2 + 1; }
 
 // Work kinds: each image contributes a number of work items of each kind;
 // batched launches walk a global list of (image, item) pairs.
@@ -63,6 +71,8 @@ struct ImgDesc {
   float* sigma_dev;        // [1] adjusted sigma; when set, the filter's tau is tau_mult * *sigma_dev
   unsigned long long* wsum64; // [H][W] weight sums (fixed point, 2^-48 units) of the weighted
                               // aggregation; nullable (then weights go to cnt, or are uniform)
+  double* ufg;             // general c: [2 * (C/2+1)][re/im][64] Fourier-domain eigenvectors
+  float* gscratch;         // general c: filter scratch, [work group][K][C][64]
   int32_t woff[W_NKIND];   // first global work item of each kind (batched)
   int32_t wcnt[W_NKIND];   // work items of each kind
 };
@@ -138,7 +148,12 @@ inline int ref_count_axis(int n_valid, int s) {
   return n;
 }
 
-__host__ __device__ inline int cov_elems(int C) { return C == 1 ? 2 * 64 : 2 * 64 + 2 * 128; }
+// FP64 entries of one covariance partial: c = 1 two real 8x8 matrices;
+// c = 3 two real (f = 0) and two complex (f = 1); other c two complex per
+// frequency f <= c/2, [U: f, then V: f][re/im][64].
+__host__ __device__ inline int cov_elems(int C) {
+  return C == 1 ? 2 * 64 : C == 3 ? 2 * 64 + 2 * 128 : 2 * n_freq(C) * 128;
+}
 // Covariance partial blocks: tiles of cov_tile x cov_tile references, whose
 // pixel region (at most cov_region pixels square) is staged in LDS.
 __host__ __device__ inline int cov_tile(int s) { return s <= 4 ? 16 : 8; }
@@ -184,5 +199,13 @@ size_t filter_lds_bytes(int C, int K, int stride, int window, int ty, int tx, bo
 hipError_t launch_filter_ft(const Launch& L, int g, size_t lds, bool batch, bool masks, bool wt,
                             hipStream_t s);
 size_t match_lds_bytes(int stride, int window);   // one plane slot: the minimum
+
+// General band counts (csrc/k_general.hip): covariances per (reference tile,
+// frequency chunk), eigen-solves, real tensors, Fourier slices, filter.
+hipError_t launch_basis_gen(const Launch& L, hipStream_t s);
+hipError_t launch_fbasis_gen(const Launch& L, hipStream_t s);
+hipError_t launch_filter_gen(const Launch& L, int grid, hipStream_t s);
+size_t filter_gen_lds_bytes(int C);
+size_t cov_gen_lds_bytes(int C);
 
 }  // namespace hts

@@ -5,7 +5,9 @@
 
 namespace hts {
 
-// Guide planes from the noisy image: C = 1 -> q; C = 3 -> (qG, qR + qG + qB).
+// Guide planes from the noisy image: C = 1 -> q; C = 3 -> (qG, qR + qG + qB);
+// other C -> the band mean on the same grid, round-half-even(sum q_j / C) in
+// exact integer arithmetic.
 __global__ __launch_bounds__(256) void k_quant(Launch L) {
   for_each_item<W_PIX>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
     const int HW = d.H * d.W;
@@ -18,6 +20,18 @@ __global__ __launch_bounds__(256) void k_quant(Launch L) {
         const float v = d.img[p];
         d.gplanes[p] = quantize(v);
         mb = max(mb, abs_bits(v));
+      } else if (L.C != 3) {
+        long long sq = 0;
+        for (int j = 0; j < L.C; ++j) {
+          const float v = d.img[(size_t)j * HW + p];
+          sq += quantize(v);
+          mb = max(mb, abs_bits(v));
+        }
+        // floor division, then half to even
+        long long fl = sq / L.C, rem = sq - fl * L.C;
+        if (rem < 0) { --fl; rem += L.C; }
+        if (2 * rem > L.C || (2 * rem == L.C && (fl & 1))) ++fl;
+        d.gplanes[p] = (int)fl;
       } else {
         const float r = d.img[p], g = d.img[HW + p], b = d.img[2 * HW + p];
         int qr = quantize(r);
@@ -38,7 +52,7 @@ __global__ __launch_bounds__(256) void k_gcp(Launch L) {
   for_each_item<W_REF>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
     const int r = item * 256 + threadIdx.x;
     if (r >= d.n_ref) return;
-    if (L.C == 1) { d.green[r] = 1; return; }
+    if (L.C != 3) { d.green[r] = 1; return; }   // one guide plane
     const int ry = ref_coord(r / d.nrx, L.stride, d.Hp);
     const int rx = ref_coord(r % d.nrx, L.stride, d.Wp);
     const int HW = d.H * d.W;

@@ -77,8 +77,13 @@ def _ws_status(lib, C=1, H=64, W=64, **kw):
     ({"stride": 0}, 1, (64, 64), L.HTS_ERR_INVALID),
     ({"stride": 9}, 1, (64, 64), L.HTS_ERR_INVALID),
     ({"ps": 4}, 1, (64, 64), L.HTS_ERR_UNSUPPORTED),
-    ({}, 2, (64, 64), L.HTS_ERR_UNSUPPORTED),
-    ({}, 4, (64, 64), L.HTS_ERR_UNSUPPORTED),
+    ({}, 2, (64, 64), L.HTS_OK),                        # spectral tubes
+    ({}, 31, (64, 64), L.HTS_OK),
+    ({}, 256, (64, 64), L.HTS_OK),
+    ({}, 257, (64, 64), L.HTS_ERR_UNSUPPORTED),
+    ({"K": 64, "window": 21}, 4, (64, 64), L.HTS_ERR_UNSUPPORTED),
+    ({"flags": 1}, 5, (64, 64), L.HTS_ERR_UNSUPPORTED),
+    ({}, 0, (64, 64), L.HTS_ERR_UNSUPPORTED),
     ({}, 1, (7, 64), L.HTS_ERR_INVALID),
     ({"K": 32, "window": 7}, 1, (64, 64), L.HTS_ERR_INVALID),   # corner window 4x4 < K
     ({"K": 16, "window": 7}, 1, (64, 64), L.HTS_OK),           # corner window 4x4 = K
@@ -135,6 +140,15 @@ def test_calls_reject_null_pointers_and_small_workspace(lib):
     assert lib.hts_denoise_backward_basis(ctypes.byref(wt), FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE,
                                           FAKE, 1, 64, 64, FAKE, FAKE, need,
                                           None) == L.HTS_ERR_UNSUPPORTED
+    # band counts other than 1 and 3 run through hts_denoise / hts_match / hts_basis only
+    assert lib.hts_workspace_size(bp, 5, 64, 64, ctypes.byref(n)) == L.HTS_OK
+    need5 = n.value
+    assert lib.hts_filter(bp, FAKE, 5, 64, 64, 25.0, FAKE, FAKE, FAKE, 0, 4, FAKE, FAKE,
+                          None, None, FAKE, need5, None) == L.HTS_ERR_UNSUPPORTED
+    assert lib.hts_denoise_backward(bp, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, 5, 64, 64, FAKE, None,
+                                    FAKE, need5, None) == L.HTS_ERR_UNSUPPORTED
+    imgs = (L.HtsImage * 1)(L.HtsImage(FAKE.value, FAKE.value, 5, 64, 64, 10.0))
+    assert lib.hts_batch_workspace_size(bp, imgs, 1, ctypes.byref(n)) == L.HTS_ERR_UNSUPPORTED
     bad = api.Params(K=12).c()
     assert lib.hts_match(ctypes.byref(bad), FAKE, 1, 64, 64, FAKE, None, None, FAKE, need,
                          None) == L.HTS_ERR_INVALID

@@ -1,0 +1,99 @@
+"""GPU parity of the general band counts (spectral tubes, reading H1) with the
+FP64 oracle, through the C ABI: match indices bit-exact (band-mean guide),
+the FP64 basis within 1e-9, and the denoised image within 1e-3 on the
+0..255 scale under the GPU's exported keep-masks (the threshold-kink
+protocol of the RGB tests); equal bands reproduce the grey result, a NaN
+band pixel makes the whole output NaN, and repeated calls give the same
+bits."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import basis as obasis
+from oracle import matching as om
+from oracle import pipeline as opipe
+from paper_2508_10307_amd import api, synth
+
+pytestmark = pytest.mark.gpu
+
+PIX_TOL = 1e-3
+DELTA_REL = 2e-4
+CASES = [(2, 32, 30, 3, 9, 8), (5, 36, 33, 3, 11, 16), (8, 29, 28, 2, 11, 32),
+         (31, 24, 26, 3, 9, 8), (4, 27, 25, 3, 9, 2)]
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev())
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def tube(C, H, W, seed, sigma=20.0):
+    return synth.tiny(seed, C, H, W, sigma=sigma, n_blobs=5)
+
+
+@pytest.mark.parametrize("C,H,W,s,w,K", CASES)
+def test_match_and_basis_match_oracle(C, H, W, s, w, K):
+    y = tube(C, H, W, 2100 + C)
+    p = api.Params(stride=s, window=w, K=K)
+    x = T(y)
+    idx = api.hts_match(x, p)
+    idx_o, _, _ = om.match(y, 8, s, w, K)
+    np.testing.assert_array_equal(idx.cpu().numpy().astype(np.int64), idx_o)
+    U, V, U64, V64, eig = api.hts_basis(x, p, want_fp64=True)
+    _, _, Uo, Vo, eUo, eVo = obasis.global_basis(y.astype(np.float64), 8, s)
+    np.testing.assert_allclose(U64.cpu().numpy(), Uo, atol=1e-9)
+    np.testing.assert_allclose(V64.cpu().numpy(), Vo, atol=1e-9)
+    ev = eig.cpu().numpy()
+    np.testing.assert_allclose(ev[0], eUo, rtol=1e-11, atol=1e-9 * eUo.max())
+    np.testing.assert_allclose(ev[1], eVo, rtol=1e-11, atol=1e-9 * eVo.max())
+
+
+@pytest.mark.parametrize("C,H,W,s,w,K", CASES)
+def test_denoise_matches_oracle(C, H, W, s, w, K):
+    sigma = 20.0
+    y = tube(C, H, W, 2200 + C, sigma)
+    p = api.Params(stride=s, window=w, K=K)
+    x = T(y)
+    out, st = api.hts_denoise(x, sigma, p, save=True)
+    out2 = api.hts_denoise(x, sigma, p)
+    assert torch.equal(out, out2)
+    idx = st["idx"].cpu().numpy().astype(np.int64)
+    masks = opipe.unpack_masks(st["masks"].cpu().numpy().view(np.uint32), len(idx), K, C)
+    r = opipe.denoise(y, sigma, 8, s, w, K, p.tau_mult, idx=idx, U=st["U"].cpu().numpy(),
+                      V=st["V"].cpu().numpy(), mask=masks)
+    tau = p.tau_mult * sigma
+    log(f"C{C}: overrides {r['n_override']}, max margin {r['max_override_margin']:.3e}")
+    assert r["max_override_margin"] <= DELTA_REL * max(tau, 1.0)
+    err = np.abs(out.cpu().numpy() - r["out"]).max()
+    log(f"C{C} {H}x{W} s{s} w{w} K{K}: max |gpu - oracle| = {err:.3e}")
+    assert err <= PIX_TOL
+    np.testing.assert_array_equal(st["cnt"].cpu().numpy(), r["cnt"])
+
+
+def test_equal_bands_give_the_grey_result():
+    g = synth.tiny(2301, 1, 36, 34, sigma=20.0)
+    p = api.Params(stride=3, window=11, K=16)
+    grey = api.hts_denoise(T(g), 20.0, p)
+    tubes = api.hts_denoise(T(np.repeat(g, 4, axis=0)), 20.0, p)
+    for ch in range(4):
+        assert (tubes[ch] - grey[0]).abs().max().item() <= PIX_TOL
+
+
+def test_zero_sigma_reconstructs():
+    y = tube(6, 30, 31, 2302)
+    out = api.hts_denoise(T(y), 0.0, api.Params(stride=3, window=9, K=8))
+    assert (out - T(y)).abs().max().item() <= 1e-3
+
+
+def test_nan_band_pixel_makes_the_output_nan():
+    y = tube(5, 30, 28, 2303, 10.0)
+    y[3, 11, 7] = np.nan
+    out = api.hts_denoise(T(y), 10.0, api.Params(stride=3, window=9, K=8))
+    assert torch.isnan(out).all()

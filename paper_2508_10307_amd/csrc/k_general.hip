@@ -239,21 +239,24 @@ hipError_t launch_fbasis_gen(const Launch& L, hipStream_t s) {
 }
 
 size_t filter_gen_lds_bytes(int C) {
-  return ((size_t)2 * C + (size_t)C * 64 + (size_t)n_freq(C) * 128 + 128) * 4;
+  return ((size_t)2 * C + (size_t)2 * n_freq(C) * 128) * 4;
 }
 
 // One wavefront per work group, groups [ref_begin, ref_begin + ref_count)
 // in a grid-stride loop; lane = patch element (a, b).  The work group's
-// scratch holds the group's real core tensor [K][C][64].
+// scratch holds the group's real core tensor [K][C][64].  Per slot, the
+// products of all frequencies share two LDS round trips: X(f) (the DFT of
+// the bands, lane-private entry) -> Y(f) = X(f) V_F(f) (or X(f) V_F(f)^H)
+// -> U_F(f)^H Y(f) (or U_F(f) Y(f)) back into X(f).  The lane's band values
+// are parked in the Y area while the DFT reads them.
 template <int K>
 __global__ __launch_bounds__(64) void k_filter_gen(Launch L) {
   extern __shared__ float fsm[];
   const int C = L.C, NF = n_freq(C);
   float* tc = fsm;                 // twiddles e^{-2 pi i m / c}
   float* ts = tc + C;
-  float* pv = ts + C;              // [C][64] lane-private band values
-  float* zf = pv + C * 64;         // [NF][re/im][64] lane-private per-frequency results
-  float* tl = zf + NF * 128;       // [re/im][64] product tile
+  float* X = ts + C;               // [NF][re/im][64]
+  float* Y = X + NF * 128;         // [NF][re/im][64]; the band values [C][64] before the products
   const int lane = threadIdx.x, a = lane >> 3, b = lane & 7;
   const ImgDesc& d = L.one;
   const int HW = d.H * d.W;
@@ -264,43 +267,83 @@ __global__ __launch_bounds__(64) void k_filter_gen(Launch L) {
   const float fxs = fx_scale(d) / (float)C;
   fill_twiddles(tc, ts, C);
   __syncthreads();
-  // Z = U_F(f)^H X V_F(f) (forward) or U_F(f) X V_F(f)^H (inverse) of the
-  // tile X at this lane's element, through the LDS tile.
-  auto product = [&](int f, bool inverse, float xr, float xi, float& zr, float& zi) {
-    const float* Ur = fb + (f * 2 + 0) * 64;
-    const float* Ui = fb + (f * 2 + 1) * 64;
-    const float* Vr = fb + ((NF + f) * 2 + 0) * 64;
-    const float* Vi = fb + ((NF + f) * 2 + 1) * 64;
-    __syncthreads();
-    tl[lane] = xr;
-    tl[64 + lane] = xi;
-    __syncthreads();
-    float yr = 0.f, yi = 0.f;
+  // X(f) <- DFT of the lane's band values (in Y), f < NF; four frequencies
+  // per pass over the bands (twiddle index m_f = f j mod c, kept by adding f)
+  auto dft_bands = [&]() {
+    for (int f0 = 0; f0 < NF; f0 += 4) {
+      float xr[4] = {0.f, 0.f, 0.f, 0.f}, xi[4] = {0.f, 0.f, 0.f, 0.f};
+      int m[4] = {0, 0, 0, 0};
+      for (int j = 0; j < C; ++j) {
+        const float v = Y[j * 64 + lane];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const float pr = tl[a * 8 + t], pi = tl[64 + a * 8 + t];
-      // forward: V(t, b); inverse: conj(V(b, t))
-      const float vr = inverse ? Vr[b * 8 + t] : Vr[t * 8 + b];
-      const float vi = inverse ? -Vi[b * 8 + t] : Vi[t * 8 + b];
-      yr += pr * vr - pi * vi;
-      yi += pr * vi + pi * vr;
+        for (int u = 0; u < 4; ++u) {
+          xr[u] = fmaf(v, tc[m[u]], xr[u]);
+          xi[u] = fmaf(v, ts[m[u]], xi[u]);
+          m[u] += f0 + u;
+          m[u] -= m[u] >= C ? C : 0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (f0 + u < NF) {
+          X[(f0 + u) * 128 + lane] = xr[u];
+          X[(f0 + u) * 128 + 64 + lane] = xi[u];
+        }
+    }
+  };
+  // bands j0..j0+3 of c x the (1/c) IDFT of the lane's X(f), f < NF
+  auto idft_bands4 = [&](int j0, float* t) {
+    int m[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      t[u] = X[lane];
+      m[u] = min(j0 + u, C - 1);
+    }
+    for (int f = 1; f < NF; ++f) {
+      const float w = 2 * f == C ? 1.f : 2.f;
+      const float zr = w * X[f * 128 + lane], zi = w * X[f * 128 + 64 + lane];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        t[u] += zr * tc[m[u]] + zi * ts[m[u]];
+        m[u] += j0 + u;
+        m[u] -= m[u] >= C ? C : 0;
+      }
+    }
+  };
+  // X(f) <- U_F(f)^H X(f) V_F(f) (forward) or U_F(f) X(f) V_F(f)^H (inverse)
+  auto products = [&](bool inverse) {
+    __syncthreads();
+    for (int f = 0; f < NF; ++f) {
+      const float* Vr = fb + ((NF + f) * 2 + 0) * 64;
+      const float* Vi = fb + ((NF + f) * 2 + 1) * 64;
+      float yr = 0.f, yi = 0.f;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const float pr = X[f * 128 + a * 8 + t], pi = X[f * 128 + 64 + a * 8 + t];
+        const float vr = inverse ? Vr[b * 8 + t] : Vr[t * 8 + b];     // conj(V(b,t)) or V(t,b)
+        const float vi = inverse ? -Vi[b * 8 + t] : Vi[t * 8 + b];
+        yr += pr * vr - pi * vi;
+        yi += pr * vi + pi * vr;
+      }
+      Y[f * 128 + lane] = yr;
+      Y[f * 128 + 64 + lane] = yi;
     }
     __syncthreads();
-    tl[lane] = yr;
-    tl[64 + lane] = yi;
-    __syncthreads();
-    float or_ = 0.f, oi = 0.f;
+    for (int f = 0; f < NF; ++f) {
+      const float* Ur = fb + (f * 2 + 0) * 64;
+      const float* Ui = fb + (f * 2 + 1) * 64;
+      float zr = 0.f, zi = 0.f;
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const float pr = tl[t * 8 + b], pi = tl[64 + t * 8 + b];
-      // forward: conj(U(t, a)); inverse: U(a, t)
-      const float ur = inverse ? Ur[a * 8 + t] : Ur[t * 8 + a];
-      const float ui = inverse ? Ui[a * 8 + t] : -Ui[t * 8 + a];
-      or_ += ur * pr - ui * pi;
-      oi += ur * pi + ui * pr;
+      for (int t = 0; t < 8; ++t) {
+        const float pr = Y[f * 128 + t * 8 + b], pi = Y[f * 128 + 64 + t * 8 + b];
+        const float ur = inverse ? Ur[a * 8 + t] : Ur[t * 8 + a];     // U(a,t) or conj(U(t,a))
+        const float ui = inverse ? Ui[a * 8 + t] : -Ui[t * 8 + a];
+        zr += ur * pr - ui * pi;
+        zi += ur * pi + ui * pr;
+      }
+      X[f * 128 + lane] = zr;
+      X[f * 128 + 64 + lane] = zi;
     }
-    zr = or_;
-    zi = oi;
   };
   for (int gl = blockIdx.x; gl < d.ref_count; gl += gridDim.x) {
     const int grp = d.ref_begin + gl;
@@ -313,30 +356,20 @@ __global__ __launch_bounds__(64) void k_filter_gen(Launch L) {
       py = min(max(py, 0), d.Hp - 1);
       px = min(max(px, 0), d.Wp - 1);
       const int pix = (py + a) * d.W + px + b;
+      __syncthreads();   // Y is read across lanes by the previous slot's products
       for (int j = 0; j < C; ++j) {
         const float v = d.img[(size_t)j * HW + pix];
         bad |= !isfinite(v);
-        pv[j * 64 + lane] = v;
+        Y[j * 64 + lane] = v;
       }
-      for (int f = 0; f < NF; ++f) {
-        float pr = 0.f, pi = 0.f;
-        for (int j = 0, m = 0; j < C; ++j, m = (m + f) % C) {
-          pr = fmaf(pv[j * 64 + lane], tc[m], pr);
-          pi = fmaf(pv[j * 64 + lane], ts[m], pi);
-        }
-        float zr, zi;
-        product(f, false, pr, pi, zr, zi);
-        zf[f * 128 + lane] = zr;
-        zf[f * 128 + 64 + lane] = zi;
-      }
-      // T_j = (1/c) sum over all f of Z(f) e^{2 pi i f j / c}
-      for (int j = 0; j < C; ++j) {
-        float t = zf[lane];
-        for (int f = 1, m = j; f < NF; ++f, m = (m + j) % C) {
-          const float w = 2 * f == C ? 1.f : 2.f;
-          t += w * (zf[f * 128 + lane] * tc[m] + zf[f * 128 + 64 + lane] * ts[m]);
-        }
-        S[((size_t)k * C + j) * 64 + lane] = t * (1.0f / (float)C);
+      dft_bands();
+      products(false);
+      for (int j0 = 0; j0 < C; j0 += 4) {
+        float t[4];
+        idft_bands4(j0, t);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (j0 + u < C) S[((size_t)k * C + j0 + u) * 64 + lane] = t[u] * (1.0f / (float)C);
       }
     }
     // Haar along the group, hard threshold (Eq. 19), inverse; per band
@@ -369,30 +402,24 @@ __global__ __launch_bounds__(64) void k_filter_gen(Launch L) {
       py = min(max(py, 0), d.Hp - 1);
       px = min(max(px, 0), d.Wp - 1);
       const int pix = (py + a) * d.W + px + b;
-      for (int j = 0; j < C; ++j) pv[j * 64 + lane] = S[((size_t)k * C + j) * 64 + lane];
-      for (int f = 0; f < NF; ++f) {
-        float sr = 0.f, si = 0.f;
-        for (int j = 0, m = 0; j < C; ++j, m = (m + f) % C) {
-          sr = fmaf(pv[j * 64 + lane], tc[m], sr);
-          si = fmaf(pv[j * 64 + lane], ts[m], si);
-        }
-        float zr, zi;
-        product(f, true, sr, si, zr, zi);
-        zf[f * 128 + lane] = zr;
-        zf[f * 128 + 64 + lane] = zi;
-      }
-      for (int j = 0; j < C; ++j) {
-        float t = zf[lane];
-        for (int f = 1, m = j; f < NF; ++f, m = (m + j) % C) {
-          const float w = 2 * f == C ? 1.f : 2.f;
-          t += w * (zf[f * 128 + lane] * tc[m] + zf[f * 128 + 64 + lane] * ts[m]);
-        }
-        pv[j * 64 + lane] = t;   // c x the estimate (the 1/c is in fxs)
-        bad |= !isfinite(t);
+      __syncthreads();
+      for (int j = 0; j < C; ++j) Y[j * 64 + lane] = S[((size_t)k * C + j) * 64 + lane];
+      dft_bands();
+      products(true);
+      // c x the estimate (the 1/c is in fxs), parked in the slot's scratch
+      for (int j0 = 0; j0 < C; j0 += 4) {
+        float t[4];
+        idft_bands4(j0, t);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (j0 + u < C) {
+            bad |= !isfinite(t[u]);
+            S[((size_t)k * C + j0 + u) * 64 + lane] = t[u];
+          }
       }
       if (__ballot(bad)) break;
       for (int j = 0; j < C; ++j)
-        atomicAdd(d.num64 + (size_t)j * HW + pix, fx_from_float(pv[j * 64 + lane] * fxs));
+        atomicAdd(d.num64 + (size_t)j * HW + pix, fx_from_float(S[((size_t)k * C + j) * 64 + lane] * fxs));
     }
     if (__ballot(bad)) poison_group(d, gi, gl, K, C, rW, lane);
   }

@@ -239,7 +239,7 @@ hipError_t launch_fbasis_gen(const Launch& L, hipStream_t s) {
 }
 
 size_t filter_gen_lds_bytes(int C) {
-  return ((size_t)2 * C + (size_t)2 * n_freq(C) * 128) * 4;
+  return ((size_t)C + (size_t)2 * n_freq(C) * 64) * sizeof(float2);
 }
 
 // One wavefront per work group, groups [ref_begin, ref_begin + ref_count)
@@ -247,16 +247,17 @@ size_t filter_gen_lds_bytes(int C) {
 // scratch holds the group's real core tensor [K][C][64].  Per slot, the
 // products of all frequencies share two LDS round trips: X(f) (the DFT of
 // the bands, lane-private entry) -> Y(f) = X(f) V_F(f) (or X(f) V_F(f)^H)
-// -> U_F(f)^H Y(f) (or U_F(f) Y(f)) back into X(f).  The lane's band values
-// are parked in the Y area while the DFT reads them.
+// -> U_F(f)^H Y(f) (or U_F(f) Y(f)) back into X(f).  Complex values and
+// twiddles are float2 (one LDS access per complex operand); the lane's band
+// values are parked in the Y area while the DFT reads them.
 template <int K>
 __global__ __launch_bounds__(64) void k_filter_gen(Launch L) {
-  extern __shared__ float fsm[];
+  extern __shared__ float2 fsm2[];
   const int C = L.C, NF = n_freq(C);
-  float* tc = fsm;                 // twiddles e^{-2 pi i m / c}
-  float* ts = tc + C;
-  float* X = ts + C;               // [NF][re/im][64]
-  float* Y = X + NF * 128;         // [NF][re/im][64]; the band values [C][64] before the products
+  float2* tw = fsm2;               // e^{-2 pi i m / c} = (cos, -sin), m < c
+  float2* X = tw + C;              // [NF][64]
+  float2* Y = X + NF * 64;         // [NF][64]; the band values (float [C][64]) before the products
+  float* Yb = (float*)Y;
   const int lane = threadIdx.x, a = lane >> 3, b = lane & 7;
   const ImgDesc& d = L.one;
   const int HW = d.H * d.W;
@@ -265,7 +266,11 @@ __global__ __launch_bounds__(64) void k_filter_gen(Launch L) {
   float* S = d.gscratch + (size_t)blockIdx.x * K * C * 64;
   const float tau = d.tau;
   const float fxs = fx_scale(d) / (float)C;
-  fill_twiddles(tc, ts, C);
+  for (int m = threadIdx.x; m < C; m += blockDim.x) {
+    double sn, cs;
+    sincospi(2.0 * (double)m / (double)C, &sn, &cs);
+    tw[m] = make_float2((float)cs, (float)-sn);
+  }
   __syncthreads();
   // X(f) <- DFT of the lane's band values (in Y), f < NF; four frequencies
   // per pass over the bands (twiddle index m_f = f j mod c, kept by adding f)
@@ -274,37 +279,38 @@ __global__ __launch_bounds__(64) void k_filter_gen(Launch L) {
       float xr[4] = {0.f, 0.f, 0.f, 0.f}, xi[4] = {0.f, 0.f, 0.f, 0.f};
       int m[4] = {0, 0, 0, 0};
       for (int j = 0; j < C; ++j) {
-        const float v = Y[j * 64 + lane];
+        const float v = Yb[j * 64 + lane];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          xr[u] = fmaf(v, tc[m[u]], xr[u]);
-          xi[u] = fmaf(v, ts[m[u]], xi[u]);
+          const float2 w = tw[m[u]];
+          xr[u] = fmaf(v, w.x, xr[u]);
+          xi[u] = fmaf(v, w.y, xi[u]);
           m[u] += f0 + u;
           m[u] -= m[u] >= C ? C : 0;
         }
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u)
-        if (f0 + u < NF) {
-          X[(f0 + u) * 128 + lane] = xr[u];
-          X[(f0 + u) * 128 + 64 + lane] = xi[u];
-        }
+        if (f0 + u < NF) X[(f0 + u) * 64 + lane] = make_float2(xr[u], xi[u]);
     }
   };
   // bands j0..j0+3 of c x the (1/c) IDFT of the lane's X(f), f < NF
   auto idft_bands4 = [&](int j0, float* t) {
     int m[4];
+    const float x0 = X[lane].x;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      t[u] = X[lane];
+      t[u] = x0;
       m[u] = min(j0 + u, C - 1);
     }
     for (int f = 1; f < NF; ++f) {
       const float w = 2 * f == C ? 1.f : 2.f;
-      const float zr = w * X[f * 128 + lane], zi = w * X[f * 128 + 64 + lane];
+      const float2 z = X[f * 64 + lane];
+      const float zr = w * z.x, zi = w * z.y;
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        t[u] += zr * tc[m[u]] + zi * ts[m[u]];
+        const float2 e = tw[m[u]];
+        t[u] += zr * e.x + zi * e.y;
         m[u] += j0 + u;
         m[u] -= m[u] >= C ? C : 0;
       }
@@ -319,14 +325,13 @@ __global__ __launch_bounds__(64) void k_filter_gen(Launch L) {
       float yr = 0.f, yi = 0.f;
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
-        const float pr = X[f * 128 + a * 8 + t], pi = X[f * 128 + 64 + a * 8 + t];
+        const float2 p = X[f * 64 + a * 8 + t];
         const float vr = inverse ? Vr[b * 8 + t] : Vr[t * 8 + b];     // conj(V(b,t)) or V(t,b)
         const float vi = inverse ? -Vi[b * 8 + t] : Vi[t * 8 + b];
-        yr += pr * vr - pi * vi;
-        yi += pr * vi + pi * vr;
+        yr += p.x * vr - p.y * vi;
+        yi += p.x * vi + p.y * vr;
       }
-      Y[f * 128 + lane] = yr;
-      Y[f * 128 + 64 + lane] = yi;
+      Y[f * 64 + lane] = make_float2(yr, yi);
     }
     __syncthreads();
     for (int f = 0; f < NF; ++f) {
@@ -335,14 +340,13 @@ __global__ __launch_bounds__(64) void k_filter_gen(Launch L) {
       float zr = 0.f, zi = 0.f;
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
-        const float pr = Y[f * 128 + t * 8 + b], pi = Y[f * 128 + 64 + t * 8 + b];
+        const float2 p = Y[f * 64 + t * 8 + b];
         const float ur = inverse ? Ur[a * 8 + t] : Ur[t * 8 + a];     // U(a,t) or conj(U(t,a))
         const float ui = inverse ? Ui[a * 8 + t] : -Ui[t * 8 + a];
-        zr += ur * pr - ui * pi;
-        zi += ur * pi + ui * pr;
+        zr += ur * p.x - ui * p.y;
+        zi += ur * p.y + ui * p.x;
       }
-      X[f * 128 + lane] = zr;
-      X[f * 128 + 64 + lane] = zi;
+      X[f * 64 + lane] = make_float2(zr, zi);
     }
   };
   for (int gl = blockIdx.x; gl < d.ref_count; gl += gridDim.x) {
@@ -360,7 +364,7 @@ __global__ __launch_bounds__(64) void k_filter_gen(Launch L) {
       for (int j = 0; j < C; ++j) {
         const float v = d.img[(size_t)j * HW + pix];
         bad |= !isfinite(v);
-        Y[j * 64 + lane] = v;
+        Yb[j * 64 + lane] = v;
       }
       dft_bands();
       products(false);
@@ -403,7 +407,7 @@ __global__ __launch_bounds__(64) void k_filter_gen(Launch L) {
       px = min(max(px, 0), d.Wp - 1);
       const int pix = (py + a) * d.W + px + b;
       __syncthreads();
-      for (int j = 0; j < C; ++j) Y[j * 64 + lane] = S[((size_t)k * C + j) * 64 + lane];
+      for (int j = 0; j < C; ++j) Yb[j * 64 + lane] = S[((size_t)k * C + j) * 64 + lane];
       dft_bands();
       products(true);
       // c x the estimate (the 1/c is in fxs), parked in the slot's scratch

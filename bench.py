@@ -37,7 +37,8 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-path comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adaptive", action="store_true",
-                    help="skip the A-Haar-tSVD, weighted-aggregation and Fourier-threshold batch timings")
+                    help="skip the A-Haar-tSVD, weighted-aggregation, Fourier-threshold and "
+                         "spectral-tube timings")
     ap.add_argument("--batch-api", type=int, default=1,
                     help="1: hts_denoise_batch (one graph); 0: one hts_denoise per image")
     ap.add_argument("--tune", type=int, default=0)
@@ -282,6 +283,29 @@ def main():
                    "psnr_db": round(psnr_all(), 4)}
         del ws_f
 
+    # ---- spectral tubes: one HSI-shaped image (520 x 696 x 34 bands, the
+    # size of the paper's real-HSI scenes), synthetic, AWGN sigma = 25, the
+    # same method parameters; general band-count path of hts_denoise ----
+    tubes = None
+    if not args.no_adaptive:
+        from paper_2508_10307_amd import synth
+        Ct, Ht, Wt = 34, 520, 696
+        clean_t = synth.clean_image(4242, 0, Ct, Ht, Wt, 40)
+        xt = torch.from_numpy(synth.add_awgn(4242, 0, clean_t, 25.0)).to(dev)
+        pt = api.Params(stride=q.stride, window=q.window, K=q.K, tau_mult=q.tau_mult)
+        ws_t = api.workspace(pt, Ct, Ht, Wt, dev)
+        res_t = {}
+
+        def run_t():
+            res_t["o"] = api.hts_denoise(xt, 25.0, pt, ws=ws_t)
+
+        mst = timed(run_t, 3, 1)
+        mse_t = float(((res_t["o"].double().cpu().numpy() - clean_t) ** 2).mean())
+        tubes = {"value": round(Ht * Wt / 1e6 / (mst / 1e3), 3), "unit": "MPix/s",
+                 "ms_per_image": round(mst, 3), "shape": [Ct, Ht, Wt],
+                 "psnr_db": round(10 * np.log10(255.0 ** 2 / mse_t), 4)}
+        del ws_t, xt
+
     # ---- roofline of the dominant kernel: the fused filter, timed live ----
     # One eager launch per image (the same filter the batched graph runs, as
     # its single-image instantiation), timed with HIP events on its stream:
@@ -366,6 +390,7 @@ def main():
         "adaptive": adaptive,
         "weighted": weighted,
         "fourier_threshold": fourier,
+        "spectral_tubes": tubes,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

@@ -442,9 +442,15 @@ hts_status enqueue_batch(const hts_params* p, int C, const BatchPlan& plan, cons
     return L;
   };
   HIPCHK(launch_reset_counters(LK(-1), s));
-  // The basis (covariances, eigen-solve, Fourier slices) depends on the
-  // images only: it runs on a second stream beside quantisation and matching
-  // (a branch of the captured graph) and joins before the filter.
+  HIPCHK(launch_quant(LC(W_PIX), cus * 8, s));
+  HIPCHK(launch_gcp(LK(W_REF), cus * 8, s));
+  // The covariances depend on the images only: they run on a second stream
+  // beside the match (a branch of the captured graph) and join after it.
+  // Forked before quantisation instead, so that they also ran beside it and
+  // GCP, they made the match 1.8x slower on MI355X (16 -> 29 ms on the
+  // 64-image batch; measured, with the same results).  The eigen-solves (one
+  // work group per image, a barrier-bound Jacobi) run after the join on
+  // their own, so they hold none of the match's compute-unit slots.
   const Branch br = branch_for_device();
   hipStream_t bs = s;
   if (br.side) {
@@ -452,18 +458,16 @@ hts_status enqueue_batch(const hts_params* p, int C, const BatchPlan& plan, cons
     HIPCHK(hipStreamWaitEvent(br.side, br.fork, 0));
     bs = br.side;
   }
-  HIPCHK(launch_quant(LC(W_PIX), cus * 8, s));
-  HIPCHK(launch_gcp(LK(W_REF), cus * 8, s));
   HIPCHK(launch_match(LC(W_MATCH), p->match_mode, sc.terms, cus * 2, s));
   HIPCHK(launch_cov(LK(W_COV), cus * 4, bs));
-  HIPCHK(launch_eig(LK(-1), bs));
-  HIPCHK(launch_fbasis(LK(-1), nullptr, nullptr, bs));
   if (br.side) HIPCHK(hipEventRecord(br.join, bs));
   HIPCHK(launch_match_fallback(LC(-1), cus, s));
   if (plan.descs[0].n_samples > 0) HIPCHK(launch_vote(LK(-1), s));   // A-Haar-tSVD sigma
   HIPCHK(launch_zero_accum(LK(W_PIX), cus * 8, s));
   HIPCHK(launch_count_box(LK(W_BOX), cus * 8, s));
   if (br.side) HIPCHK(hipStreamWaitEvent(s, br.join, 0));
+  HIPCHK(launch_eig(LK(-1), s));
+  HIPCHK(launch_fbasis(LK(-1), nullptr, nullptr, s));
   if (sc.valu) HIPCHK(launch_filter(LK(W_FILT), sc.fty, sc.ftx, 0, cus * 2, s));
   else HIPCHK(launch_filter_mfma(LK(W_FILT), sc.fty, sc.ftx, 0, cus * 2, s));
   HIPCHK(launch_finalize(LK(W_PIX), cus * 8, s));

@@ -21,17 +21,17 @@ __global__ __launch_bounds__(256) void k_quant(Launch L) {
         d.gplanes[p] = quantize(v);
         mb = max(mb, abs_bits(v));
       } else if (L.C != 3) {
-        long long sq = 0;
+        int sq = 0;   // |sum| <= 256 (2^20 - 1) < 2^28
         for (int j = 0; j < L.C; ++j) {
           const float v = d.img[(size_t)j * HW + p];
           sq += quantize(v);
           mb = max(mb, abs_bits(v));
         }
         // floor division, then half to even
-        long long fl = sq / L.C, rem = sq - fl * L.C;
+        int fl = sq / L.C, rem = sq - fl * L.C;
         if (rem < 0) { --fl; rem += L.C; }
         if (2 * rem > L.C || (2 * rem == L.C && (fl & 1))) ++fl;
-        d.gplanes[p] = (int)fl;
+        d.gplanes[p] = fl;
       } else {
         const float r = d.img[p], g = d.img[HW + p], b = d.img[2 * HW + p];
         int qr = quantize(r);

@@ -91,7 +91,7 @@ TRAFFIC_SOURCES = ["paper_2508_10307_amd/csrc/k_filter.hip",
                    "paper_2508_10307_amd/csrc/hts_internal.h"]
 TRAFFIC = {    # kernel name -> (sources sha256, bytes per launch)
     "void hts::k_filter<3, 4, 0, 0, 0, 0, 0>(hts::Launch)":
-        ("eede9109030988bab2861379c862de2d82fc0f296ea2c91708f344b8eaafec92", 58501355),
+        ("aeca2903cac52c8fea28c9e7f1f2d2d16b60d8654adb5ba28c2cfcf0e0354175", 58499712),
 }
 
 

@@ -97,3 +97,38 @@ def test_nan_band_pixel_makes_the_output_nan():
     y[3, 11, 7] = np.nan
     out = api.hts_denoise(T(y), 10.0, api.Params(stride=3, window=9, K=8))
     assert torch.isnan(out).all()
+
+
+@pytest.mark.parametrize("C,K,s", [(256, 4, 3), (2, 32, 1), (12, 2, 8)])
+def test_band_count_extremes(C, K, s):
+    """The largest band count, stride 1 with the largest group, stride 8 with
+    the smallest group: the same parity bar."""
+    sigma = 15.0
+    H, W, w = 20, 22, 11
+    y = tube(C, H, W, 2400 + C + K, sigma)
+    p = api.Params(stride=s, window=w, K=K)
+    x = T(y)
+    out, st = api.hts_denoise(x, sigma, p, save=True)
+    idx = st["idx"].cpu().numpy().astype(np.int64)
+    idx_o, _, _ = om.match(y, 8, s, w, K)
+    np.testing.assert_array_equal(idx, idx_o)
+    masks = opipe.unpack_masks(st["masks"].cpu().numpy().view(np.uint32), len(idx), K, C)
+    r = opipe.denoise(y, sigma, 8, s, w, K, p.tau_mult, idx=idx, U=st["U"].cpu().numpy(),
+                      V=st["V"].cpu().numpy(), mask=masks)
+    assert r["max_override_margin"] <= DELTA_REL * max(p.tau_mult * sigma, 1.0)
+    err = np.abs(out.cpu().numpy() - r["out"]).max()
+    log(f"C{C} K{K} s{s}: max |gpu - oracle| = {err:.3e}, overrides {r['n_override']}")
+    assert err <= PIX_TOL
+
+
+def test_band_count_entry_points_refuse_unbuilt_calls():
+    y = tube(5, 24, 24, 2500)
+    x = T(y)
+    p = api.Params(stride=3, window=9, K=8)
+    _, st = api.hts_denoise(x, 10.0, p, save=True)
+    with pytest.raises(api.L.HtsError):
+        api.hts_denoise_batch([x], [10.0], p)
+    with pytest.raises(api.L.HtsError):
+        api.hts_denoise_backward(T(np.ones_like(y)), st, p)
+    with pytest.raises(api.L.HtsError):
+        api.hts_denoise(x, 10.0, api.Params(stride=3, window=9, K=8, flags=api.L.HTS_FLAG_WEIGHTED))

@@ -22,13 +22,15 @@ Modules
   adjoint   the frozen-index/frozen-mask linear map and its transpose.
   basis_adjoint  the derivative through the learned basis (eigenvector
             perturbation, phase gauge, covariance chain rule).
+  video     spatio-temporal grouping across frames and the video pipeline
+            on the stacked frames.
   adaptive  A-Haar-tSVD noise-level adjustment (Sec. III-C, Eq. 21-22): the
             circulant eigenvalue rank test, the vote, sub-image denoising.
 
 Parity status (each function is pinned by a test in tests/test_oracle_*.py
 against printed values, closed forms, invariants or brute force):
   haar, grid, matching, basis, filtering, pipeline, adjoint, basis_adjoint,
-  adaptive: pinned.
+  video, adaptive: pinned.
   End-to-end denoising quality: parity unpinned by the paper (its PSNR tables
   need datasets that are not available); only a sanity band is checked.
 """

@@ -243,6 +243,30 @@ hts_status hts_denoise_backward_basis(const hts_params* p, const float* noisy,
                                       int32_t W, float* grad_in, void* ws, size_t ws_bytes,
                                       void* stream);
 
+/* Video denoising with spatio-temporal patch search (Sec. IV: the search
+ * runs over the spatial and the temporal dimension).  frames: device
+ * float32 [T][C][H][W] (C = 1, 3, or 2..256 bands), out the same.  Each
+ * frame has the reference grid of hts_match; a reference of frame t takes
+ * candidates from frames t-dt..t+dt (truncated at the ends of the sequence)
+ * inside its truncated spatial window, ranked by the exact guide distance of
+ * hts_match (GCP branch from the reference patch for C = 3, band mean for
+ * other C), ties to the lower stacked index; positions are numbered in the
+ * frames stacked one above the other, idx = (t' H + y) W + x.  One basis for
+ * the sequence (Eq. 11-12 over the reference patches of every frame); the
+ * groups are filtered (Eq. 18-20) and averaged (Eq. 2) over the stacked
+ * frames.  idx_out (nullable, int32 [T n_ref][K], references frame by
+ * frame), masks_out (nullable, as hts_filter for the T n_ref groups),
+ * U_out / V_out (nullable, float32 [C][ps][ps]), cnt_out (nullable, float32
+ * [T H][W]).  Requires K <= 32, no flags and (2 min(dt, T-1) + 1) window^2
+ * <= 4096 (HTS_ERR_UNSUPPORTED otherwise); HTS_ERR_INVALID for T < 1,
+ * dt < 0, null frames / out / ws, sigma < 0 or non-finite. */
+hts_status hts_video_workspace_size(const hts_params* p, int32_t T, int32_t C, int32_t H,
+                                    int32_t W, int32_t dt, size_t* bytes);
+hts_status hts_denoise_video(const hts_params* p, const float* frames, int32_t T, int32_t C,
+                             int32_t H, int32_t W, int32_t dt, float sigma, float* out,
+                             int32_t* idx_out, uint32_t* masks_out, float* U_out, float* V_out,
+                             float* cnt_out, void* ws, size_t ws_bytes, void* stream);
+
 /* Workspace bytes for hts_denoise_batch over these n images (host array). */
 hts_status hts_batch_workspace_size(const hts_params* p, const hts_image* imgs, int32_t n,
                                     size_t* bytes);

@@ -384,6 +384,41 @@ def hts_denoise_backward_basis(noisy, grad_out, st, p: Params, grad_in, basis64=
     return grad_in
 
 
+def hts_denoise_video(frames: torch.Tensor, sigma: float, p: Params, dt: int = 1, save=False,
+                      ws=None):
+    """Video denoising with spatio-temporal search over frames t-dt..t+dt.
+    frames [T, C, H, W] float32 on the GPU.  With save=True also returns
+    dict(idx [T n_ref, K] in stacked coordinates, masks, U, V, cnt [T H, W])."""
+    if frames.dim() != 4:
+        raise ValueError("frames must be [T, C, H, W]")
+    if not frames.is_cuda or frames.dtype != torch.float32:
+        raise ValueError("frames must be a float32 tensor on the GPU")
+    x = frames.contiguous()
+    T, C, H, W = x.shape
+    dev = x.device
+    out = torch.empty_like(x)
+    pc = p.c()
+    n = L.c_sz()
+    L.check("hts_video_workspace_size", L.load().hts_video_workspace_size(
+        ctypes.byref(pc), T, C, H, W, int(dt), ctypes.byref(n)))
+    if ws is None:
+        ws = torch.empty(n.value, dtype=torch.uint8, device=dev)
+    st = {}
+    if save:
+        ny, nx = ref_grid(H, W, p)
+        n_ref = T * ny * nx
+        st = {"idx": torch.empty((n_ref, p.K), dtype=torch.int32, device=dev),
+              "masks": torch.zeros(mask_words(n_ref, p.K, C), dtype=torch.int32, device=dev),
+              "U": torch.empty((C, 8, 8), dtype=torch.float32, device=dev),
+              "V": torch.empty((C, 8, 8), dtype=torch.float32, device=dev),
+              "cnt": torch.empty((T * H, W), dtype=torch.float32, device=dev)}
+    L.check("hts_denoise_video", L.load().hts_denoise_video(
+        ctypes.byref(pc), _ptr(x), T, C, H, W, int(dt), float(sigma), _ptr(out),
+        _ptr(st.get("idx")), _ptr(st.get("masks")), _ptr(st.get("U")), _ptr(st.get("V")),
+        _ptr(st.get("cnt")), _ptr(ws), ws.numel(), _stream(dev)))
+    return (out, st) if save else out
+
+
 class HaarTSVD(torch.autograd.Function):
     """Differentiable Haar-tSVD denoiser: forward = hts_denoise; backward =
     the hand-written adjoint kernel with match indices, threshold masks,

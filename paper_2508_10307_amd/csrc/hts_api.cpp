@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "hts_internal.h"
+#include "video_internal.h"
 
 using namespace hts;
 
@@ -1008,6 +1009,154 @@ hts_status hts_autotune(const hts_params* p, int32_t C, int32_t H, int32_t W,
     }
   }
   *tune_out = word;
+  return HTS_OK;
+}
+
+// ---- video: spatio-temporal search over the stacked frames ----
+
+namespace {
+
+struct VideoPlan {
+  Geo f;                 // one frame
+  VideoGeo v;
+  int n_ref, np, NF, grid;
+  size_t stacked, sout, gplanes, idx, cov, basis64, basis, fbasis, ufg, num64, cnt, hist, poison,
+      fxmax, fb_count, gscratch, total;
+};
+
+hts_status plan_video(const hts_params* p, int T, int C, int H, int W, int dt, VideoPlan& vp) {
+  hts_status st = make_geo(p, C, H, W, vp.f);
+  if (st != HTS_OK) return st;
+  if (T < 1 || dt < 0) return HTS_ERR_INVALID;
+  if (p->flags || p->K > GEN_KMAX) return HTS_ERR_UNSUPPORTED;   // uniform Eq. 2 and Eq. 19
+  if ((long long)(2 * std::min(dt, T - 1) + 1) * p->window * p->window > VIDEO_CAND_MAX)
+    return HTS_ERR_UNSUPPORTED;
+  const long long px = (long long)T * H * W;
+  if (px * C >= (1LL << 31) || (long long)T * vp.f.n_ref * p->K >= (1LL << 31)) return HTS_ERR_UNSUPPORTED;
+  vp.n_ref = T * vp.f.n_ref;
+  vp.np = C == 3 ? 2 : 1;
+  vp.NF = n_freq(C);
+  vp.grid = std::min(vp.n_ref, GEN_GRID);
+  vp.v = VideoGeo{T, H, vp.f.Hp, vp.f.Wp, vp.f.nry, vp.f.nrx, vp.f.n_ref, dt};
+  size_t o = 0;
+  vp.stacked = o; o += al((size_t)px * C * 4);
+  vp.sout = o; o += al((size_t)px * C * 4);
+  vp.gplanes = o; o += al((size_t)px * vp.np * 4);
+  vp.idx = o; o += al((size_t)vp.n_ref * p->K * 4);
+  vp.cov = o; o += al((size_t)T * vp.f.n_cov * cov_elems(C) * 8);
+  vp.basis64 = o; o += al((size_t)(2 * C * 64 + 2 * vp.NF * 8) * 8);
+  vp.basis = o; o += al((size_t)2 * C * 64 * 4);
+  vp.fbasis = o; o += al((size_t)std::max(FB_SIZE, 2 * vp.NF * 128) * 4);
+  vp.ufg = o; o += al((size_t)2 * vp.NF * 128 * 8);
+  vp.num64 = o; o += al((size_t)px * C * 8);
+  vp.cnt = o; o += al((size_t)px * 4);
+  vp.hist = o; o += al((size_t)px * 4);
+  vp.poison = o; o += al((size_t)px);
+  vp.fxmax = o; o += al(4);
+  vp.fb_count = o; o += al(4);
+  vp.gscratch = o; o += al((size_t)vp.grid * p->K * C * 64 * 4);
+  vp.total = o;
+  return HTS_OK;
+}
+
+}  // namespace
+
+hts_status hts_video_workspace_size(const hts_params* p, int32_t T, int32_t C, int32_t H,
+                                    int32_t W, int32_t dt, size_t* bytes) {
+  if (!bytes) return HTS_ERR_INVALID;
+  VideoPlan vp;
+  const hts_status st = plan_video(p, T, C, H, W, dt, vp);
+  if (st != HTS_OK) return st;
+  *bytes = vp.total;
+  return HTS_OK;
+}
+
+hts_status hts_denoise_video(const hts_params* p, const float* frames, int32_t T, int32_t C,
+                             int32_t H, int32_t W, int32_t dt, float sigma, float* out,
+                             int32_t* idx_out, uint32_t* masks_out, float* U_out, float* V_out,
+                             float* cnt_out, void* ws, size_t ws_bytes, void* stream) {
+  VideoPlan vp;
+  hts_status st = plan_video(p, T, C, H, W, dt, vp);
+  if (st != HTS_OK) return st;
+  if (!frames || !out || !ws) return HTS_ERR_INVALID;
+  if (!(sigma >= 0.f) || !std::isfinite(sigma)) return HTS_ERR_INVALID;
+  if (ws_bytes < vp.total) return HTS_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  char* b = (char*)ws;
+  const int TH = T * H;
+  // descriptor of the stacked image [C][T*H][W]
+  ImgDesc d;
+  std::memset(&d, 0, sizeof(d));
+  d.img = (const float*)(b + vp.stacked);
+  d.out = (float*)(b + vp.sout);
+  d.gplanes = (int32_t*)(b + vp.gplanes);
+  d.idx = idx_out ? idx_out : (int32_t*)(b + vp.idx);
+  d.fb_count = (int32_t*)(b + vp.fb_count);
+  d.cov_part = (double*)(b + vp.cov);
+  d.basis64 = (double*)(b + vp.basis64);
+  d.basis = (float*)(b + vp.basis);
+  d.fbasis = (float*)(b + vp.fbasis);
+  d.ufg = (double*)(b + vp.ufg);
+  d.num64 = (unsigned long long*)(b + vp.num64);
+  d.cnt = cnt_out ? cnt_out : (float*)(b + vp.cnt);
+  d.hist = (int32_t*)(b + vp.hist);
+  d.poison = (uint8_t*)(b + vp.poison);
+  d.fxmax = (uint32_t*)(b + vp.fxmax);
+  d.gscratch = (float*)(b + vp.gscratch);
+  d.masks = masks_out;
+  d.H = TH; d.W = W; d.Hp = TH - PS + 1; d.Wp = W - PS + 1;
+  d.nry = vp.f.nry; d.nrx = vp.f.nrx; d.n_ref = vp.n_ref;
+  d.ref_begin = 0; d.ref_count = vp.n_ref;
+  d.sigma = sigma;
+  d.tau = p->tau_mult * sigma;
+  d.n_cov = T * vp.f.n_cov;
+  d.wcnt[W_PIX] = (int)(((long long)TH * W + PIX_CHUNK - 1) / PIX_CHUNK);
+  d.wcnt[W_REF] = (vp.n_ref + 255) / 256;
+  d.wcnt[W_BOX] = ((TH + BOX_TY - 1) / BOX_TY) * ((W + BOX_TX - 1) / BOX_TX);
+  auto LS = [&](const ImgDesc& dd, int kind) {
+    Launch L;
+    std::memset(&L, 0, sizeof(L));
+    L.one = dd;
+    L.n_img = 1;
+    L.total = kind >= 0 ? dd.wcnt[kind] : 1;
+    L.C = C; L.K = p->K; L.stride = p->stride; L.window = p->window;
+    L.tau_mult = p->tau_mult;
+    L.gcp_num = p->gcp_num; L.gcp_den = p->gcp_den;
+    return L;
+  };
+  HIPCHK(launch_stack(frames, (float*)d.img, T, C, H, W, false, s));
+  // guide planes (and the magnitude that sets the fixed-point scale)
+  HIPCHK(launch_reset_counters(LS(d, -1), s));
+  HIPCHK(launch_quant(LS(d, W_PIX), 0, s));
+  HIPCHK(launch_match_video(LS(d, -1), vp.v, s));
+  // one basis for the sequence: every frame's covariance partials, in
+  // frame order, then the eigen-solves over all of them
+  for (int t = 0; t < T; ++t) {
+    ImgDesc df;
+    std::memset(&df, 0, sizeof(df));
+    df.img = frames + (size_t)t * C * H * W;
+    df.cov_part = d.cov_part + (size_t)t * vp.f.n_cov * cov_elems(C);
+    df.H = H; df.W = W; df.Hp = vp.f.Hp; df.Wp = vp.f.Wp;
+    df.nry = vp.f.nry; df.nrx = vp.f.nrx; df.n_ref = vp.f.n_ref;
+    df.n_cov = vp.f.n_cov;
+    df.wcnt[W_COV] = vp.f.n_cov;
+    if (general_c(C)) HIPCHK(launch_cov_gen(LS(df, -1), s));
+    else HIPCHK(launch_cov(LS(df, W_COV), 0, s));
+  }
+  if (general_c(C)) HIPCHK(launch_eig_gen(LS(d, -1), s));
+  else HIPCHK(launch_eig(LS(d, -1), s));
+  HIPCHK(launch_fbasis_gen(LS(d, -1), s));
+  // filter and average over the stacked image
+  HIPCHK(launch_zero_accum(LS(d, W_PIX), 0, s));
+  HIPCHK(launch_filter_gen(LS(d, -1), vp.grid, s));
+  HIPCHK(launch_zero_hist(LS(d, W_PIX), 0, s));
+  HIPCHK(launch_count_hist(LS(d, W_REF), 0, s));
+  HIPCHK(launch_count_box(LS(d, W_BOX), 0, s));
+  HIPCHK(launch_finalize(LS(d, W_PIX), 0, s));
+  HIPCHK(launch_stack(out, d.out, T, C, H, W, true, s));
+  const size_t nb = (size_t)C * 64;
+  if (U_out) HIPCHK(hipMemcpyAsync(U_out, d.basis, nb * 4, hipMemcpyDeviceToDevice, s));
+  if (V_out) HIPCHK(hipMemcpyAsync(V_out, d.basis + nb, nb * 4, hipMemcpyDeviceToDevice, s));
   return HTS_OK;
 }
 

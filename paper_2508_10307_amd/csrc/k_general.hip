@@ -23,6 +23,7 @@
 // Twiddles come from sincospi (exact at the quarter points).
 #include "jacobi8.h"
 #include "group_proj.h"
+#include "video_internal.h"
 
 namespace hts {
 
@@ -197,19 +198,30 @@ __global__ void k_tensor_gen(Launch L) {
   d.basis[e] = (float)val;
 }
 
-hipError_t launch_basis_gen(const Launch& L, hipStream_t s) {
-  const int C = L.C, NF = n_freq(C);
+// Covariance partials of one image (d.n_cov tiles from d.cov_part on).
+hipError_t launch_cov_gen(const Launch& L, hipStream_t s) {
+  const int NF = n_freq(L.C);
   const int nchunk = (NF + GEN_FC - 1) / GEN_FC;
   Launch Lc = L;
   Lc.total = L.one.n_cov * nchunk;
-  hipLaunchKernelGGL(k_cov_gen, dim3(Lc.total), dim3(64), cov_gen_lds_bytes(C), s, Lc);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (Lc.total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cov_gen, dim3(Lc.total), dim3(64), cov_gen_lds_bytes(L.C), s, Lc);
+  return hipGetLastError();
+}
+
+// Eigen-solves of the d.n_cov partials and the real tensors.
+hipError_t launch_eig_gen(const Launch& L, hipStream_t s) {
+  const int C = L.C, NF = n_freq(C);
   hipLaunchKernelGGL(k_eig_gen, dim3((2 * NF + GEN_EIG_M - 1) / GEN_EIG_M), dim3(128), 0, s, L);
-  e = hipGetLastError();
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_tensor_gen, dim3((2 * C * 64 + 255) / 256), dim3(256), 0, s, L);
   return hipGetLastError();
+}
+
+hipError_t launch_basis_gen(const Launch& L, hipStream_t s) {
+  const hipError_t e = launch_cov_gen(L, s);
+  return e != hipSuccess ? e : launch_eig_gen(L, s);
 }
 
 // Float Fourier slices of the float real tensors, FP64 sums:

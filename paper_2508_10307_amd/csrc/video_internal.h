@@ -1,0 +1,22 @@
+// Internal declarations of the video path (spatio-temporal search over the
+// frames stacked one above the other) and of the split band-count basis
+// launchers it uses.
+#pragma once
+#include "hts_internal.h"
+
+namespace hts {
+
+// Geometry of one frame of the sequence and the temporal reach.
+struct VideoGeo {
+  int32_t T, H, Hp, Wp, nry, nrx, n_ref_frame, dt;
+};
+
+constexpr int VIDEO_CAND_MAX = 4096;   // candidates per reference (12-bit ordinal in the key)
+
+hipError_t launch_stack(const float* frames, float* stacked, int T, int C, int H, int W,
+                        bool inverse, hipStream_t s);
+hipError_t launch_match_video(const Launch& L, const VideoGeo& v, hipStream_t s);
+hipError_t launch_cov_gen(const Launch& L, hipStream_t s);
+hipError_t launch_eig_gen(const Launch& L, hipStream_t s);
+
+}  // namespace hts

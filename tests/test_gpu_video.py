@@ -1,0 +1,87 @@
+"""GPU parity of the video path (hts_denoise_video, reading V1:
+spatio-temporal search over the stacked frames) with the FP64 oracle:
+match indices bit-exact, the basis within float rounding, the denoised
+frames within 1e-3 on the 0..255 scale under the GPU's keep-masks (the
+threshold-kink protocol of the image tests); zero temporal reach gives each
+frame's own image matches; repeated calls give the same bits."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import video as ovideo
+from paper_2508_10307_amd import api, synth
+
+pytestmark = pytest.mark.gpu
+
+PIX_TOL = 1e-3
+DELTA_REL = 2e-4
+CASES = [(3, 1, 24, 22, 3, 9, 8, 1), (4, 3, 20, 21, 3, 9, 16, 2), (2, 5, 18, 20, 2, 7, 8, 1),
+         (1, 3, 21, 23, 3, 9, 8, 2), (5, 1, 19, 18, 4, 11, 32, 1)]
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def T_(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev())
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def clip(Tn, C, H, W, seed, sigma=20.0):
+    return np.stack([synth.tiny(seed + t, C, H, W, sigma=sigma, n_blobs=4) for t in range(Tn)])
+
+
+@pytest.mark.parametrize("Tn,C,H,W,s,w,K,dt", CASES)
+def test_video_matches_oracle(Tn, C, H, W, s, w, K, dt):
+    sigma = 20.0
+    f = clip(Tn, C, H, W, 3000 + Tn * 10 + C, sigma)
+    p = api.Params(stride=s, window=w, K=K)
+    x = T_(f)
+    out, st = api.hts_denoise_video(x, sigma, p, dt=dt, save=True)
+    out2 = api.hts_denoise_video(x, sigma, p, dt=dt)
+    assert torch.equal(out, out2)
+    idx = st["idx"].cpu().numpy().astype(np.int64)
+    idx_o, _ = ovideo.match(f.astype(np.float64), 8, s, w, K, dt)
+    np.testing.assert_array_equal(idx, idx_o)
+    _, _, Uo, Vo, _, _ = ovideo.global_basis(f.astype(np.float64), 8, s)
+    np.testing.assert_allclose(st["U"].cpu().numpy(), Uo, atol=2e-6)
+    np.testing.assert_allclose(st["V"].cpu().numpy(), Vo, atol=2e-6)
+    from oracle import pipeline as opipe
+    masks = opipe.unpack_masks(st["masks"].cpu().numpy().view(np.uint32), len(idx), K, C)
+    r = ovideo.denoise(f, sigma, 8, s, w, K, dt, p.tau_mult, idx=idx, U=st["U"].cpu().numpy(),
+                       V=st["V"].cpu().numpy(), mask=masks)
+    tau = p.tau_mult * sigma
+    log(f"T{Tn} C{C} {H}x{W} K{K} dt{dt}: overrides {r['n_override']}, "
+        f"max margin {r['max_override_margin']:.3e}")
+    assert r["max_override_margin"] <= DELTA_REL * max(tau, 1.0)
+    err = np.abs(out.cpu().numpy() - r["out"]).max()
+    log(f"  max |gpu - oracle| = {err:.3e}")
+    assert err <= PIX_TOL
+    np.testing.assert_array_equal(st["cnt"].cpu().numpy(), r["cnt"])
+
+
+def test_zero_reach_gives_each_frames_image_matches():
+    f = clip(3, 3, 26, 24, 3100)
+    p = api.Params(stride=3, window=11, K=16)
+    _, st = api.hts_denoise_video(T_(f), 15.0, p, dt=0, save=True)
+    idx = st["idx"].cpu().numpy()
+    n = len(idx) // 3
+    for t in range(3):
+        own = api.hts_match(T_(f[t]), p).cpu().numpy()
+        np.testing.assert_array_equal(idx[t * n:(t + 1) * n], own + t * 26 * 24)
+
+
+def test_video_refuses_unbuilt_configurations():
+    f = T_(clip(2, 1, 24, 24, 3200))
+    with pytest.raises(api.L.HtsError):
+        api.hts_denoise_video(f, 10.0, api.Params(stride=3, window=21, K=64))
+    f3 = T_(clip(3, 1, 40, 40, 3201))   # 5 frames x 31^2 candidates > 4096
+    with pytest.raises(api.L.HtsError):
+        api.hts_denoise_video(f3, 10.0, api.Params(stride=3, window=31, K=16), dt=2)
+    with pytest.raises(api.L.HtsError):
+        api.hts_denoise_video(f, 10.0, api.Params(stride=3, window=9, K=8,
+                                                  flags=api.L.HTS_FLAG_WEIGHTED))

@@ -37,8 +37,8 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-path comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adaptive", action="store_true",
-                    help="skip the A-Haar-tSVD, weighted-aggregation, Fourier-threshold and "
-                         "spectral-tube timings")
+                    help="skip the A-Haar-tSVD, weighted-aggregation, Fourier-threshold, "
+                         "spectral-tube and video timings")
     ap.add_argument("--batch-api", type=int, default=1,
                     help="1: hts_denoise_batch (one graph); 0: one hts_denoise per image")
     ap.add_argument("--tune", type=int, default=0)
@@ -306,6 +306,29 @@ def main():
                  "psnr_db": round(10 * np.log10(255.0 ** 2 / mse_t), 4)}
         del ws_t, xt
 
+    # ---- video: 8 synthetic 540 x 960 RGB frames (the frame size of the
+    # paper's Set8 clips), AWGN sigma = 25, spatio-temporal search over
+    # frames t-2..t+2, K = 32, w = 21 ----
+    vid = None
+    if not args.no_adaptive:
+        from paper_2508_10307_amd import synth
+        Tv, Hv, Wv = 8, 540, 960
+        clean_v = np.stack([synth.clean_image(4343, t, 3, Hv, Wv, 40) for t in range(Tv)])
+        xv = torch.from_numpy(np.stack([synth.add_awgn(4343, t, clean_v[t], 25.0)
+                                        for t in range(Tv)])).to(dev)
+        pv = api.Params(stride=3, window=21, K=32, tau_mult=q.tau_mult)
+        res_v = {}
+
+        def run_v():
+            res_v["o"] = api.hts_denoise_video(xv, 25.0, pv, dt=2)
+
+        msv = timed(run_v, 2, 1)
+        mse_v = float(((res_v["o"].double().cpu().numpy() - clean_v) ** 2).mean())
+        vid = {"value": round(Tv * Hv * Wv / 1e6 / (msv / 1e3), 3), "unit": "MPix/s",
+               "ms_per_clip": round(msv, 3), "shape": [Tv, 3, Hv, Wv], "dt": 2,
+               "psnr_db": round(10 * np.log10(255.0 ** 2 / mse_v), 4)}
+        del xv
+
     # ---- roofline of the dominant kernel: the fused filter, timed live ----
     # One eager launch per image (the same filter the batched graph runs, as
     # its single-image instantiation), timed with HIP events on its stream:
@@ -391,6 +414,7 @@ def main():
         "weighted": weighted,
         "fourier_threshold": fourier,
         "spectral_tubes": tubes,
+        "video": vid,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

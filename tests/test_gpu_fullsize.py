@@ -1,0 +1,130 @@
+"""Parity at full size, in the launch configuration bench.py times: the
+64-image mixed-size RGB batch through hts_denoise_batch (s3 w31 K32, the
+autotuned schedule), checked against the FP64 oracle on samples it can
+compute one by one:
+  * sampled references of three images (the largest, a middle and a small
+    one): the exact top-K of the brute-force window scan;
+  * the FP64 basis of those images;
+  * sampled output pixels: every group with a patch over the pixel is
+    filtered by the oracle (Eq. 18-20 under the GPU's keep-masks, the
+    threshold-kink protocol of the small tests, GPU float basis) and
+    averaged (Eq. 2); the pixel must agree within 1e-3.
+The batch output of each image equals its single-image hts_denoise bit for
+bit (the bench's timed path is the batched one)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import basis as obasis
+from oracle import filtering as of
+from oracle import matching as omatch
+from oracle.grid import ref_grid
+from paper_2508_10307_amd import api, synth
+
+pytestmark = pytest.mark.gpu
+
+PIX_TOL = 1e-3
+DELTA_REL = 2e-4
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def group_masks(words, g, K, C):
+    """Keep-masks of group g from the bit-packed stream, bool [K, C, 8, 8]."""
+    n = K * C * 2
+    w = np.ascontiguousarray(words[g * n:(g + 1) * n], dtype="<u4")
+    bits = np.unpackbits(w.view(np.uint8), bitorder="little")
+    return bits.astype(bool).reshape(K, C, 8, 8)
+
+
+@pytest.fixture(scope="module")
+def batch():
+    wl = synth.batch64()
+    q = wl.params
+    xs = [torch.from_numpy(im.noisy).to(dev()) for im in wl.images]
+    # the schedule bench.py picks: the autotuner on the largest image shape
+    th, tw = max(x.shape[1] for x in xs), max(x.shape[2] for x in xs)
+    tune = api.hts_autotune(api.Params(stride=q.stride, window=q.window, K=q.K,
+                                       tau_mult=q.tau_mult), 3, th, tw)
+    log("autotuned schedule", tune)
+    p = api.Params(stride=q.stride, window=q.window, K=q.K, tau_mult=q.tau_mult, tune=tune)
+    sig = [im.sigma for im in wl.images]
+    outs = api.hts_denoise_batch(xs, sig, p)
+    torch.cuda.synchronize()
+    return wl, p, xs, sig, outs
+
+
+def picks(wl):
+    areas = [im.noisy.shape[1] * im.noisy.shape[2] for im in wl.images]
+    order = np.argsort(areas, kind="stable")
+    return [int(order[-1]), int(order[len(order) // 2]), int(order[0])]
+
+
+def test_fullsize_batch_samples_match_the_oracle(batch):
+    wl, p, xs, sig, outs = batch
+    rng = np.random.default_rng(11)
+    K, s, w = p.K, p.stride, p.window
+    r = (w - 1) // 2
+    for i in picks(wl):
+        y = wl.images[i].noisy
+        C, H, W = y.shape
+        log(f"image {i}: {H}x{W}, sigma {sig[i]:.2f}")
+        out1, st = api.hts_denoise(xs[i], sig[i], p, save=True)
+        assert torch.equal(out1, outs[i])
+        idx = st["idx"].cpu().numpy().astype(np.int64)
+        words = st["masks"].cpu().numpy().view(np.uint32)
+        # sampled references: brute-force window scan
+        ys, xs_, _, _ = ref_grid(H, W, 8, s)
+        qg = omatch.quantize(y)
+        planes = omatch.guide_planes(qg)
+        green = omatch.gcp_green(qg, ys, xs_, 8, p.gcp_num, p.gcp_den)
+        Hp, Wp = H - 7, W - 7
+        for n in rng.choice(len(ys), 40, replace=False):
+            ry, rx = int(ys[n]), int(xs_[n])
+            pl = planes[0 if green[n] else 1]
+            ref = pl[ry:ry + 8, rx:rx + 8]
+            c = []
+            for cy in range(max(0, ry - r), min(Hp - 1, ry + r) + 1):
+                for cx in range(max(0, rx - r), min(Wp - 1, rx + r) + 1):
+                    if (cy, cx) != (ry, rx):
+                        c.append((int(((pl[cy:cy + 8, cx:cx + 8] - ref) ** 2).sum()), cy * W + cx))
+            c.sort()
+            assert list(idx[n]) == [ry * W + rx] + [v for _, v in c[:K - 1]], (i, n)
+        # FP64 basis
+        _, _, U64, V64, _ = api.hts_basis(xs[i], p, want_fp64=True)
+        _, _, Uo, Vo, _, _ = obasis.global_basis(y.astype(np.float64), 8, s)
+        np.testing.assert_allclose(U64.cpu().numpy(), Uo, atol=1e-9)
+        np.testing.assert_allclose(V64.cpu().numpy(), Vo, atol=1e-9)
+        # sampled output pixels
+        UF = obasis.fourier_from_real(st["U"].cpu().numpy().astype(np.float64))
+        VF = obasis.fourier_from_real(st["V"].cpu().numpy().astype(np.float64))
+        tau = p.tau_mult * sig[i]
+        py, px = np.divmod(idx, W)
+        out = outs[i].cpu().numpy()
+        for _ in range(4):
+            yy, xx = int(rng.integers(0, H)), int(rng.integers(0, W))
+            cover = (py <= yy) & (yy < py + 8) & (px <= xx) & (xx < px + 8)
+            gs = np.nonzero(cover.any(axis=1))[0]
+            G = of.gather_groups(y.astype(np.float64), idx[gs], 8)
+            S = of.haar_group(of.tsvd_forward(G, UF, VF), K)
+            M = np.stack([group_masks(words, int(g), K, C) for g in gs])
+            keep = np.abs(S) >= tau
+            diff = M != keep
+            if diff.any():
+                assert np.abs(np.abs(S[diff]) - tau).max() <= DELTA_REL * max(tau, 1.0)
+            est = of.tsvd_inverse(of.haar_group_inverse(np.where(M, S, 0.0), K), UF, VF)
+            num = np.zeros(C)
+            cnt = 0
+            for gi, g in enumerate(gs):
+                for k in np.nonzero(cover[g])[0]:
+                    num += est[gi, k, :, yy - py[g, k], xx - px[g, k]]
+                    cnt += 1
+            err = np.abs(out[:, yy, xx] - num / cnt).max()
+            log(f"  pixel ({yy},{xx}): {len(gs)} groups, {cnt} estimates, |gpu - oracle| = {err:.2e}")
+            assert err <= PIX_TOL

@@ -269,8 +269,11 @@ hts_status run_count(const hts_params* p, int C, const Schedule& sc, const ImgDe
 hts_status run_filter(const hts_params* p, int C, const Schedule& sc, ImgDesc d, int adjoint,
                       hipStream_t s, const float* U = nullptr, const float* V = nullptr,
                       bool hist_ready = false) {
-  if (general_c(C)) {   // the spectral-tube filter: fixed-point numerator, own basis only
-    if (adjoint || U || V || !d.num64) return HTS_ERR_UNSUPPORTED;
+  if (general_c(C)) {   // the spectral-tube filter
+    if (adjoint) return HTS_ERR_UNSUPPORTED;
+    const size_t nb = (size_t)C * PS2 * sizeof(float);
+    if (U) HIPCHK(hipMemcpyAsync(d.basis, U, nb, hipMemcpyDeviceToDevice, s));
+    if (V) HIPCHK(hipMemcpyAsync(d.basis + C * PS2, V, nb, hipMemcpyDeviceToDevice, s));
     HIPCHK(launch_fbasis_gen(make_launch(p, C, d, -1, sc.fty, sc.ftx), s));
     HIPCHK(launch_filter_gen(make_launch(p, C, d, W_FILT, sc.fty, sc.ftx),
                              std::min(d.ref_count, GEN_GRID), s));
@@ -594,7 +597,6 @@ hts_status hts_filter(const hts_params* p, const float* noisy, int32_t C, int32_
   Geo g;
   hts_status st = make_geo(p, C, H, W, g);
   if (st != HTS_OK) return st;
-  if (general_c(C)) return HTS_ERR_UNSUPPORTED;   // spectral tubes: hts_denoise, hts_match, hts_basis
   if (!noisy || !idx || !U || !V || !ws) return HTS_ERR_INVALID;
   if ((num == nullptr) != (cnt == nullptr)) return HTS_ERR_INVALID;
   if (!(sigma >= 0.f) || !std::isfinite(sigma)) return HTS_ERR_INVALID;

@@ -18,7 +18,8 @@
 //                  tile), the real core tensor by the inverse DFT into the
 //                  work group's scratch, Haar along the group and the hard
 //                  threshold per channel, then the inverse, aggregated in
-//                  fixed point (Eq. 2).
+//                  fixed point (Eq. 2; float atomics into a float numerator
+//                  for hts_filter), optional per-group estimates.
 //
 // Twiddles come from sincospi (exact at the quarter points).
 #include "jacobi8.h"
@@ -434,8 +435,12 @@ __global__ __launch_bounds__(64) void k_filter_gen(Launch L) {
           }
       }
       if (__ballot(bad)) break;
-      for (int j = 0; j < C; ++j)
-        atomicAdd(d.num64 + (size_t)j * HW + pix, fx_from_float(S[((size_t)k * C + j) * 64 + lane] * fxs));
+      for (int j = 0; j < C; ++j) {
+        const float t = S[((size_t)k * C + j) * 64 + lane];
+        if (d.num64) atomicAdd(d.num64 + (size_t)j * HW + pix, fx_from_float(t * fxs));
+        else atomicAdd(d.num + (size_t)j * HW + pix, t * fxs);   // fxs = 1 / c here
+        if (d.group_est) d.group_est[(((size_t)gl * K + k) * C + j) * PS2 + lane] = t * (1.0f / (float)C);
+      }
     }
     if (__ballot(bad)) poison_group(d, gi, gl, K, C, rW, lane);
   }

@@ -132,3 +132,36 @@ def test_band_count_entry_points_refuse_unbuilt_calls():
         api.hts_denoise_backward(T(np.ones_like(y)), st, p)
     with pytest.raises(api.L.HtsError):
         api.hts_denoise(x, 10.0, api.Params(stride=3, window=9, K=8, flags=api.L.HTS_FLAG_WEIGHTED))
+
+
+def test_filter_entry_point_for_band_counts():
+    """hts_filter over two reference ranges adds the same numerator and
+    counts as hts_denoise forms (float atomics: within 1e-3 after the
+    division); its per-group estimates equal the oracle's for the GPU's
+    masks and basis."""
+    C, H, W, s, w, K = 6, 30, 28, 3, 9, 8
+    sigma = 18.0
+    y = tube(C, H, W, 2600, sigma)
+    p = api.Params(stride=s, window=w, K=K)
+    x = T(y)
+    out, st = api.hts_denoise(x, sigma, p, save=True)
+    n_ref = st["idx"].shape[0]
+    half = n_ref // 2
+    a = api.hts_filter(x, sigma, st["idx"], st["U"], st["V"], p, 0, half, want_group_est=True,
+                       want_masks=True)
+    b = api.hts_filter(x, sigma, st["idx"], st["U"], st["V"], p, half, n_ref - half)
+    num = (a["num"] + b["num"]).cpu().numpy()
+    cnt = (a["cnt"] + b["cnt"]).cpu().numpy()
+    np.testing.assert_array_equal(cnt, st["cnt"].cpu().numpy())
+    assert np.abs(num / cnt[None] - out.cpu().numpy()).max() <= PIX_TOL
+    idx = st["idx"].cpu().numpy().astype(np.int64)
+    masks = opipe.unpack_masks(a["masks"].cpu().numpy().view(np.uint32), half, K, C)
+    from oracle import basis as ob, filtering as of
+    UF = ob.fourier_from_real(st["U"].cpu().numpy().astype(np.float64))
+    VF = ob.fourier_from_real(st["V"].cpu().numpy().astype(np.float64))
+    S = of.haar_group(of.tsvd_forward(of.gather_groups(y.astype(np.float64), idx[:half], 8),
+                                      UF, VF), K)
+    est = of.tsvd_inverse(of.haar_group_inverse(np.where(masks, S, 0.0), K), UF, VF)
+    err = np.abs(a["group_est"].cpu().numpy() - est).max()
+    log(f"group estimates: max |gpu - oracle| = {err:.3e}")
+    assert err <= PIX_TOL

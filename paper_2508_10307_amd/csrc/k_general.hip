@@ -285,21 +285,41 @@ __global__ __launch_bounds__(64) void k_filter_gen(Launch L) {
     tw[m] = make_float2((float)cs, (float)-sn);
   }
   __syncthreads();
-  // X(f) <- DFT of the lane's band values (in Y), f < NF; four frequencies
-  // per pass over the bands (twiddle index m_f = f j mod c, kept by adding f)
+  // Bands j and c - j share their cosines and have opposite sines, so the
+  // DFTs below work on pairs: JH = floor((c - 1) / 2) pairs, band 0 and, for
+  // even c, band c/2 on their own.
+  const int JH = (C - 1) / 2;
+  const bool even = (C & 1) == 0;
+  // X(f) <- DFT of the lane's band values (in Y), f < NF:
+  //   X(f) = x_0 + sum_{j <= JH} [(x_j + x_{c-j}) cos - i (x_j - x_{c-j}) sin](2 pi f j / c)
+  //          (+ (-1)^f x_{c/2});
+  // the band values are first turned into the pair sums (j) and differences
+  // (c - j) in place; four frequencies per pass (m_f = f j mod c, kept by
+  // adding f).
   auto dft_bands = [&]() {
+    for (int j = 1; j <= JH; ++j) {
+      const float u = Yb[j * 64 + lane], w = Yb[(C - j) * 64 + lane];
+      Yb[j * 64 + lane] = u + w;
+      Yb[(C - j) * 64 + lane] = u - w;
+    }
+    const float x0 = Yb[lane], xh = even ? Yb[(C / 2) * 64 + lane] : 0.f;
     for (int f0 = 0; f0 < NF; f0 += 4) {
-      float xr[4] = {0.f, 0.f, 0.f, 0.f}, xi[4] = {0.f, 0.f, 0.f, 0.f};
-      int m[4] = {0, 0, 0, 0};
-      for (int j = 0; j < C; ++j) {
-        const float v = Yb[j * 64 + lane];
+      float xr[4], xi[4] = {0.f, 0.f, 0.f, 0.f};
+      int m[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        xr[u] = x0 + (((f0 + u) & 1) ? -xh : xh);
+        m[u] = 0;
+      }
+      for (int j = 1; j <= JH; ++j) {
+        const float sj = Yb[j * 64 + lane], dj = Yb[(C - j) * 64 + lane];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const float2 w = tw[m[u]];
-          xr[u] = fmaf(v, w.x, xr[u]);
-          xi[u] = fmaf(v, w.y, xi[u]);
           m[u] += f0 + u;
           m[u] -= m[u] >= C ? C : 0;
+          const float2 w = tw[m[u]];
+          xr[u] = fmaf(sj, w.x, xr[u]);
+          xi[u] = fmaf(dj, w.y, xi[u]);
         }
       }
 #pragma unroll
@@ -307,26 +327,43 @@ __global__ __launch_bounds__(64) void k_filter_gen(Launch L) {
         if (f0 + u < NF) X[(f0 + u) * 64 + lane] = make_float2(xr[u], xi[u]);
     }
   };
-  // bands j0..j0+3 of c x the (1/c) IDFT of the lane's X(f), f < NF
-  auto idft_bands4 = [&](int j0, float* t) {
-    int m[4];
+  // c x the (1/c) IDFT of the lane's X(f), f < NF, scaled by sc, into band
+  // j of dst (stride 64 floats): with A_j = sum_f w_f Re X(f) cos and
+  // B_j = -sum_f w_f Im X(f) sin (w_f = 2, 1 at f = c/2),
+  // t_j = X(0) + A_j + B_j and t_{c-j} = X(0) + A_j - B_j; four pairs per pass.
+  auto idft_bands = [&](float* dst, float sc) {
     const float x0 = X[lane].x;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      t[u] = x0;
-      m[u] = min(j0 + u, C - 1);
-    }
+    float t0 = x0, th = x0;
     for (int f = 1; f < NF; ++f) {
       const float w = 2 * f == C ? 1.f : 2.f;
-      const float2 z = X[f * 64 + lane];
-      const float zr = w * z.x, zi = w * z.y;
+      const float zr = w * X[f * 64 + lane].x;
+      t0 += zr;
+      th += (f & 1) ? -zr : zr;
+    }
+    dst[lane] = t0 * sc;
+    if (even) dst[(C / 2) * 64 + lane] = th * sc;
+    for (int j0 = 1; j0 <= JH; j0 += 4) {
+      float A[4] = {0.f, 0.f, 0.f, 0.f}, B[4] = {0.f, 0.f, 0.f, 0.f};
+      int m[4] = {0, 0, 0, 0};
+      for (int f = 1; f < NF; ++f) {
+        const float w = 2 * f == C ? 1.f : 2.f;
+        const float2 z = X[f * 64 + lane];
+        const float zr = w * z.x, zi = w * z.y;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const float2 e = tw[m[u]];
-        t[u] += zr * e.x + zi * e.y;
-        m[u] += j0 + u;
-        m[u] -= m[u] >= C ? C : 0;
+        for (int u = 0; u < 4; ++u) {
+          m[u] += j0 + u;
+          m[u] -= m[u] >= C ? C : 0;
+          const float2 e = tw[m[u]];
+          A[u] = fmaf(zr, e.x, A[u]);
+          B[u] = fmaf(zi, e.y, B[u]);
+        }
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (j0 + u <= JH) {
+          dst[(j0 + u) * 64 + lane] = (x0 + A[u] + B[u]) * sc;
+          dst[(C - j0 - u) * 64 + lane] = (x0 + A[u] - B[u]) * sc;
+        }
     }
   };
   // X(f) <- U_F(f)^H X(f) V_F(f) (forward) or U_F(f) X(f) V_F(f)^H (inverse)
@@ -381,13 +418,7 @@ __global__ __launch_bounds__(64) void k_filter_gen(Launch L) {
       }
       dft_bands();
       products(false);
-      for (int j0 = 0; j0 < C; j0 += 4) {
-        float t[4];
-        idft_bands4(j0, t);
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (j0 + u < C) S[((size_t)k * C + j0 + u) * 64 + lane] = t[u] * (1.0f / (float)C);
-      }
+      idft_bands(S + (size_t)k * C * 64, 1.0f / (float)C);
     }
     // Haar along the group, hard threshold (Eq. 19), inverse; per band
     for (int j = 0; j < C; ++j) {
@@ -424,16 +455,8 @@ __global__ __launch_bounds__(64) void k_filter_gen(Launch L) {
       dft_bands();
       products(true);
       // c x the estimate (the 1/c is in fxs), parked in the slot's scratch
-      for (int j0 = 0; j0 < C; j0 += 4) {
-        float t[4];
-        idft_bands4(j0, t);
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (j0 + u < C) {
-            bad |= !isfinite(t[u]);
-            S[((size_t)k * C + j0 + u) * 64 + lane] = t[u];
-          }
-      }
+      idft_bands(S + (size_t)k * C * 64, 1.f);
+      for (int j = 0; j < C; ++j) bad |= !isfinite(S[((size_t)k * C + j) * 64 + lane]);
       if (__ballot(bad)) break;
       for (int j = 0; j < C; ++j) {
         const float t = S[((size_t)k * C + j) * 64 + lane];

@@ -16,9 +16,9 @@
  *    C is 1 (grey), 3 (RGB) or, for the spectral tubes of HSI (Sec. IV: a
  *    ps x ps x N_bands patch, other parameters unchanged), 2 and 4..256 with
  *    K <= 32 and no flags; ps must be 8.  The band counts other than 1 and 3
- *    run through hts_denoise, hts_match, hts_basis, hts_filter and
- *    hts_denoise_video (the other entry points return HTS_ERR_UNSUPPORTED
- *    for them).
+ *    run through hts_denoise, hts_match, hts_basis, hts_filter,
+ *    hts_denoise_backward and hts_denoise_video (the other entry points
+ *    return HTS_ERR_UNSUPPORTED for them).
  *  - Reference grid: top-left corners 0, s, 2s, ... along each axis plus the
  *    last valid position H-ps (resp. W-ps); references are numbered
  *    row-major over that grid (n_ref = n_ref_y * n_ref_x).

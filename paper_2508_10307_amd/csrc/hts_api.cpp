@@ -270,13 +270,14 @@ hts_status run_filter(const hts_params* p, int C, const Schedule& sc, ImgDesc d,
                       hipStream_t s, const float* U = nullptr, const float* V = nullptr,
                       bool hist_ready = false) {
   if (general_c(C)) {   // the spectral-tube filter
-    if (adjoint) return HTS_ERR_UNSUPPORTED;
     const size_t nb = (size_t)C * PS2 * sizeof(float);
     if (U) HIPCHK(hipMemcpyAsync(d.basis, U, nb, hipMemcpyDeviceToDevice, s));
     if (V) HIPCHK(hipMemcpyAsync(d.basis + C * PS2, V, nb, hipMemcpyDeviceToDevice, s));
     HIPCHK(launch_fbasis_gen(make_launch(p, C, d, -1, sc.fty, sc.ftx), s));
-    HIPCHK(launch_filter_gen(make_launch(p, C, d, W_FILT, sc.fty, sc.ftx),
-                             std::min(d.ref_count, GEN_GRID), s));
+    const Launch Lf = make_launch(p, C, d, W_FILT, sc.fty, sc.ftx);
+    const int gg = std::min(d.ref_count, GEN_GRID);
+    if (adjoint) HIPCHK(launch_filter_gen_adj(Lf, gg, s));
+    else HIPCHK(launch_filter_gen(Lf, gg, s));
     if (d.cnt) return run_count(p, C, sc, d, hist_ready, s);
     return HTS_OK;
   }
@@ -725,7 +726,6 @@ hts_status hts_denoise_backward(const hts_params* p, const float* grad_out, cons
   Geo g;
   hts_status st = make_geo(p, C, H, W, g);
   if (st != HTS_OK) return st;
-  if (general_c(C)) return HTS_ERR_UNSUPPORTED;   // spectral tubes: hts_denoise, hts_match, hts_basis
   if (weighted(p)) return HTS_ERR_UNSUPPORTED;   // adjoint of the uniform average only
   if (fourier(p, C)) return HTS_ERR_UNSUPPORTED;  // masks of the real-domain threshold only
   if (!grad_out || !idx || !masks || !U || !V || !cnt || !grad_in || !ws) return HTS_ERR_INVALID;

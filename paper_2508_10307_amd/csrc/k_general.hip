@@ -13,7 +13,9 @@
 //                  first on ties), into ufg and the eigenvalues;
 //  k_tensor_gen    U(:,:,j) = (1/c) sum_f U_F(f) e^{2 pi i f j / c}, real;
 //  k_fbasis_gen    float Fourier slices U_F(f) of the (float) real tensors;
-//  k_filter_gen    Eq. 18-20 per group: per slot and frequency
+//  k_filter_gen    Eq. 18-20 per group (or, with ADJ, the transpose of the
+//                  frozen-mask map: the forward masks replace Eq. 19):
+//                  per slot and frequency
 //                  Z(f) = U_F^H P^(f) V_F (8x8 products through an LDS
 //                  tile), the real core tensor by the inverse DFT into the
 //                  work group's scratch, Haar along the group and the hard
@@ -263,7 +265,7 @@ size_t filter_gen_lds_bytes(int C) {
 // -> U_F(f)^H Y(f) (or U_F(f) Y(f)) back into X(f).  Complex values and
 // twiddles are float2 (one LDS access per complex operand); the lane's band
 // values are parked in the Y area while the DFT reads them.
-template <int K>
+template <int K, int ADJ>
 __global__ __launch_bounds__(64) void k_filter_gen(Launch L) {
   extern __shared__ float2 fsm2[];
   const int C = L.C, NF = n_freq(C);
@@ -428,9 +430,15 @@ __global__ __launch_bounds__(64) void k_filter_gen(Launch L) {
       haar_forward_slots<K, 1>(x);
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const bool keep = fabsf(x[k][0]) >= tau;
+        bool keep;
+        if (ADJ) {   // the frozen mask of the forward pass
+          const size_t word = ((size_t)gl * K + haar_slot_row(k, K)) * C + j;
+          keep = (d.masks_in[2 * word + (lane >> 5)] >> (lane & 31)) & 1u;
+        } else {
+          keep = fabsf(x[k][0]) >= tau;
+        }
         x[k][0] = keep ? x[k][0] : 0.f;
-        if (d.masks) {
+        if (!ADJ && d.masks) {
           const unsigned long long bal = __ballot(keep);
           if (lane == 0) {
             const size_t word = ((size_t)gl * K + haar_slot_row(k, K)) * C + j;
@@ -469,18 +477,27 @@ __global__ __launch_bounds__(64) void k_filter_gen(Launch L) {
   }
 }
 
-hipError_t launch_filter_gen(const Launch& L, int grid, hipStream_t s) {
+template <int ADJ>
+static hipError_t launch_fg(const Launch& L, int grid, hipStream_t s) {
   const size_t lds = filter_gen_lds_bytes(L.C);
   const int g = grid > 0 ? grid : 1;
   switch (L.K) {
-    case 2: hipLaunchKernelGGL(k_filter_gen<2>, dim3(g), dim3(64), lds, s, L); break;
-    case 4: hipLaunchKernelGGL(k_filter_gen<4>, dim3(g), dim3(64), lds, s, L); break;
-    case 8: hipLaunchKernelGGL(k_filter_gen<8>, dim3(g), dim3(64), lds, s, L); break;
-    case 16: hipLaunchKernelGGL(k_filter_gen<16>, dim3(g), dim3(64), lds, s, L); break;
-    case 32: hipLaunchKernelGGL(k_filter_gen<32>, dim3(g), dim3(64), lds, s, L); break;
+    case 2: hipLaunchKernelGGL((k_filter_gen<2, ADJ>), dim3(g), dim3(64), lds, s, L); break;
+    case 4: hipLaunchKernelGGL((k_filter_gen<4, ADJ>), dim3(g), dim3(64), lds, s, L); break;
+    case 8: hipLaunchKernelGGL((k_filter_gen<8, ADJ>), dim3(g), dim3(64), lds, s, L); break;
+    case 16: hipLaunchKernelGGL((k_filter_gen<16, ADJ>), dim3(g), dim3(64), lds, s, L); break;
+    case 32: hipLaunchKernelGGL((k_filter_gen<32, ADJ>), dim3(g), dim3(64), lds, s, L); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_filter_gen(const Launch& L, int grid, hipStream_t s) { return launch_fg<0>(L, grid, s); }
+
+// The transpose of the frozen-mask map (the adjoint): the masks of the
+// forward pass (d.masks_in) replace the threshold.
+hipError_t launch_filter_gen_adj(const Launch& L, int grid, hipStream_t s) {
+  return launch_fg<1>(L, grid, s);
 }
 
 }  // namespace hts

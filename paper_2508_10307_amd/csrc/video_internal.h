@@ -1,6 +1,6 @@
 // Internal declarations of the video path (spatio-temporal search over the
-// frames stacked one above the other) and of the split band-count basis
-// launchers it uses.
+// frames stacked one above the other), of the split band-count basis
+// launchers it uses, and of the band-count adjoint filter.
 #pragma once
 #include "hts_internal.h"
 
@@ -18,5 +18,6 @@ hipError_t launch_stack(const float* frames, float* stacked, int T, int C, int H
 hipError_t launch_match_video(const Launch& L, const VideoGeo& v, hipStream_t s);
 hipError_t launch_cov_gen(const Launch& L, hipStream_t s);
 hipError_t launch_eig_gen(const Launch& L, hipStream_t s);
+hipError_t launch_filter_gen_adj(const Launch& L, int grid, hipStream_t s);
 
 }  // namespace hts

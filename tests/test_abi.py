@@ -140,13 +140,13 @@ def test_calls_reject_null_pointers_and_small_workspace(lib):
     assert lib.hts_denoise_backward_basis(ctypes.byref(wt), FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE,
                                           FAKE, 1, 64, 64, FAKE, FAKE, need,
                                           None) == L.HTS_ERR_UNSUPPORTED
-    # band counts other than 1 and 3: no batch or adjoint (hts_filter validates as usual)
+    # band counts other than 1 and 3: no batch (hts_filter and the adjoint validate as usual)
     assert lib.hts_workspace_size(bp, 5, 64, 64, ctypes.byref(n)) == L.HTS_OK
     need5 = n.value
     assert lib.hts_filter(bp, FAKE, 5, 64, 64, 25.0, None, FAKE, FAKE, 0, 4, FAKE, FAKE,
                           None, None, FAKE, need5, None) == L.HTS_ERR_INVALID
-    assert lib.hts_denoise_backward(bp, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, 5, 64, 64, FAKE, None,
-                                    FAKE, need5, None) == L.HTS_ERR_UNSUPPORTED
+    assert lib.hts_denoise_backward(bp, FAKE, None, FAKE, FAKE, FAKE, FAKE, 5, 64, 64, FAKE, None,
+                                    FAKE, need5, None) == L.HTS_ERR_INVALID
     imgs = (L.HtsImage * 1)(L.HtsImage(FAKE.value, FAKE.value, 5, 64, 64, 10.0))
     assert lib.hts_batch_workspace_size(bp, imgs, 1, ctypes.byref(n)) == L.HTS_ERR_UNSUPPORTED
     bad = api.Params(K=12).c()

@@ -129,8 +129,6 @@ def test_band_count_entry_points_refuse_unbuilt_calls():
     with pytest.raises(api.L.HtsError):
         api.hts_denoise_batch([x], [10.0], p)
     with pytest.raises(api.L.HtsError):
-        api.hts_denoise_backward(T(np.ones_like(y)), st, p)
-    with pytest.raises(api.L.HtsError):
         api.hts_denoise(x, 10.0, api.Params(stride=3, window=9, K=8, flags=api.L.HTS_FLAG_WEIGHTED))
 
 
@@ -165,3 +163,26 @@ def test_filter_entry_point_for_band_counts():
     err = np.abs(a["group_est"].cpu().numpy() - est).max()
     log(f"group estimates: max |gpu - oracle| = {err:.3e}")
     assert err <= PIX_TOL
+
+
+@pytest.mark.parametrize("C,K", [(5, 8), (2, 16)])
+def test_adjoint_for_band_counts_matches_oracle(C, K):
+    """hts_denoise_backward with band counts other than 1 and 3: the
+    transpose of the frozen-mask map against the oracle's frozen adjoint."""
+    from oracle import adjoint as oadj
+    H, W, s, w = 30, 29, 3, 11
+    y = tube(C, H, W, 2700 + C, 15.0)
+    p = api.Params(stride=s, window=w, K=K)
+    x = T(y)
+    _, st = api.hts_denoise(x, 15.0, p, save=True)
+    g = np.random.default_rng(C).normal(size=y.shape)
+    gin, gtau = api.hts_denoise_backward(T(g), st, p)
+    idx = st["idx"].cpu().numpy().astype(np.int64)
+    masks = opipe.unpack_masks(st["masks"].cpu().numpy().view(np.uint32), len(idx), K, C)
+    ref = oadj.frozen_adjoint(g, idx, masks, st["U"].cpu().numpy().astype(np.float64),
+                              st["V"].cpu().numpy().astype(np.float64),
+                              st["cnt"].cpu().numpy().astype(np.float64), K)
+    err = np.abs(gin.cpu().numpy() - ref).max()
+    log(f"C{C} K{K} adjoint: max |gpu - oracle| = {err:.3e}, max |oracle| = {np.abs(ref).max():.3e}")
+    assert err <= 1e-4 * max(1.0, np.abs(ref).max())
+    assert gtau.item() == 0.0

@@ -268,6 +268,20 @@ hts_status hts_denoise_video(const hts_params* p, const float* frames, int32_t T
                              int32_t* idx_out, uint32_t* masks_out, float* U_out, float* V_out,
                              float* cnt_out, void* ws, size_t ws_bytes, void* stream);
 
+/* Adjoint of hts_denoise_video with the grouping, masks, basis and counts
+ * of the forward pass frozen (the video counterpart of
+ * hts_denoise_backward): grad_in = Place Q^T M Q Gather (grad_out / cnt) over
+ * the stacked frames, Q = Haar along the group o t-SVD projection, M the
+ * frozen keep-mask.  grad_out, grad_in: device float32 [T][C][H][W]; idx,
+ * masks, U, V, cnt ([T H][W]) as hts_denoise_video returns them; the same
+ * dt, parameters and workspace size as the forward call.  Errors as
+ * hts_denoise_video, and HTS_ERR_INVALID for null pointers. */
+hts_status hts_denoise_video_backward(const hts_params* p, const float* grad_out, int32_t T,
+                                      int32_t C, int32_t H, int32_t W, int32_t dt,
+                                      const int32_t* idx, const uint32_t* masks, const float* U,
+                                      const float* V, const float* cnt, float* grad_in, void* ws,
+                                      size_t ws_bytes, void* stream);
+
 /* Workspace bytes for hts_denoise_batch over these n images (host array). */
 hts_status hts_batch_workspace_size(const hts_params* p, const hts_image* imgs, int32_t n,
                                     size_t* bytes);

@@ -70,6 +70,8 @@ SIGNATURES = {
                                          ctypes.POINTER(c_sz)]),
     "hts_denoise_video": (c_i32, [P, c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_f32, c_vp, c_vp,
                                   c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
+    "hts_denoise_video_backward": (c_i32, [P, c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_vp,
+                                           c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
     "hts_autotune": (c_i32, [P, c_i32, c_i32, c_i32, ctypes.c_char_p, ctypes.POINTER(c_i32),
                              c_vp, c_sz, c_vp]),
     "hts_status_string": (ctypes.c_char_p, [c_i32]),

@@ -419,6 +419,28 @@ def hts_denoise_video(frames: torch.Tensor, sigma: float, p: Params, dt: int = 1
     return (out, st) if save else out
 
 
+def hts_denoise_video_backward(grad_out: torch.Tensor, st, p: Params, dt: int = 1, ws=None):
+    """Adjoint of hts_denoise_video with the state st of the forward call
+    (save=True) frozen.  Returns grad_noisy [T, C, H, W]."""
+    g = grad_out.contiguous()
+    if g.dim() != 4 or not g.is_cuda or g.dtype != torch.float32:
+        raise ValueError("grad_out must be a float32 [T, C, H, W] tensor on the GPU")
+    T, C, H, W = g.shape
+    dev = g.device
+    pc = p.c()
+    if ws is None:
+        n = L.c_sz()
+        L.check("hts_video_workspace_size", L.load().hts_video_workspace_size(
+            ctypes.byref(pc), T, C, H, W, int(dt), ctypes.byref(n)))
+        ws = torch.empty(n.value, dtype=torch.uint8, device=dev)
+    gin = torch.empty_like(g)
+    L.check("hts_denoise_video_backward", L.load().hts_denoise_video_backward(
+        ctypes.byref(pc), _ptr(g), T, C, H, W, int(dt), _ptr(st["idx"]), _ptr(st["masks"]),
+        _ptr(st["U"]), _ptr(st["V"]), _ptr(st["cnt"]), _ptr(gin), _ptr(ws), ws.numel(),
+        _stream(dev)))
+    return gin
+
+
 class HaarTSVD(torch.autograd.Function):
     """Differentiable Haar-tSVD denoiser: forward = hts_denoise; backward =
     the hand-written adjoint kernel with match indices, threshold masks,

@@ -1162,4 +1162,65 @@ hts_status hts_denoise_video(const hts_params* p, const float* frames, int32_t T
   return HTS_OK;
 }
 
+hts_status hts_denoise_video_backward(const hts_params* p, const float* grad_out, int32_t T,
+                                      int32_t C, int32_t H, int32_t W, int32_t dt,
+                                      const int32_t* idx, const uint32_t* masks, const float* U,
+                                      const float* V, const float* cnt, float* grad_in, void* ws,
+                                      size_t ws_bytes, void* stream) {
+  VideoPlan vp;
+  hts_status st = plan_video(p, T, C, H, W, dt, vp);
+  if (st != HTS_OK) return st;
+  if (!grad_out || !idx || !masks || !U || !V || !cnt || !grad_in || !ws) return HTS_ERR_INVALID;
+  if (ws_bytes < vp.total) return HTS_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  char* b = (char*)ws;
+  const int TH = T * H;
+  ImgDesc d;
+  std::memset(&d, 0, sizeof(d));
+  d.img = (const float*)(b + vp.stacked);        // grad_out, stacked
+  d.num = (float*)(b + vp.sout);                 // r = grad_out / cnt, stacked
+  d.cnt = const_cast<float*>(cnt);
+  d.fb_count = (int32_t*)(b + vp.fb_count);
+  d.fxmax = (uint32_t*)(b + vp.fxmax);
+  d.H = TH; d.W = W; d.Hp = TH - PS + 1; d.Wp = W - PS + 1;
+  d.nry = vp.f.nry; d.nrx = vp.f.nrx; d.n_ref = vp.n_ref;
+  d.ref_begin = 0; d.ref_count = vp.n_ref;
+  d.wcnt[W_PIX] = (int)(((long long)TH * W + PIX_CHUNK - 1) / PIX_CHUNK);
+  auto LS = [&](const ImgDesc& dd, int kind) {
+    Launch L;
+    std::memset(&L, 0, sizeof(L));
+    L.one = dd;
+    L.n_img = 1;
+    L.total = kind >= 0 ? dd.wcnt[kind] : 1;
+    L.C = C; L.K = p->K; L.stride = p->stride; L.window = p->window;
+    L.tau_mult = p->tau_mult;
+    return L;
+  };
+  HIPCHK(launch_stack(grad_out, (float*)d.img, T, C, H, W, false, s));
+  HIPCHK(launch_reset_counters(LS(d, -1), s));
+  HIPCHK(launch_adjoint_prep(LS(d, W_PIX), 0, s));
+  // the transpose of the frozen-mask map on r, summed in fixed point
+  ImgDesc a = d;
+  a.img = d.num;
+  a.num = nullptr;
+  a.cnt = nullptr;
+  a.idx = const_cast<int32_t*>(idx);
+  a.masks_in = masks;
+  a.num64 = (unsigned long long*)(b + vp.num64);
+  a.poison = (uint8_t*)(b + vp.poison);
+  a.basis = (float*)(b + vp.basis);
+  a.fbasis = (float*)(b + vp.fbasis);
+  a.gscratch = (float*)(b + vp.gscratch);
+  a.out = (float*)(b + vp.stacked);              // grad_out is no longer needed
+  const size_t nb = (size_t)C * PS2 * sizeof(float);
+  HIPCHK(hipMemcpyAsync(a.basis, U, nb, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(a.basis + C * PS2, V, nb, hipMemcpyDeviceToDevice, s));
+  HIPCHK(launch_fbasis_gen(LS(a, -1), s));
+  HIPCHK(launch_zero_accum(LS(a, W_PIX), 0, s));
+  HIPCHK(launch_filter_gen_adj(LS(a, -1), vp.grid, s));
+  HIPCHK(launch_finalize(LS(a, W_PIX), 0, s));   // no cnt: the numerator itself
+  HIPCHK(launch_stack(grad_in, a.out, T, C, H, W, true, s));
+  return HTS_OK;
+}
+
 }  // extern "C"

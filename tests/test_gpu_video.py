@@ -85,3 +85,25 @@ def test_video_refuses_unbuilt_configurations():
     with pytest.raises(api.L.HtsError):
         api.hts_denoise_video(f, 10.0, api.Params(stride=3, window=9, K=8,
                                                   flags=api.L.HTS_FLAG_WEIGHTED))
+
+
+@pytest.mark.parametrize("Tn,C,K,dt", [(3, 3, 8, 1), (2, 1, 16, 1)])
+def test_video_adjoint_matches_oracle(Tn, C, K, dt):
+    """hts_denoise_video_backward: the transpose of the frozen-mask video map
+    against the oracle's frozen adjoint on the stacked frames."""
+    from oracle import adjoint as oadj
+    from oracle import pipeline as opipe
+    H, W = 22, 21
+    f = clip(Tn, C, H, W, 3300 + C)
+    p = api.Params(stride=3, window=9, K=K)
+    _, st = api.hts_denoise_video(T_(f), 15.0, p, dt=dt, save=True)
+    g = np.random.default_rng(Tn + C).normal(size=f.shape)
+    gin = api.hts_denoise_video_backward(T_(g), st, p, dt=dt).cpu().numpy()
+    idx = st["idx"].cpu().numpy().astype(np.int64)
+    masks = opipe.unpack_masks(st["masks"].cpu().numpy().view(np.uint32), len(idx), K, C)
+    ref = oadj.frozen_adjoint(ovideo.stack(g), idx, masks, st["U"].cpu().numpy().astype(np.float64),
+                              st["V"].cpu().numpy().astype(np.float64),
+                              st["cnt"].cpu().numpy().astype(np.float64), K)
+    err = np.abs(gin - ovideo.unstack(ref, Tn)).max()
+    log(f"T{Tn} C{C} K{K} video adjoint: max |gpu - oracle| = {err:.3e}")
+    assert err <= 1e-4 * max(1.0, np.abs(ref).max())

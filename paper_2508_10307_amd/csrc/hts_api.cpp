@@ -37,6 +37,15 @@ struct Geo {
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// Work groups of the band-count filter for n groups: each holds its own
+// scratch (K * C * 64 floats), kept within about 1 GB (at least one work
+// group per CU, at most GEN_GRID).
+int gen_filter_grid(int n, int K, int C) {
+  const size_t per = (size_t)K * C * 64 * 4;
+  const int cap = (int)std::max<size_t>(256, std::min<size_t>(GEN_GRID, ((size_t)1 << 30) / per));
+  return std::max(1, std::min(n, cap));
+}
+
 bool weighted(const hts_params* p) { return (p->flags & HTS_FLAG_WEIGHTED) != 0; }
 bool fourier(const hts_params* p, int C) { return C == 3 && (p->flags & HTS_FLAG_FOURIER_THRESHOLD) != 0; }
 
@@ -114,7 +123,7 @@ Carve carve(const Geo& g) {
   const bool gen = general_c(g.C);
   c.ufg = o; o += gen ? al((size_t)2 * n_freq(g.C) * 128 * 8) : 0;
   c.gscratch = o;
-  o += gen ? al((size_t)std::min(g.n_ref, GEN_GRID) * g.K * g.C * 64 * 4) : 0;
+  o += gen ? al((size_t)gen_filter_grid(g.n_ref, g.K, g.C) * g.K * g.C * 64 * 4) : 0;
   c.total = o;
   return c;
 }
@@ -275,7 +284,7 @@ hts_status run_filter(const hts_params* p, int C, const Schedule& sc, ImgDesc d,
     if (V) HIPCHK(hipMemcpyAsync(d.basis + C * PS2, V, nb, hipMemcpyDeviceToDevice, s));
     HIPCHK(launch_fbasis_gen(make_launch(p, C, d, -1, sc.fty, sc.ftx), s));
     const Launch Lf = make_launch(p, C, d, W_FILT, sc.fty, sc.ftx);
-    const int gg = std::min(d.ref_count, GEN_GRID);
+    const int gg = gen_filter_grid(d.ref_count, p->K, C);
     if (adjoint) HIPCHK(launch_filter_gen_adj(Lf, gg, s));
     else HIPCHK(launch_filter_gen(Lf, gg, s));
     if (d.cnt) return run_count(p, C, sc, d, hist_ready, s);
@@ -1038,7 +1047,7 @@ hts_status plan_video(const hts_params* p, int T, int C, int H, int W, int dt, V
   vp.n_ref = T * vp.f.n_ref;
   vp.np = C == 3 ? 2 : 1;
   vp.NF = n_freq(C);
-  vp.grid = std::min(vp.n_ref, GEN_GRID);
+  vp.grid = gen_filter_grid(vp.n_ref, p->K, C);
   vp.v = VideoGeo{T, H, vp.f.Hp, vp.f.Wp, vp.f.nry, vp.f.nrx, vp.f.n_ref, dt};
   size_t o = 0;
   vp.stacked = o; o += al((size_t)px * C * 4);

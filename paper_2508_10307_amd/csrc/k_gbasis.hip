@@ -50,9 +50,11 @@ __device__ inline void put(Tile& t, int lane, float re, float im) {
 template <int K, int C>
 __global__ __launch_bounds__(64) void k_gbasis_acc(Launch L, const float* g, double* partial) {
   constexpr int NF = C / 2 + 1;
-  __shared__ float lr[8][8], li[8][8];
-  __shared__ float core[2][K][C][64];   // T' and D per slot, per lane
+  // eight complex 8x8 tiles: the projections' X and Y, then the cotangent
+  // products' operands (the two uses never overlap)
   __shared__ Tile tl[8];
+  __shared__ float core[2][K][C][64];   // T' and D per slot, per lane
+  float (*PX)[2][64] = tl, (*PY)[2][64] = tl + 4;
   const int lane = threadIdx.x;
   const int a = lane >> 3, b = lane & 7;
   const ImgDesc& d = L.one;
@@ -73,15 +75,17 @@ __global__ __launch_bounds__(64) void k_gbasis_acc(Launch L, const float* g, dou
       px = min(max(px, 0), d.Wp - 1);
       const int pix = (py + a) * d.W + px + b;
       const float rc = 1.0f / d.cnt[pix];
+      float p[2][C], t[2][C];
 #pragma unroll
-      for (int which = 0; which < 2; ++which) {
-        float p[C], t[C];
+      for (int ch = 0; ch < C; ++ch) {
+        p[0][ch] = d.img[ch * HW + pix];
+        p[1][ch] = g[ch * HW + pix] * rc;
+      }
+      project_pair<C>(PX, PY, lane, fb, p, t);
 #pragma unroll
-        for (int ch = 0; ch < C; ++ch)
-          p[ch] = which == 0 ? d.img[ch * HW + pix] : g[ch * HW + pix] * rc;
-        project_patch<C>(lr, li, a, b, fb, p, t);
-#pragma unroll
-        for (int ch = 0; ch < C; ++ch) core[which][k][ch][lane] = t[ch];
+      for (int ch = 0; ch < C; ++ch) {
+        core[0][k][ch][lane] = t[0][ch];
+        core[1][k][ch][lane] = t[1][ch];
       }
     }
     // Haar along the group, frozen mask, inverse: T' and D (lane-private)
@@ -136,20 +140,20 @@ __global__ __launch_bounds__(64) void k_gbasis_acc(Launch L, const float* g, dou
         tp[ch] = core[0][k][ch][lane];
         dd[ch] = core[1][k][ch][lane];
       }
+      // channel DFT at f: X^(f) = sum_j X_j e^{-2 pi i f j / 3}
+      auto dft = [&](const float* x, int f, float& re, float& im) {
+        if (C == 1) { re = x[0]; im = 0.f; }
+        else if (f == 0) { re = x[0] + x[1] + x[2]; im = 0.f; }
+        else { re = x[0] - 0.5f * (x[1] + x[2]); im = (float)GP_SQ3_2 * (x[2] - x[1]); }
+      };
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
-        // channel DFT at f: X^(f) = sum_j X_j e^{-2 pi i f j / 3}
-        auto dft = [&](const float* x, float& re, float& im) {
-          if (C == 1) { re = x[0]; im = 0.f; }
-          else if (f == 0) { re = x[0] + x[1] + x[2]; im = 0.f; }
-          else { re = x[0] - 0.5f * (x[1] + x[2]); im = (float)GP_SQ3_2 * (x[2] - x[1]); }
-        };
         float rr, ri, pr, pi, tr_, ti, dr, di;
-        dft(r, rr, ri);
-        dft(p, pr, pi);
-        dft(tp, tr_, ti);
-        dft(dd, dr, di);
-        __syncthreads();
+        dft(r, f, rr, ri);
+        dft(p, f, pr, pi);
+        dft(tp, f, tr_, ti);
+        dft(dd, f, dr, di);
+        __syncthreads();   // the previous readers of the tiles are done
         put(tl[0], lane, rr, ri);   // R^
         put(tl[1], lane, pr, pi);   // P^
         put(tl[2], lane, tr_, ti);  // T'^

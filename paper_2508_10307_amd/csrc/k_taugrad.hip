@@ -8,7 +8,7 @@
 // (Eq. 18) and g = dL/dx_hat.
 //
 // One wavefront per work group, one group at a time; lane = patch element
-// (a, b).  The projection's row and column sums go through a small LDS tile;
+// (a, b).  The projections of y and r share LDS tiles and three barriers;
 // each lane's element of the K slots' real core tensors of y and of r (C*K
 // values each) is parked in LDS, then the Haar transform along the group
 // runs in the lane's registers.  Each group's sum (FP64, fixed butterfly across the
@@ -21,7 +21,7 @@ namespace hts {
 template <int K, int C>
 __global__ __launch_bounds__(64) void k_taugrad(Launch L, const float* g, double* partial,
                                                  float kappa) {
-  __shared__ float lr[8][8], li[8][8];
+  __shared__ float PX[4][2][64], PY[4][2][64];   // projection tiles
   __shared__ float core[2][K][C][64];   // real core tensors of y and r, per lane
   const int lane = threadIdx.x;
   const int a = lane >> 3, b = lane & 7;
@@ -40,15 +40,17 @@ __global__ __launch_bounds__(64) void k_taugrad(Launch L, const float* g, double
       px = min(max(px, 0), d.Wp - 1);
       const int pix = (py + a) * d.W + px + b;
       const float rc = 1.0f / d.cnt[pix];
+      float p[2][C], t[2][C];
 #pragma unroll
-      for (int which = 0; which < 2; ++which) {
-        float p[C], t[C];
+      for (int ch = 0; ch < C; ++ch) {
+        p[0][ch] = d.img[ch * HW + pix];
+        p[1][ch] = g[ch * HW + pix] * rc;
+      }
+      project_pair<C>(PX, PY, lane, fb, p, t);
 #pragma unroll
-        for (int ch = 0; ch < C; ++ch)
-          p[ch] = which == 0 ? d.img[ch * HW + pix] : g[ch * HW + pix] * rc;
-        project_patch<C>(lr, li, a, b, fb, p, t);
-#pragma unroll
-        for (int ch = 0; ch < C; ++ch) core[which][k][ch][lane] = t[ch];
+      for (int ch = 0; ch < C; ++ch) {
+        core[0][k][ch][lane] = t[0][ch];
+        core[1][k][ch][lane] = t[1][ch];
       }
     }
     // real core tensors of y (ts) and of r = g / cnt (tr): [slot][channel]

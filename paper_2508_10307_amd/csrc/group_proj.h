@@ -1,6 +1,6 @@
-// Per-element t-SVD projection of one patch for the one-wavefront group
-// kernels of the adjoint extensions (k_taugrad, k_gbasis): lane = patch
-// element (a, b); the 8x8 slice products go through a small LDS tile.
+// Per-element t-SVD projection for the one-wavefront group kernels of the
+// adjoint extensions (k_taugrad, k_gbasis): lane = patch element (a, b); the
+// 8x8 slice products go through LDS tiles.
 #pragma once
 #include "hts_device.h"
 
@@ -8,78 +8,14 @@ namespace hts {
 
 constexpr double GP_SQ3_2 = 0.86602540378443864676;   // sqrt(3) / 2
 
-// Y = P V (if right) or Z = U^H P (else) for one 8x8 complex slice held one
-// element per lane: element (a, b) of the product from the LDS copy of P.
-// B is the basis slice pair (re, im) in row-major [r][c] order (im nullable).
-__device__ inline void slice_product(float (*lr)[8], float (*li)[8], int a, int b, const float* Br,
-                                     const float* Bi, bool right, double& outr, double& outi) {
-  double yr = 0.0, yi = 0.0;
-#pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    // right: sum_t P[a][t] V[t][b];  left: sum_t conj(U[t][a]) P[t][b]
-    const double pr = right ? lr[a][t] : lr[t][b];
-    const double pi = right ? li[a][t] : li[t][b];
-    const double br = right ? Br[t * 8 + b] : Br[t * 8 + a];
-    const double bi = Bi ? (right ? Bi[t * 8 + b] : -(double)Bi[t * 8 + a]) : 0.0;
-    yr = fma(pr, br, fma(-pi, bi, yr));
-    yi = fma(pr, bi, fma(pi, br, yi));
-  }
-  outr = yr;
-  outi = yi;
-}
-
-// Real core tensor T = U^T * P * V (t-product, Eq. 18) of one patch at this
-// lane's element, from the patch's C channel values p[] there: per frequency
-// f <= c/2, Z(f) = U_F(f)^H (P^(f) V_F(f)) through the LDS tile (lr, li),
-// then the inverse DFT along the channel mode,
-// T_j = (Z_0 + 2 Re(Z_1 e^{2 pi i j / 3})) / 3.  fb holds the Fourier basis
-// slices (FB_* layout).  Synchronises the work group (one wavefront).
-template <int C>
-__device__ inline void project_patch(float (*lr)[8], float (*li)[8], int a, int b, const float* fb,
-                                     const float* p, float* t) {
-  double z0 = 0.0, z1r = 0.0, z1i = 0.0;
-#pragma unroll
-  for (int f = 0; f < (C == 3 ? 2 : 1); ++f) {
-    double pr, pi;
-    if (C == 1) {
-      pr = p[0];
-      pi = 0.0;
-    } else if (f == 0) {
-      pr = (double)p[0] + (double)p[1] + (double)p[2];
-      pi = 0.0;
-    } else {
-      pr = (double)p[0] - 0.5 * ((double)p[1] + (double)p[2]);
-      pi = GP_SQ3_2 * ((double)p[2] - (double)p[1]);
-    }
-    __syncthreads();
-    lr[a][b] = (float)pr;
-    li[a][b] = (float)pi;
-    __syncthreads();
-    double yr, yi;
-    slice_product(lr, li, a, b, fb + (f ? FB_V1R : FB_V0), f ? fb + FB_V1I : nullptr, true, yr, yi);
-    __syncthreads();
-    lr[a][b] = (float)yr;
-    li[a][b] = (float)yi;
-    __syncthreads();
-    double zr, zi;
-    slice_product(lr, li, a, b, fb + (f ? FB_U1R : FB_U0), f ? fb + FB_U1I : nullptr, false, zr, zi);
-    if (f == 0) z0 = zr;
-    else { z1r = zr; z1i = zi; }
-  }
-#pragma unroll
-  for (int ch = 0; ch < C; ++ch) {
-    double v;
-    if (C == 1) v = z0;
-    else if (ch == 0) v = (z0 + 2.0 * z1r) / 3.0;
-    else if (ch == 1) v = (z0 - z1r - 2.0 * GP_SQ3_2 * z1i) / 3.0;
-    else v = (z0 - z1r + 2.0 * GP_SQ3_2 * z1i) / 3.0;
-    t[ch] = (float)v;
-  }
-}
-
-// The same projection for two patches at once (p[0], p[1] -> t[0], t[1]),
-// all frequencies sharing three work-group barriers: X (the DFTs of the
-// bands) and Y = X V_F live in LDS tiles [which * NF + f][re/im][64].
+// Real core tensors T = U^T * P * V (t-product, Eq. 18) of two patches at
+// this lane's element, from their C channel values p[0], p[1] there: per
+// frequency f <= c/2, Z(f) = U_F(f)^H (P^(f) V_F(f)), then the inverse DFT
+// along the channel mode, T_j = (Z_0 + 2 Re(Z_1 e^{2 pi i j / 3})) / 3.  Both
+// patches and all frequencies share three work-group barriers: X (the DFTs
+// of the bands) and Y = X V_F live in LDS tiles [which * NF + f][re/im][64];
+// fb holds the Fourier basis slices (FB_* layout).  One wavefront per work
+// group.
 template <int C>
 __device__ inline void project_pair(float (*X)[2][64], float (*Y)[2][64], int lane,
                                     const float* fb, const float (&p)[2][C], float (&t)[2][C]) {

@@ -10,7 +10,8 @@ compute one by one:
     threshold-kink protocol of the small tests, GPU float basis) and
     averaged (Eq. 2); the pixel must agree within 1e-3.
 The batch output of each image equals its single-image hts_denoise bit for
-bit (the bench's timed path is the batched one)."""
+bit (the bench's timed path is the batched one).  The same checks on one
+520 x 696 x 34 spectral-tube image through the band-count path."""
 import numpy as np
 import pytest
 import torch
@@ -128,3 +129,60 @@ def test_fullsize_batch_samples_match_the_oracle(batch):
             err = np.abs(out[:, yy, xx] - num / cnt).max()
             log(f"  pixel ({yy},{xx}): {len(gs)} groups, {cnt} estimates, |gpu - oracle| = {err:.2e}")
             assert err <= PIX_TOL
+
+
+def test_fullsize_spectral_tube_samples_match_the_oracle():
+    """One 520 x 696 x 34 image (the size of the paper's real-HSI scenes)
+    through the band-count path, as bench.py's spectral_tubes object runs
+    it: sampled references, the FP64 basis and sampled output pixels."""
+    C, H, W = 34, 520, 696
+    clean = synth.clean_image(4242, 0, C, H, W, 40)
+    y = synth.add_awgn(4242, 0, clean, 25.0)
+    p = api.Params(stride=3, window=31, K=32)
+    x = torch.from_numpy(y).to(dev())
+    out, st = api.hts_denoise(x, 25.0, p, save=True)
+    idx = st["idx"].cpu().numpy().astype(np.int64)
+    words = st["masks"].cpu().numpy().view(np.uint32)
+    rng = np.random.default_rng(12)
+    K, s, r = p.K, p.stride, (p.window - 1) // 2
+    ys, xs_, _, _ = ref_grid(H, W, 8, s)
+    g = omatch.guide_planes(omatch.quantize(y))[0]
+    Hp, Wp = H - 7, W - 7
+    for n in rng.choice(len(ys), 20, replace=False):
+        ry, rx = int(ys[n]), int(xs_[n])
+        ref = g[ry:ry + 8, rx:rx + 8]
+        c = []
+        for cy in range(max(0, ry - r), min(Hp - 1, ry + r) + 1):
+            for cx in range(max(0, rx - r), min(Wp - 1, rx + r) + 1):
+                if (cy, cx) != (ry, rx):
+                    c.append((int(((g[cy:cy + 8, cx:cx + 8] - ref) ** 2).sum()), cy * W + cx))
+        c.sort()
+        assert list(idx[n]) == [ry * W + rx] + [v for _, v in c[:K - 1]], n
+    _, _, U64, V64, _ = api.hts_basis(x, p, want_fp64=True)
+    _, _, Uo, Vo, _, _ = obasis.global_basis(y.astype(np.float64), 8, s)
+    np.testing.assert_allclose(U64.cpu().numpy(), Uo, atol=1e-9)
+    np.testing.assert_allclose(V64.cpu().numpy(), Vo, atol=1e-9)
+    UF = obasis.fourier_from_real(st["U"].cpu().numpy().astype(np.float64))
+    VF = obasis.fourier_from_real(st["V"].cpu().numpy().astype(np.float64))
+    tau = p.tau_mult * 25.0
+    py, px = np.divmod(idx, W)
+    o = out.cpu().numpy()
+    for _ in range(3):
+        yy, xx = int(rng.integers(0, H)), int(rng.integers(0, W))
+        cover = (py <= yy) & (yy < py + 8) & (px <= xx) & (xx < px + 8)
+        gs = np.nonzero(cover.any(axis=1))[0]
+        S = of.haar_group(of.tsvd_forward(of.gather_groups(y.astype(np.float64), idx[gs], 8),
+                                          UF, VF), K)
+        M = np.stack([group_masks(words, int(q), K, C) for q in gs])
+        diff = M != (np.abs(S) >= tau)
+        if diff.any():
+            assert np.abs(np.abs(S[diff]) - tau).max() <= DELTA_REL * tau
+        est = of.tsvd_inverse(of.haar_group_inverse(np.where(M, S, 0.0), K), UF, VF)
+        num, cnt = np.zeros(C), 0
+        for gi, q in enumerate(gs):
+            for k in np.nonzero(cover[q])[0]:
+                num += est[gi, k, :, yy - py[q, k], xx - px[q, k]]
+                cnt += 1
+        err = np.abs(o[:, yy, xx] - num / cnt).max()
+        log(f"  tube pixel ({yy},{xx}): {len(gs)} groups, |gpu - oracle| = {err:.2e}")
+        assert err <= PIX_TOL

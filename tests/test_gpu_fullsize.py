@@ -186,3 +186,45 @@ def test_fullsize_spectral_tube_samples_match_the_oracle():
         err = np.abs(o[:, yy, xx] - num / cnt).max()
         log(f"  tube pixel ({yy},{xx}): {len(gs)} groups, |gpu - oracle| = {err:.2e}")
         assert err <= PIX_TOL
+
+
+def test_fullsize_adjoint_samples_match_the_oracle():
+    """The differentiable configuration (512 x 512 RGB, K = 16, w = 31, loss =
+    mean squared error to the clean image): autograd through HaarTSVD, the
+    input gradient checked at sampled pixels against the oracle's frozen
+    adjoint (every group over the pixel, its K patches of g / cnt through
+    Q^T M Q with the forward masks)."""
+    wl = synth.diff_batch16(n=1)
+    im, q = wl.images[0], wl.params
+    p = api.Params(stride=q.stride, window=q.window, K=q.K, tau_mult=q.tau_mult)
+    x = torch.from_numpy(im.noisy).to(dev()).requires_grad_(True)
+    clean = torch.from_numpy(im.clean.astype(np.float32)).to(dev())
+    out = api.HaarTSVD.apply(x, im.sigma, q.tau_mult, p)
+    ((out - clean) ** 2).mean().backward()
+    g = (2.0 * (out.detach() - clean) / out.numel()).cpu().numpy().astype(np.float64)
+    _, st = api.hts_denoise(x.detach(), im.sigma, p, save=True)
+    C, H, W = im.noisy.shape
+    K = q.K
+    idx = st["idx"].cpu().numpy().astype(np.int64)
+    words = st["masks"].cpu().numpy().view(np.uint32)
+    r = g / st["cnt"].cpu().numpy().astype(np.float64)[None]
+    UF = obasis.fourier_from_real(st["U"].cpu().numpy().astype(np.float64))
+    VF = obasis.fourier_from_real(st["V"].cpu().numpy().astype(np.float64))
+    py, px = np.divmod(idx, W)
+    grad = x.grad.cpu().numpy()
+    scale = np.abs(grad).max()
+    rng = np.random.default_rng(13)
+    for _ in range(4):
+        yy, xx = int(rng.integers(0, H)), int(rng.integers(0, W))
+        cover = (py <= yy) & (yy < py + 8) & (px <= xx) & (xx < px + 8)
+        gs = np.nonzero(cover.any(axis=1))[0]
+        S = of.haar_group(of.tsvd_forward(of.gather_groups(r, idx[gs], 8), UF, VF), K)
+        M = np.stack([group_masks(words, int(q_), K, C) for q_ in gs])
+        est = of.tsvd_inverse(of.haar_group_inverse(np.where(M, S, 0.0), K), UF, VF)
+        acc = np.zeros(C)
+        for gi, q_ in enumerate(gs):
+            for k in np.nonzero(cover[q_])[0]:
+                acc += est[gi, k, :, yy - py[q_, k], xx - px[q_, k]]
+        err = np.abs(grad[:, yy, xx] - acc).max()
+        log(f"  gradient at ({yy},{xx}): {len(gs)} groups, |gpu - oracle| = {err:.2e} (max |grad| {scale:.2e})")
+        assert err <= 1e-4 * scale

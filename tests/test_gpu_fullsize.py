@@ -11,7 +11,9 @@ compute one by one:
     averaged (Eq. 2); the pixel must agree within 1e-3.
 The batch output of each image equals its single-image hts_denoise bit for
 bit (the bench's timed path is the batched one).  The same checks on one
-520 x 696 x 34 spectral-tube image through the band-count path."""
+520 x 696 x 34 spectral-tube image through the band-count path and on an
+eight-frame 540 x 960 RGB video; the gradient of the differentiable
+configuration at sampled pixels."""
 import numpy as np
 import pytest
 import torch
@@ -228,3 +230,69 @@ def test_fullsize_adjoint_samples_match_the_oracle():
         err = np.abs(grad[:, yy, xx] - acc).max()
         log(f"  gradient at ({yy},{xx}): {len(gs)} groups, |gpu - oracle| = {err:.2e} (max |grad| {scale:.2e})")
         assert err <= 1e-4 * scale
+
+
+def test_fullsize_video_samples_match_the_oracle():
+    """Eight 540 x 960 RGB frames with temporal reach 2 (bench.py's video
+    object): sampled references against the brute-force spatio-temporal
+    scan, the sequence basis in float, and sampled output pixels recomputed
+    from every group over them (stacked coordinates)."""
+    from oracle import video as ovideo
+    Tn, C, H, W, dt = 8, 3, 540, 960, 2
+    clean = np.stack([synth.clean_image(4343, t, C, H, W, 40) for t in range(Tn)])
+    f = np.stack([synth.add_awgn(4343, t, clean[t], 25.0) for t in range(Tn)])
+    p = api.Params(stride=3, window=21, K=32)
+    x = torch.from_numpy(f).to(dev())
+    out, st = api.hts_denoise_video(x, 25.0, p, dt=dt, save=True)
+    idx = st["idx"].cpu().numpy().astype(np.int64)
+    words = st["masks"].cpu().numpy().view(np.uint32)
+    K, s, r = p.K, p.stride, (p.window - 1) // 2
+    ys, xs_, _, _ = ref_grid(H, W, 8, s)
+    n_f = len(ys)
+    q = [omatch.quantize(f[t]) for t in range(Tn)]
+    planes = [omatch.guide_planes(qq) for qq in q]
+    rng = np.random.default_rng(14)
+    Hp, Wp = H - 7, W - 7
+    for ref in rng.choice(Tn * n_f, 12, replace=False):
+        t, n = divmod(int(ref), n_f)
+        ry, rx = int(ys[n]), int(xs_[n])
+        green = omatch.gcp_green(q[t], ys[n:n + 1], xs_[n:n + 1], 8, p.gcp_num, p.gcp_den)[0]
+        pl = 0 if green else 1
+        refp = planes[t][pl][ry:ry + 8, rx:rx + 8]
+        c = []
+        for t2 in range(max(0, t - dt), min(Tn - 1, t + dt) + 1):
+            gp = planes[t2][pl]
+            for cy in range(max(0, ry - r), min(Hp - 1, ry + r) + 1):
+                for cx in range(max(0, rx - r), min(Wp - 1, rx + r) + 1):
+                    if (t2, cy, cx) != (t, ry, rx):
+                        c.append((int(((gp[cy:cy + 8, cx:cx + 8] - refp) ** 2).sum()),
+                                  (t2 * H + cy) * W + cx))
+        c.sort()
+        assert list(idx[ref]) == [(t * H + ry) * W + rx] + [v for _, v in c[:K - 1]], ref
+    _, _, Uo, Vo, _, _ = ovideo.global_basis(f.astype(np.float64), 8, s)
+    np.testing.assert_allclose(st["U"].cpu().numpy(), Uo, atol=2e-6)
+    np.testing.assert_allclose(st["V"].cpu().numpy(), Vo, atol=2e-6)
+    UF = obasis.fourier_from_real(st["U"].cpu().numpy().astype(np.float64))
+    VF = obasis.fourier_from_real(st["V"].cpu().numpy().astype(np.float64))
+    ystack = ovideo.stack(f.astype(np.float64))
+    ostack = ovideo.stack(out.cpu().numpy())
+    tau = p.tau_mult * 25.0
+    py, px = np.divmod(idx, W)
+    for _ in range(3):
+        yy, xx = int(rng.integers(0, Tn * H)), int(rng.integers(0, W))
+        cover = (py <= yy) & (yy < py + 8) & (px <= xx) & (xx < px + 8)
+        gs = np.nonzero(cover.any(axis=1))[0]
+        S = of.haar_group(of.tsvd_forward(of.gather_groups(ystack, idx[gs], 8), UF, VF), K)
+        M = np.stack([group_masks(words, int(q_), K, C) for q_ in gs])
+        diff = M != (np.abs(S) >= tau)
+        if diff.any():
+            assert np.abs(np.abs(S[diff]) - tau).max() <= DELTA_REL * tau
+        est = of.tsvd_inverse(of.haar_group_inverse(np.where(M, S, 0.0), K), UF, VF)
+        num, cnt = np.zeros(C), 0
+        for gi, q_ in enumerate(gs):
+            for k in np.nonzero(cover[q_])[0]:
+                num += est[gi, k, :, yy - py[q_, k], xx - px[q_, k]]
+                cnt += 1
+        err = np.abs(ostack[:, yy, xx] - num / cnt).max()
+        log(f"  video pixel (row {yy}, col {xx}): {len(gs)} groups, |gpu - oracle| = {err:.2e}")
+        assert err <= PIX_TOL

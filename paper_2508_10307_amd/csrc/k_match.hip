@@ -600,7 +600,8 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
 // Exact scan of the whole window for references whose certified shortlist
 // overflowed: the window's guide pixels are staged in LDS, integer distances
 // are computed for every candidate, and (distance, window index) keys are
-// sorted bitonically in LDS; the first K-1 after the reference are kept.
+// sorted bitonically in LDS (padded to the next power of two of the window's
+// candidates); the first K-1 after the reference are kept.
 // The (image, entry) pairs of all images are dealt round-robin to the work
 // groups.
 __global__ __launch_bounds__(256) void k_match_fallback(Launch L) {
@@ -612,71 +613,81 @@ __global__ __launch_bounds__(256) void k_match_fallback(Launch L) {
   const int K = L.K;
   const int G = gridDim.x;
   const int nimg = L.table ? L.n_img : 1;
+  __shared__ int counts[256];
   long long base = 0;   // global number of the image's first entry
-  for (int im = 0; im < nimg; ++im) {
-    const ImgDesc d = L.table ? L.table[im] : L.one;
-    const int count = *d.fb_count;
-    const int j0 = (int)(((long long)blockIdx.x - base % G + G) % G);
-    base += count;
-    for (int j = j0; j < count; j += G) {
-      const int ref = d.fb_list[j];
-      const int ry = ref_coord(ref / d.nrx, L.stride, d.Hp);
-      const int rx = ref_coord(ref % d.nrx, L.stride, d.Wp);
-      const int y0 = max(0, ry - r), y1 = min(d.Hp - 1, ry + r);
-      const int x0 = max(0, rx - r), x1 = min(d.Wp - 1, rx + r);
-      const int wx = x1 - x0 + 1, nc = (y1 - y0 + 1) * wx;
-      const int pw = wx + PS - 1, ph = y1 - y0 + PS;   // staged pixel region
-      const int plane = (L.C == 1 || d.green[ref]) ? 0 : 1;
-      const int* g = d.gplanes + (size_t)plane * d.H * d.W;
-      __syncthreads();
-      for (int e = tid; e < ph * pw; e += 256) {
-        const int yy = e / pw, xx = e - yy * pw;
-        win[yy * WMAX + xx] = g[(y0 + yy) * d.W + x0 + xx];
-      }
-      __syncthreads();
-      const int* rp = win + (ry - y0) * WMAX + (rx - x0);
-      for (int c = tid; c < 4096; c += 256) {
-        unsigned long long key = ~0ull;
-        if (c < nc) {
-          const int cy = c / wx, cx = c - cy * wx;
-          if (cy + y0 != ry || cx + x0 != rx) {
-            const int* cp = win + cy * WMAX + cx;
-            long long dd = 0;
-            for (int a = 0; a < PS; ++a)
-#pragma unroll
-              for (int b = 0; b < PS; ++b) {
-                const int df = rp[a * WMAX + b] - cp[a * WMAX + b];
-                dd += (long long)df * df;
-              }
-            key = ((unsigned long long)dd << 12) | (unsigned)(cy * 64 + cx);
-          }
+  for (int i0 = 0; i0 < nimg; i0 += 256) {
+    // the images' list lengths, 256 at a time (most are 0: no descriptor read)
+    __syncthreads();
+    if (i0 + tid < nimg) counts[tid] = *(L.table ? L.table[i0 + tid] : L.one).fb_count;
+    __syncthreads();
+    for (int im = i0; im < min(nimg, i0 + 256); ++im) {
+      const int count = counts[im - i0];
+      if (count == 0) continue;
+      const ImgDesc d = L.table ? L.table[im] : L.one;
+      const int j0 = (int)(((long long)blockIdx.x - base % G + G) % G);
+      base += count;
+      for (int j = j0; j < count; j += G) {
+        const int ref = d.fb_list[j];
+        const int ry = ref_coord(ref / d.nrx, L.stride, d.Hp);
+        const int rx = ref_coord(ref % d.nrx, L.stride, d.Wp);
+        const int y0 = max(0, ry - r), y1 = min(d.Hp - 1, ry + r);
+        const int x0 = max(0, rx - r), x1 = min(d.Wp - 1, rx + r);
+        const int wx = x1 - x0 + 1, nc = (y1 - y0 + 1) * wx;
+        const int pw = wx + PS - 1, ph = y1 - y0 + PS;   // staged pixel region
+        const int plane = (L.C == 1 || d.green[ref]) ? 0 : 1;
+        const int* g = d.gplanes + (size_t)plane * d.H * d.W;
+        __syncthreads();
+        for (int e = tid; e < ph * pw; e += 256) {
+          const int yy = e / pw, xx = e - yy * pw;
+          win[yy * WMAX + xx] = g[(y0 + yy) * d.W + x0 + xx];
         }
-        keys[c] = key;
-      }
-      __syncthreads();
-      for (int k = 2; k <= 4096; k <<= 1)
-        for (int jj = k >> 1; jj > 0; jj >>= 1) {
-          for (int i = tid; i < 4096; i += 256) {
-            const int q = i ^ jj;
-            if (q > i) {
-              const unsigned long long a = keys[i], b = keys[q];
-              const bool asc = (i & k) == 0;
-              if (asc ? (a > b) : (a < b)) { keys[i] = b; keys[q] = a; }
+        __syncthreads();
+        const int* rp = win + (ry - y0) * WMAX + (rx - x0);
+        int n2 = 256;   // keys sorted: the window's candidates, padded to a power of two
+        while (n2 < nc) n2 <<= 1;
+        for (int c = tid; c < n2; c += 256) {
+          unsigned long long key = ~0ull;
+          if (c < nc) {
+            const int cy = c / wx, cx = c - cy * wx;
+            if (cy + y0 != ry || cx + x0 != rx) {
+              const int* cp = win + cy * WMAX + cx;
+              long long dd = 0;
+              for (int a = 0; a < PS; ++a)
+#pragma unroll
+                for (int b = 0; b < PS; ++b) {
+                  const int df = rp[a * WMAX + b] - cp[a * WMAX + b];
+                  dd += (long long)df * df;
+                }
+              key = ((unsigned long long)dd << 12) | (unsigned)(cy * 64 + cx);
             }
           }
-          __syncthreads();
+          keys[c] = key;
         }
-      for (int i = tid; i < K - 1; i += 256) {
-        const unsigned loc = (unsigned)(keys[i] & 0xFFFu);
-        const int pos = (y0 + (int)(loc >> 6)) * d.W + x0 + (int)(loc & 63u);
-        d.idx[(size_t)ref * K + 1 + i] = pos;
-        if (L.count_hist) atomicAdd(d.hist + pos, 1);
-        if (d.dist) d.dist[(size_t)ref * K + 1 + i] = (long long)(keys[i] >> 12);
-      }
-      if (tid == 0) {
-        d.idx[(size_t)ref * K] = ry * d.W + rx;
-        if (L.count_hist) atomicAdd(d.hist + ry * d.W + rx, 1);
-        if (d.dist) d.dist[(size_t)ref * K] = 0;
+        __syncthreads();
+        for (int k = 2; k <= n2; k <<= 1)
+          for (int jj = k >> 1; jj > 0; jj >>= 1) {
+            for (int i = tid; i < n2; i += 256) {
+              const int q = i ^ jj;
+              if (q > i) {
+                const unsigned long long a = keys[i], b = keys[q];
+                const bool asc = (i & k) == 0;
+                if (asc ? (a > b) : (a < b)) { keys[i] = b; keys[q] = a; }
+              }
+            }
+            __syncthreads();
+          }
+        for (int i = tid; i < K - 1; i += 256) {
+          const unsigned loc = (unsigned)(keys[i] & 0xFFFu);
+          const int pos = (y0 + (int)(loc >> 6)) * d.W + x0 + (int)(loc & 63u);
+          d.idx[(size_t)ref * K + 1 + i] = pos;
+          if (L.count_hist) atomicAdd(d.hist + pos, 1);
+          if (d.dist) d.dist[(size_t)ref * K + 1 + i] = (long long)(keys[i] >> 12);
+        }
+        if (tid == 0) {
+          d.idx[(size_t)ref * K] = ry * d.W + rx;
+          if (L.count_hist) atomicAdd(d.hist + ry * d.W + rx, 1);
+          if (d.dist) d.dist[(size_t)ref * K] = 0;
+        }
       }
     }
   }

@@ -307,13 +307,14 @@ def main():
         del ws_t, xt
 
     # ---- video: 8 synthetic 540 x 960 RGB frames (the frame size of the
-    # paper's Set8 clips), AWGN sigma = 25, spatio-temporal search over
-    # frames t-2..t+2, K = 32, w = 21 ----
+    # paper's Set8 clips) of one scene translating by (1, 2) px per frame,
+    # AWGN sigma = 25 drawn per frame, spatio-temporal search over frames
+    # t-2..t+2, K = 32, w = 21 ----
     vid = None
     if not args.no_adaptive:
         from paper_2508_10307_amd import synth
         Tv, Hv, Wv = 8, 540, 960
-        clean_v = np.stack([synth.clean_image(4343, t, 3, Hv, Wv, 40) for t in range(Tv)])
+        clean_v = synth.clean_video(4343, Tv, 3, Hv, Wv, 40)
         xv = torch.from_numpy(np.stack([synth.add_awgn(4343, t, clean_v[t], 25.0)
                                         for t in range(Tv)])).to(dev)
         pv = api.Params(stride=3, window=21, K=32, tau_mult=q.tau_mult)

@@ -37,9 +37,11 @@ struct Geo {
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
-// Work groups of the band-count filter for n groups: each holds its own
-// scratch (K * C * 64 floats), kept within about 1 GB (at least one work
-// group per CU, at most GEN_GRID).
+// Work groups of the band-count filter for n groups (one wavefront each):
+// each holds its own scratch (K * C * 64 floats), kept within about 1 GB;
+// at least one work group per CU and at most GEN_GRID, enough to fill every
+// SIMD's wavefront slots, which hides the latency of the kernel's LDS and
+// scratch round trips.
 int gen_filter_grid(int n, int K, int C) {
   const size_t per = (size_t)K * C * 64 * 4;
   const int cap = (int)std::max<size_t>(256, std::min<size_t>(GEN_GRID, ((size_t)1 << 30) / per));

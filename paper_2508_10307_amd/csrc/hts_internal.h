@@ -22,7 +22,7 @@ constexpr int GEN_CMAX = 256;          // bands
 constexpr int GEN_KMAX = 32;           // group size
 constexpr int GEN_FC = 8;              // frequencies per covariance work item
 constexpr int GEN_EIG_M = 16;          // eigenproblems per work group
-constexpr int GEN_GRID = 2048;         // filter work groups (each with its own scratch)
+constexpr int GEN_GRID = 32768;        // filter work groups (each with its own scratch)
 __host__ __device__ inline bool general_c(int C) { return C != 1 && C != 3; }
 __host__ __device__ inline int n_freq(int C) { return C / 2 + 1; }
 

@@ -74,6 +74,18 @@ def clean_image(workload_id: int, image_index: int, C: int, H: int, W: int,
     return np.stack([np.clip(0.6 * L + 0.4 * c, 0.0, 255.0) for c in chans])
 
 
+def clean_video(workload_id: int, T: int, C: int, H: int, W: int, n_blobs: int,
+                motion=(1, 2)) -> np.ndarray:
+    """T clean frames [T][C][H][W] float64 of one scene under a global
+    translation of ``motion`` = (my, mx) pixels per frame: frame t is the
+    H x W window at (t my, t mx) of one clean image (clean_image, image
+    index 0) of size (H + (T-1) my) x (W + (T-1) mx), so the content of
+    frame t reappears in frame t+1 shifted by (-my, -mx)."""
+    my, mx = int(motion[0]), int(motion[1])
+    base = clean_image(workload_id, 0, C, H + (T - 1) * my, W + (T - 1) * mx, n_blobs)
+    return np.stack([base[:, t * my:t * my + H, t * mx:t * mx + W] for t in range(T)])
+
+
 def add_awgn(workload_id: int, image_index: int, clean: np.ndarray, sigma: float) -> np.ndarray:
     rng = _rng(workload_id, image_index, 1)
     return (clean + rng.normal(0.0, sigma, clean.shape)).astype(np.float32)

@@ -239,7 +239,7 @@ def test_fullsize_video_samples_match_the_oracle():
     from every group over them (stacked coordinates)."""
     from oracle import video as ovideo
     Tn, C, H, W, dt = 8, 3, 540, 960, 2
-    clean = np.stack([synth.clean_image(4343, t, C, H, W, 40) for t in range(Tn)])
+    clean = synth.clean_video(4343, Tn, C, H, W, 40)
     f = np.stack([synth.add_awgn(4343, t, clean[t], 25.0) for t in range(Tn)])
     p = api.Params(stride=3, window=21, K=32)
     x = torch.from_numpy(f).to(dev())

@@ -64,3 +64,15 @@ def test_zero_sigma_reconstructs_the_sequence():
     f = frames_of(3, 3, 20, 21, 750)
     r = video.denoise(f, 0.0, 8, 3, 9, 8, dt=1)
     np.testing.assert_allclose(r["out"], f, atol=1e-9)
+
+
+def test_synthetic_clip_is_one_translating_scene():
+    """The clip generator of the video workloads: frame t+1 is frame t moved
+    by the motion vector (content shifted up-left by (my, mx))."""
+    from paper_2508_10307_amd import synth
+    T, C, H, W, my, mx = 4, 3, 40, 56, 1, 2
+    f = synth.clean_video(7, T, C, H, W, 6, motion=(my, mx))
+    assert f.shape == (T, C, H, W)
+    for t in range(T - 1):
+        np.testing.assert_array_equal(f[t + 1][:, :H - my, :W - mx], f[t][:, my:, mx:])
+    assert np.abs(f[1] - f[0]).max() > 1.0   # the scene does move

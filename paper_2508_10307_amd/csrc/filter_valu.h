@@ -163,6 +163,11 @@ __device__ inline float haar_unscale(int k, int K) {
 // MASKS = 1 exports the keep-masks (when d.masks is set).
 // WT = 1: weighted aggregation (a separate instantiation, so that the
 // uniform one keeps its register budget).
+// WT = 2: uniform weights without the LDS tile: every estimate row is
+// transposed through the wavefront's scratch and added straight into the
+// image numerator (64-bit fixed point, eight consecutive pixels per patch
+// and instruction), for groups whose patches may lie anywhere in the image
+// (the stacked frames of a video).
 // FT = 1 (c = 3): threshold in the channel-Fourier domain (whole conjugate
 // pairs by their orthonormal magnitude) instead of Eq. 19 on the real core:
 // the channel IDFT after the projection and the DFT before the inverse are
@@ -181,11 +186,12 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
   const int RA = (TY - 1) * s + 2 * r + PS, CA = (TX - 1) * s + 2 * r + PS;
   // weighted aggregation (Eq. 2 with w_g = 1 / max(1, kept coefficients)):
   // one more tile plane for the weight sums
-  constexpr bool wtd = WT != 0 && !ADJ;
+  constexpr bool wtd = WT == 1 && !ADJ;
+  constexpr bool glob = WT == 2 && !ADJ;
   constexpr bool ft = FT != 0 && C == 3 && !ADJ;
   constexpr int NP = C + (wtd ? 1 : 0);
   unsigned long long* acc = (unsigned long long*)fsm;          // [NP][RA][CA] fixed point
-  float* T = fsm + (2 * NP * RA * CA + 3) / 4 * 4 + wave * TSCRATCH;   // transpose scratch
+  float* T = fsm + (glob ? 0 : (2 * NP * RA * CA + 3) / 4 * 4) + wave * TSCRATCH;   // transpose scratch
 
   for_each_item_t<W_FILT, BATCH>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
     const int ntx = (d.nrx + TX - 1) / TX;
@@ -217,9 +223,11 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
       wj[j] = haar_unscale(kl * SPL + j, K);
     }
 
-    __syncthreads();
-    for (int e = tid; e < NP * RA * CA; e += 256) acc[e] = 0ull;
-    __syncthreads();
+    if (!glob) {
+      __syncthreads();
+      for (int e = tid; e < NP * RA * CA; e += 256) acc[e] = 0ull;
+      __syncthreads();
+    }
 
     const int ngroups = (iy1 - iy0 + 1) * (ix1 - ix0 + 1);
     for (int gl = wave; gl < ngroups; gl += 4) {
@@ -495,7 +503,19 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
         for (int ch = 0; ch < C; ++ch)
 #pragma unroll
           for (int b = 0; b < 8; ++b) nf = fmaf(out[ch][b], 0.f, nf);
-        if (active && inside) {
+        if (glob) {
+          // lane (kl, a) receives column a of its patch: row i goes to
+          // pixel (py + i, px + a)
+#pragma unroll
+          for (int ch = 0; ch < C; ++ch) {
+            transpose_rc(T, kl, a, out[ch]);
+            if (active) {
+              unsigned long long* colp = d.num64 + (size_t)ch * HW + (size_t)py[j] * d.W + px[j] + a;
+#pragma unroll
+              for (int i = 0; i < 8; ++i) atomicAdd(colp + (size_t)i * d.W, fx_from_float(out[ch][i]));
+            }
+          }
+        } else if (active && inside) {
           const int k = kl * SPL + j;
 #pragma unroll
           for (int ch = 0; ch < C; ++ch) {
@@ -519,8 +539,10 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
       }
       if (__ballot(nf != 0.f)) poison_group(d, d.idx + (size_t)g * K, grel, K, C, rW, lane);
     }
-    __syncthreads();
-    flush_tile(d, acc, C, RA, CA, AY0, AX0, AH, AW, wtd);
+    if (!glob) {
+      __syncthreads();
+      flush_tile(d, acc, C, RA, CA, AY0, AX0, AH, AW, wtd);
+    }
   });
 }
 

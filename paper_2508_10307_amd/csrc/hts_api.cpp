@@ -1158,10 +1158,23 @@ hts_status hts_denoise_video(const hts_params* p, const float* frames, int32_t T
   }
   if (general_c(C)) HIPCHK(launch_eig_gen(LS(d, -1), s));
   else HIPCHK(launch_eig(LS(d, -1), s));
-  HIPCHK(launch_fbasis_gen(LS(d, -1), s));
   // filter and average over the stacked image
   HIPCHK(launch_zero_accum(LS(d, W_PIX), 0, s));
-  HIPCHK(launch_filter_gen(LS(d, -1), vp.grid, s));
+  if (general_c(C)) {
+    HIPCHK(launch_fbasis_gen(LS(d, -1), s));
+    HIPCHK(launch_filter_gen(LS(d, -1), vp.grid, s));
+  } else {
+    // c = 1, 3: the vector-ALU filter over tiles of the stacked reference
+    // grid (T * nry rows), with global aggregation
+    HIPCHK(launch_fbasis(LS(d, -1), nullptr, nullptr, s));
+    ImgDesc dv = d;
+    dv.nry = T * vp.f.nry;
+    Launch Lv = LS(dv, -1);
+    Lv.fty = VIDEO_FTY;
+    Lv.ftx = VIDEO_FTX;
+    Lv.total = ((dv.nry + VIDEO_FTY - 1) / VIDEO_FTY) * ((dv.nrx + VIDEO_FTX - 1) / VIDEO_FTX);
+    HIPCHK(launch_filter_stacked(Lv, s));
+  }
   HIPCHK(launch_zero_hist(LS(d, W_PIX), 0, s));
   HIPCHK(launch_count_hist(LS(d, W_REF), 0, s));
   HIPCHK(launch_count_box(LS(d, W_BOX), 0, s));

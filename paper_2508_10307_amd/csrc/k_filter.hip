@@ -2,6 +2,7 @@
 // uniform or weighted aggregation, real-domain threshold (Eq. 19); the
 // channel-Fourier threshold variant is launched from k_filter_ft.hip.
 #include "filter_valu.h"
+#include "video_internal.h"
 
 namespace hts {
 
@@ -98,6 +99,20 @@ hipError_t launch_scatter_est(const Launch& L, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_scatter_est, dim3((n + 3) / 4), dim3(256), 0, s, L, L.one.group_est, L.C);
   return hipGetLastError();
+}
+
+// Global aggregation (WT = 2): the groups of a tile may reach beyond its
+// search windows (the stacked frames of a video), so there is no LDS tile,
+// only the transpose scratch; no group estimates.
+hipError_t launch_filter_stacked(const Launch& L, hipStream_t s) {
+  if (L.total <= 0) return hipSuccess;
+  if (L.table || L.one.group_est || !L.one.num64 || (L.C != 1 && L.C != 3)) return hipErrorInvalidValue;
+  const int g = xcd_grid(L.total);
+  const size_t lds = 4 * TSCRATCH * sizeof(float);
+  const bool masks = L.one.masks != nullptr;
+  if (L.C == 1)
+    return masks ? launch_filter_c<1, 0, 1, 0, 2>(L, g, lds, s) : launch_filter_c<1, 0, 0, 0, 2>(L, g, lds, s);
+  return masks ? launch_filter_c<3, 0, 1, 0, 2>(L, g, lds, s) : launch_filter_c<3, 0, 0, 0, 2>(L, g, lds, s);
 }
 
 }  // namespace hts

@@ -19,5 +19,11 @@ hipError_t launch_match_video(const Launch& L, const VideoGeo& v, hipStream_t s)
 hipError_t launch_cov_gen(const Launch& L, hipStream_t s);
 hipError_t launch_eig_gen(const Launch& L, hipStream_t s);
 hipError_t launch_filter_gen_adj(const Launch& L, int grid, hipStream_t s);
+// The vector-ALU filter of c = 1 and c = 3 with global aggregation, for one
+// image descriptor whose groups may gather patches anywhere in the image:
+// L.total tiles of L.fty x L.ftx references over d.nry x d.nrx, estimates
+// added to d.num64.
+hipError_t launch_filter_stacked(const Launch& L, hipStream_t s);
+constexpr int VIDEO_FTY = 4, VIDEO_FTX = 8;   // reference tile of one work group
 
 }  // namespace hts

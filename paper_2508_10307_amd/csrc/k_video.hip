@@ -11,9 +11,12 @@
 // window, enumerated frame-major then row-major, which is the order of their
 // stacked indices.  Lane l takes candidates l, l + 64, ...: the exact integer
 // distance on the guide plane of the reference's kind (GCP test on the
-// reference patch for c = 3), key = (distance << 12) | ordinal; after every
-// 64 candidates one bitonic sort of the 128 keys (running best 64 and the new
-// ones) keeps the 64 smallest in order.
+// reference patch for c = 3), key = (distance << 12) | ordinal.  Keys below
+// the running (K-1)-th smallest are compacted into a 64-entry LDS buffer of
+// the wavefront; when the next 64 candidates could overflow it, one bitonic
+// sort of 128 keys (running best 64 and the buffer) keeps the 64 smallest in
+// order and lowers the threshold.  A key at or above the threshold already
+// has K-1 smaller keys kept, so it can never enter the result.
 #include "hts_device.h"
 #include "video_internal.h"
 
@@ -42,10 +45,18 @@ hipError_t launch_stack(const float* frames, float* stacked, int T, int C, int H
   return hipGetLastError();
 }
 
+// Lane l's 64-bit value, read by every lane (l wavefront-uniform).
+__device__ inline unsigned long long lane_u64(unsigned long long v, int l) {
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)v, l);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(v >> 32), l);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
 // L.one: the stacked image (img, gplanes of the stacked image, idx / dist
 // rows for T * n_ref_frame references).  Four wavefronts per work group.
 __global__ __launch_bounds__(256) void k_match_video(Launch L, VideoGeo v) {
   __shared__ int refp[4][64];
+  __shared__ unsigned long long kbuf[4][64];   // keys waiting for the next merge
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int a = lane >> 3, b = lane & 7;
   const ImgDesc& d = L.one;
@@ -88,7 +99,21 @@ __global__ __launch_bounds__(256) void k_match_video(Launch L, VideoGeo v) {
     const int y0 = max(0, ry - r), y1 = min(v.Hp - 1, ry + r);
     const int x0 = max(0, rx - r), x1 = min(v.Wp - 1, rx + r);
     const int wx = x1 - x0 + 1, ncf = (y1 - y0 + 1) * wx, nc = (t1 - t0 + 1) * ncf;
-    unsigned long long key[2] = {~0ull, ~0ull};   // [0]: best 64 (element = lane), [1]: new
+    unsigned long long best = ~0ull;   // the 64 smallest merged keys, ascending over the lanes
+    unsigned long long thr = ~0ull;    // the (K-1)-th smallest merged key
+    int nbuf = 0;                      // keys in kbuf[wv] (wavefront-uniform)
+    // merge the buffer into best and lower the threshold
+    auto merge = [&]() {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      unsigned long long key[2] = {best, lane < nbuf ? kbuf[wv][lane] : ~0ull};
+      wave_sort_u64<2>(key);
+      best = key[0];
+      thr = lane_u64(best, K - 2);
+      nbuf = 0;
+      __builtin_amdgcn_wave_barrier();   // the buffer is rewritten after the reads
+    };
     for (int c0 = 0; c0 < nc; c0 += 64) {
       const int c = c0 + lane;
       unsigned long long kk = ~0ull;
@@ -108,21 +133,31 @@ __global__ __launch_bounds__(256) void k_match_video(Launch L, VideoGeo v) {
           kk = ((unsigned long long)dd << 12) | (unsigned)c;
         }
       }
-      key[1] = kk;
-      wave_sort_u64<2>(key);
+      unsigned long long m = __ballot(kk < thr);
+      if (nbuf + __popcll(m) > 64) {
+        merge();
+        m = __ballot(kk < thr);
+      }
+      if (kk < thr) {
+        const int slot = nbuf + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+        kbuf[wv][slot] = kk;
+      }
+      nbuf += __popcll(m);
     }
-    // key[0] on lane i: the i-th smallest (distance, ordinal)
+    if (nbuf > 0) merge();
+    // best on lane i: the i-th smallest (distance, ordinal)
     int* row = d.idx + (size_t)ref * K;
     if (lane == 0) {
       row[0] = prow * W + rx;
       if (d.dist) d.dist[(size_t)ref * K] = 0;
     }
     if (lane < K - 1) {
-      const int c = (int)(key[0] & 0xFFFull);
+      const int c = (int)(best & 0xFFFull);
       const int tf = c / ncf, rem = c - tf * ncf;
       const int t2 = t0 + tf, cy = y0 + rem / wx, cx = x0 + rem % wx;
       row[1 + lane] = (t2 * v.H + cy) * W + cx;
-      if (d.dist) d.dist[(size_t)ref * K + 1 + lane] = (long long)(key[0] >> 12);
+      if (d.dist) d.dist[(size_t)ref * K + 1 + lane] = (long long)(best >> 12);
     }
     __builtin_amdgcn_wave_barrier();   // refp[wv] is rewritten by the next reference
   }

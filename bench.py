@@ -91,7 +91,7 @@ TRAFFIC_SOURCES = ["paper_2508_10307_amd/csrc/k_filter.hip",
                    "paper_2508_10307_amd/csrc/hts_internal.h"]
 TRAFFIC = {    # kernel name -> (sources sha256, bytes per launch)
     "void hts::k_filter<3, 4, 0, 0, 0, 0, 0>(hts::Launch)":
-        ("aeca2903cac52c8fea28c9e7f1f2d2d16b60d8654adb5ba28c2cfcf0e0354175", 58499712),
+        ("8d72426f6c5f232e17577a578c9416c967b4f27c9ce1e0a7787e6e3e7160fb68", 58522454),
 }
 
 

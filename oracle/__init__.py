@@ -24,7 +24,7 @@ Modules
             perturbation, phase gauge, covariance chain rule).
   video     spatio-temporal grouping across frames and the video pipeline
             on the stacked frames.
-  adaptive  A-Haar-tSVD noise-level adjustment (Sec. III-C, Eq. 21-22): the
+  adaptive  A-Haar-tSVD noise-level adjustment (Sec. III.D, Eq. 21-22): the
             circulant eigenvalue rank test, the vote, sub-image denoising.
 
 Parity status (each function is pinned by a test in tests/test_oracle_*.py

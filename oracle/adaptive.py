@@ -1,4 +1,4 @@
-"""A-Haar-tSVD noise-level adjustment (Sec. III-C, Eq. 21-22; Algorithm
+"""A-Haar-tSVD noise-level adjustment (Sec. III.D, Eq. 21-22; Algorithm
 A-Haar-tSVD) - oracle, test infrastructure only.
 
 The CNN estimator of the paper is out of scope: the caller supplies sigma_est.

@@ -43,9 +43,12 @@ def guide_planes(q: np.ndarray):
     times the RGB average of Eq. 10 and ranks candidates identically.
 
     Reading H1 (other band counts, the spectral tubes of HSI): the GCP test
-    of Eq. 10 is an RGB rule, so the guide is the band mean (band_mean), the
-    quantity the paper's HSI noise estimate also works on; it stays on the
-    2^-8 grid within the clamp, so distances stay exact integers."""
+    of Eq. 10 is an RGB rule and the paper names no matching guide for other
+    band counts, so the guide is the band mean (band_mean), a choice of this
+    oracle and of the kernels (the paper's HSI extension, Sec. III.E, uses
+    the mean of the medium-wavelength bands for noise estimation, not for
+    matching); it stays on the 2^-8 grid within the clamp, so distances stay
+    exact integers."""
     if q.shape[0] == 1:
         return [q[0]]
     if q.shape[0] != 3:

@@ -1,4 +1,4 @@
-// Noise-level adjustment of A-Haar-tSVD (Sec. III-C, Eq. 21-22; Algorithm
+// Noise-level adjustment of A-Haar-tSVD (Sec. III.D, Eq. 21-22; Algorithm
 // A-Haar-tSVD Step 1), for a caller-supplied sigma_est.
 //
 // circ(G) circ(G)^T of a group G = (p_1 .. p_K) along its group mode has the

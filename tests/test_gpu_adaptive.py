@@ -1,4 +1,4 @@
-"""GPU parity of the A-Haar-tSVD noise-level adjustment (Sec. III-C, Eq. 21-22)
+"""GPU parity of the A-Haar-tSVD noise-level adjustment (Sec. III.D, Eq. 21-22)
 through the C ABI against the FP64 oracle.
 
 Bar: the rank of every sampled group and the voted sigma-hat are exact (the

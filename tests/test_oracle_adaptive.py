@@ -1,4 +1,4 @@
-"""Pins of the A-Haar-tSVD noise-level adjustment in the oracle (Sec. III-C,
+"""Pins of the A-Haar-tSVD noise-level adjustment in the oracle (Sec. III.D,
 Eq. 21-22): brute-force eigenvalues of the explicitly built circulant, the
 closed form of Eq. 21, constructed groups with known ranks, the vote rule and
 the sub-image composition."""

@@ -156,7 +156,13 @@ hts_status hts_basis(const hts_params* p, const float* noisy, int32_t C, int32_t
 /* Alg. 1 Step 2(2)-(4) (Eq. 18-20) for references [ref_begin, ref_begin+ref_count):
  * gather each group, project with U^T * . * V (t-product) and H_K along the
  * group, keep coefficients with |s| >= tau_mult*sigma, invert.
- * idx        in, int32 [n_ref][K] (all references of the image).
+ * idx        in, int32 [n_ref][K] (all references of the image).  Any
+ *            grouping is accepted, not only hts_match's: a patch outside the
+ *            accumulation tile of its work group (an entry beyond its
+ *            reference's search window) is added straight into the image;
+ *            an entry that is not a valid patch corner (0 <= y <= H-ps,
+ *            0 <= x <= W-ps) is taken at the nearest valid corner, in the
+ *            estimates and in cnt alike.
  * U, V       in, float32 [C][ps][ps].
  * num, cnt   in/out, nullable together: estimates are ADDED into
  *            num float32 [C][H][W] and coverage counts into cnt float32 [H][W]
@@ -282,6 +288,23 @@ hts_status hts_denoise_video_backward(const hts_params* p, const float* grad_out
                                       const float* V, const float* cnt, float* grad_in, void* ws,
                                       size_t ws_bytes, void* stream);
 
+/* Diagnostics of the certified shortlist of hts_match (Alg. 1 Step 1):
+ * the number of references whose shortlist overflowed (or held fewer than
+ * K-1 entries) in the last hts_match / hts_denoise call on this workspace;
+ * those references were matched by an exact scan of their whole window
+ * instead, so their indices are the same either way.  count: device int32[1],
+ * written asynchronously on `stream`.  The parameters and image shape must be
+ * those of that call.  Errors: HTS_ERR_INVALID for null pointers, the
+ * parameter and workspace checks of hts_match. */
+hts_status hts_match_fallback_count(const hts_params* p, int32_t C, int32_t H, int32_t W,
+                                   const void* ws, size_t ws_bytes, int32_t* count, void* stream);
+
+/* The same for every image of the last hts_denoise_batch(_adaptive) call on
+ * this workspace with these images: counts, device int32[n]. */
+hts_status hts_batch_fallback_counts(const hts_params* p, const hts_image* imgs, int32_t n,
+                                     const void* ws, size_t ws_bytes, int32_t* counts,
+                                     void* stream);
+
 /* Workspace bytes for hts_denoise_batch over these n images (host array). */
 hts_status hts_batch_workspace_size(const hts_params* p, const hts_image* imgs, int32_t n,
                                     size_t* bytes);
@@ -294,7 +317,7 @@ hts_status hts_batch_workspace_size(const hts_params* p, const hts_image* imgs, 
 hts_status hts_denoise_batch(const hts_params* p, const hts_image* imgs, int32_t n,
                              void* ws, size_t ws_bytes, void* stream);
 
-/* A-Haar-tSVD noise-level adjustment (Sec. III-C, Eq. 21-22; Algorithm
+/* A-Haar-tSVD noise-level adjustment (Sec. III.D, Eq. 21-22; Algorithm
  * A-Haar-tSVD Step 1) for a caller-supplied sigma_est (the paper's CNN
  * estimator is not part of this library).  For each sampled group (the
  * reference indices samples[0..n_samples), device int32, drawn by the
@@ -333,6 +356,8 @@ hts_status hts_denoise_batch_adaptive(const hts_params* p, const hts_image* imgs
  * coverage count held fixed (the map noisy -> denoised is then linear;
  * derived from Eq. 18-20 and Eq. 2):
  *   grad_in = sum_g Gather_g^T Q^T M_g Q Gather_g (grad_out / cnt).
+ * idx is taken as in hts_filter (any grouping; invalid corners at the
+ * nearest valid one).
  * grad_tau_mult (nullable, device float) receives 0: the threshold enters
  * only through the frozen masks. */
 hts_status hts_denoise_backward(const hts_params* p, const float* grad_out,

@@ -198,6 +198,28 @@ def hts_denoise_backward(grad_out, st, p: Params, ws=None):
     return gin, gtau
 
 
+def hts_match_fallback_count(p: Params, C: int, H: int, W: int, ws: torch.Tensor) -> torch.Tensor:
+    """References of the last hts_match / hts_denoise on workspace ws whose
+    certified shortlist overflowed (matched by the exact window scan).
+    Returns a device int32 tensor [1]."""
+    out = torch.empty(1, dtype=torch.int32, device=ws.device)
+    pc = p.c()
+    L.check("hts_match_fallback_count", L.load().hts_match_fallback_count(
+        ctypes.byref(pc), C, H, W, _ptr(ws), ws.numel(), _ptr(out), _stream(ws.device)))
+    return out
+
+
+def hts_batch_fallback_counts(p: Params, noisy, outs, sigmas, ws: torch.Tensor) -> torch.Tensor:
+    """The same per image of the last hts_denoise_batch on ws with these
+    images.  Returns a device int32 tensor [n]."""
+    arr = _images(noisy, outs, sigmas)
+    out = torch.empty(len(noisy), dtype=torch.int32, device=ws.device)
+    pc = p.c()
+    L.check("hts_batch_fallback_counts", L.load().hts_batch_fallback_counts(
+        ctypes.byref(pc), arr, len(noisy), _ptr(ws), ws.numel(), _ptr(out), _stream(ws.device)))
+    return out
+
+
 def _images(noisy: Sequence[torch.Tensor], outs: Sequence[torch.Tensor], sigmas):
     arr = (L.HtsImage * len(noisy))()
     for i, (x, o, s) in enumerate(zip(noisy, outs, sigmas)):

@@ -496,8 +496,8 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
           }
         }
         const int ly = py[j] + a - AY0, lx = px[j] - AX0;
-        // a patch outside the tile's reach (idx not from this reference's
-        // search window) is not aggregated
+        // a patch outside the tile's reach (an idx entry that is not from
+        // its reference's search window) goes straight to the image
         const bool inside = ly >= a && ly + PS - a <= AH && lx >= 0 && lx + PS <= AW;
 #pragma unroll
         for (int ch = 0; ch < C; ++ch)
@@ -515,18 +515,28 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
               for (int i = 0; i < 8; ++i) atomicAdd(colp + (size_t)i * d.W, fx_from_float(out[ch][i]));
             }
           }
-        } else if (active && inside) {
+        } else if (active) {
           const int k = kl * SPL + j;
+          if (inside) {
 #pragma unroll
-          for (int ch = 0; ch < C; ++ch) {
-            unsigned long long* rowp = acc + (ch * RA + ly) * CA + lx;
+            for (int ch = 0; ch < C; ++ch) {
+              unsigned long long* rowp = acc + (ch * RA + ly) * CA + lx;
 #pragma unroll
-            for (int b = 0; b < 8; ++b) atomicAdd(rowp + b, fx_from_float(out[ch][b]));
-          }
-          if (wtd) {
-            unsigned long long* wrow = acc + (C * RA + ly) * CA + lx;
+              for (int b = 0; b < 8; ++b) atomicAdd(rowp + b, fx_from_float(out[ch][b]));
+            }
+            if (wtd) {
+              unsigned long long* wrow = acc + (C * RA + ly) * CA + lx;
 #pragma unroll
-            for (int b = 0; b < 8; ++b) atomicAdd(wrow + b, fxw);
+              for (int b = 0; b < 8; ++b) atomicAdd(wrow + b, fxw);
+            }
+          } else if constexpr (!BATCH) {
+            // (batched launches filter the groups of their own match, which
+            // always lie inside the tile: no cold path, no register cost)
+            const int pix = (py[j] + a) * d.W + px[j];
+            for (int ch = 0; ch < C; ++ch)
+              for (int b = 0; b < 8; ++b) add_estimate_global(d, ch, pix + b, out[ch][b]);
+            if (wtd)
+              for (int b = 0; b < 8; ++b) add_weight_global(d, pix + b, fxw);
           }
           if (d.group_est) {
             float* ge = d.group_est + (((size_t)grel * K + k) * C) * PS2 + a * 8;

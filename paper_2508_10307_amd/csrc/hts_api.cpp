@@ -503,15 +503,20 @@ std::mutex g_graph_mu;
 std::map<std::string, GraphEntry> g_graphs;
 hipStream_t g_capture_stream[64] = {nullptr};
 
-std::string graph_key(const hts_params* p, const hts_image* imgs, int n, const void* ws,
-                      bool adaptive) {
+// The key holds the schedule the parameters resolve to (tile shape, filter
+// implementation, distance-tile terms), not only the tune word: with
+// tune = 0 the schedule comes from the autotune table, which hts_autotune
+// (or a cache file) may change between calls, and a graph captured for the
+// old schedule would launch the filter over the old tile grid.
+std::string graph_key(const hts_params* p, const Schedule& sc, const hts_image* imgs, int n,
+                      const void* ws, bool adaptive) {
   std::string k = adaptive ? "A|" : "|";
-  char buf[128];
+  char buf[160];
   int dev = 0;
   (void)hipGetDevice(&dev);
-  std::snprintf(buf, sizeof(buf), "%d|%d %d %d %d %a %d %d %d %d %d|%p|", dev, p->ps, p->stride,
-                p->window, p->K, (double)p->tau_mult, p->gcp_num, p->gcp_den, p->match_mode,
-                p->flags, p->tune, ws);
+  std::snprintf(buf, sizeof(buf), "%d|%d %d %d %d %a %d %d %d %d|%d %d %d %d|%p|", dev, p->ps,
+                p->stride, p->window, p->K, (double)p->tau_mult, p->gcp_num, p->gcp_den,
+                p->match_mode, p->flags, sc.fty, sc.ftx, sc.valu, sc.terms, ws);
   k += buf;
   for (int i = 0; i < n; ++i) {
     std::snprintf(buf, sizeof(buf), "%dx%dx%d;", imgs[i].C, imgs[i].H, imgs[i].W);
@@ -827,6 +832,33 @@ hts_status hts_denoise_backward_basis(const hts_params* p, const float* noisy,
   return HTS_OK;
 }
 
+hts_status hts_match_fallback_count(const hts_params* p, int32_t C, int32_t H, int32_t W,
+                                   const void* ws, size_t ws_bytes, int32_t* count, void* stream) {
+  Geo g;
+  hts_status st = make_geo(p, C, H, W, g);
+  if (st != HTS_OK) return st;
+  if (!ws || !count) return HTS_ERR_INVALID;
+  const Carve c = carve(g);
+  if (ws_bytes < c.total) return HTS_ERR_WORKSPACE;
+  HIPCHK(hipMemcpyAsync(count, (const char*)ws + c.fb_count, sizeof(int32_t),
+                        hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return HTS_OK;
+}
+
+hts_status hts_batch_fallback_counts(const hts_params* p, const hts_image* imgs, int32_t n,
+                                     const void* ws, size_t ws_bytes, int32_t* counts,
+                                     void* stream) {
+  if (!ws || !counts) return HTS_ERR_INVALID;
+  BatchPlan plan;
+  hts_status st = plan_batch(p, imgs, n, (char*)ws, false, plan);
+  if (st != HTS_OK) return st;
+  if (ws_bytes < plan.bytes) return HTS_ERR_WORKSPACE;
+  for (int i = 0; i < n; ++i)
+    HIPCHK(hipMemcpyAsync(counts + i, plan.descs[i].fb_count, sizeof(int32_t),
+                          hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return HTS_OK;
+}
+
 hts_status hts_batch_workspace_size(const hts_params* p, const hts_image* imgs, int32_t n,
                                     size_t* bytes) {
   if (!bytes) return HTS_ERR_INVALID;
@@ -869,7 +901,7 @@ static hts_status denoise_batch_impl(const hts_params* p, const hts_image* imgs,
   const int C = imgs[0].C;
   ImgDesc* table = (ImgDesc*)((char*)ws + plan.table_off);
   std::lock_guard<std::mutex> lk(g_graph_mu);
-  const std::string key = graph_key(p, imgs, n, ws, ad != nullptr);
+  const std::string key = graph_key(p, plan.sc, imgs, n, ws, ad != nullptr);
   if (g_graphs.size() >= 64 && !g_graphs.count(key)) {
     // bounded cache: drop every entry (after the device is idle) and start over
     HIPCHK(hipDeviceSynchronize());

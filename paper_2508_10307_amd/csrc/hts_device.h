@@ -182,6 +182,21 @@ __device__ inline void flush_tile(const ImgDesc& d, const unsigned long long* ac
   }
 }
 
+// Cold path of the fused aggregation: an estimate of a patch that lies
+// outside the work group's LDS tile (a caller-given idx entry that is not
+// from its reference's search window) is added straight into the image
+// numerator, scaled like the tile values (fixed point, or a float numerator
+// when d.num64 is null).  pix is the pixel index y * W + x.
+__device__ inline void add_estimate_global(const ImgDesc& d, int ch, int pix, float v) {
+  if (d.num64) atomicAdd(d.num64 + (size_t)ch * d.H * d.W + pix, fx_from_float(v));
+  else atomicAdd(d.num + (size_t)ch * d.H * d.W + pix, v);
+}
+// The weight (fixed point, times WEIGHT_SCALE) of such a patch pixel.
+__device__ inline void add_weight_global(const ImgDesc& d, int pix, unsigned long long w) {
+  if (d.wsum64) atomicAdd(d.wsum64 + pix, w);
+  else if (d.cnt) atomicAdd(d.cnt + pix, (float)(fx_to_double(w) * (1.0 / WEIGHT_SCALE)));
+}
+
 // Guide quantisation: round_half_even(256 v) clamped to +-(2^20 - 1); NaN -> 0.
 __device__ inline int quantize(float v) {
   float r = rintf(v * 256.0f);

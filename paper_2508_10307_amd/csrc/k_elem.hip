@@ -172,10 +172,15 @@ __global__ __launch_bounds__(256) void k_count_hist(Launch L) {
     const int g = item * 256 + threadIdx.x;
     if (g < d.ref_begin || g >= d.ref_begin + d.ref_count) return;
     const int* row = d.idx + (size_t)g * L.K;
-    const int n = d.H * d.W;
+    const float rW = 1.0f / (float)d.W;
     for (int k = 0; k < L.K; ++k) {
-      const int pos = row[k];
-      if (pos >= 0 && pos < n) atomicAdd(d.hist + pos, 1);
+      // an entry that is not a valid patch corner counts at the nearest
+      // one, where the filters aggregate its estimate
+      int py, px;
+      split_pos(row[k], d.W, rW, py, px);
+      py = min(max(py, 0), d.Hp - 1);
+      px = min(max(px, 0), d.Wp - 1);
+      atomicAdd(d.hist + py * d.W + px, 1);
     }
   });
 }

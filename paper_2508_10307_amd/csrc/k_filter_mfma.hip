@@ -427,12 +427,17 @@ __global__ __launch_bounds__(256, K >= 32 ? 1 : 2) void k_filter_mfma(Launch L) 
             atomicAdd(a0, fx_from_float(o0));
             atomicAdd(a0 + RA * CA, fx_from_float(o1));
             atomicAdd(a0 + 2 * RA * CA, fx_from_float(o2));
-            if (d.group_est) {
-              float* ge = d.group_est + (((size_t)grel * K + k) * C) * PS2 + (4 * (q & 1) + j) * 8 + n8;
-              ge[0] = o0 * rfxs;
-              ge[PS2] = o1 * rfxs;
-              ge[2 * PS2] = o2 * rfxs;
-            }
+          } else if constexpr (!BATCH) {   // outside the tile's reach: straight to the image
+            const int pix = (py + 4 * (q & 1) + j) * d.W + px + n8;
+            add_estimate_global(d, 0, pix, o0);
+            add_estimate_global(d, 1, pix, o1);
+            add_estimate_global(d, 2, pix, o2);
+          }
+          if (d.group_est) {
+            float* ge = d.group_est + (((size_t)grel * K + k) * C) * PS2 + (4 * (q & 1) + j) * 8 + n8;
+            ge[0] = o0 * rfxs;
+            ge[PS2] = o1 * rfxs;
+            ge[2 * PS2] = o2 * rfxs;
           }
         }
       }

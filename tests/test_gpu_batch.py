@@ -121,3 +121,36 @@ def test_autotune_picks_a_valid_schedule_and_caches(tmp_path):
     ia = api.hts_match(T(y), api.Params(stride=3, window=31, K=32, tune=w))
     ib = api.hts_match(T(y), api.Params(stride=3, window=31, K=32, tune=1 | (1 << 4)))
     assert torch.equal(ia, ib)
+
+
+def test_graph_follows_a_schedule_changed_by_the_autotuner(tmp_path):
+    """tune = 0 takes the schedule from the autotune table; a batch call
+    after hts_autotune (here fed from a cache file) changes that table, and
+    the next tune = 0 call must run the new schedule, not replay the graph
+    captured for the old one.  The image shapes, parameters and workspace
+    stay the same across the three calls."""
+    p = api.Params(stride=3, window=13, K=16)
+    imgs, sig = make_batch(21)
+    xs = [T(y) for y in imgs]
+    outs = [torch.empty_like(x) for x in xs]
+    ws = torch.empty(api.batch_workspace_size(p, xs, outs, sig), dtype=torch.uint8,
+                     device=dev())
+    api.hts_denoise_batch(xs, sig, p, outs=outs, ws=ws)       # default schedule, graph cached
+    torch.cuda.synchronize()
+    first = [o.clone() for o in outs]
+    ref0 = eager(imgs, sig, p)
+    for o, r in zip(first, ref0):
+        assert torch.equal(o, r)
+    # a cached schedule for exactly these parameters: vector-ALU filter, 2x2
+    # reference tiles, BF16 hi/lo split (tune word (6 + 1) | 2 << 4 | 1 << 6)
+    word = 7 | (2 << 4) | (1 << 6)
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"{arch} C=3 s=3 w=13 K=16 mode=0 flags=0|{word}\n")
+    assert api.hts_autotune(p, 3, 96, 96, cache_path=str(cache)) == word
+    api.hts_denoise_batch(xs, sig, p, outs=outs, ws=ws)       # tune = 0 again
+    torch.cuda.synchronize()
+    ref = eager(imgs, sig, api.Params(stride=3, window=13, K=16, tune=word))
+    for i, (o, r) in enumerate(zip(outs, ref)):
+        log("after autotune", i, SHAPES[i], (o - r).abs().max().item())
+        assert torch.equal(o, r)

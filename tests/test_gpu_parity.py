@@ -89,6 +89,73 @@ def test_match_forced_ties():
             np.testing.assert_array_equal(idx.cpu().numpy(), idx_o)
 
 
+def _two_level(C, H, W):
+    # a two-level checkerboard: the half of a window in phase with the
+    # reference ties at distance 0, the other half at 64 * 160^2
+    yy, xx = np.mgrid[0:H, 0:W]
+    pat = np.where((yy + xx) % 2 == 0, 40.0, 200.0)
+    return np.repeat(pat[None], C, axis=0).astype(np.float32)
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["bf16", "fp32"])
+@pytest.mark.parametrize("kind", ["flat", "two_level", "half_flat"])
+@pytest.mark.parametrize("C", [1, 3])
+def test_match_overflowing_shortlists_take_the_exact_scan(C, kind, mode):
+    """Windows of 961 candidates (w = 31, K = 32) full of exact ties: the
+    certified shortlist of a reference cannot hold them all (it keeps every
+    candidate whose bound reaches the (K-1)-th smallest), so the reference
+    goes to the exact window scan.  Indices and distances stay bit-exact,
+    and the fallback count shows that the scan ran."""
+    H, W = 64, 72
+    if kind == "flat":
+        y = np.full((C, H, W), 93.5, np.float32)
+    elif kind == "two_level":
+        y = _two_level(C, H, W)
+    else:   # left part flat, right part noisy: both paths in one launch
+        y = synth.tiny(917 + C, C, H, W, sigma=20.0)
+        y[:, :, :30] = 93.5
+    log("overflow", C, kind, mode)
+    p = P(stride=3, window=31, K=32, match_mode=mode)
+    idx_o, dist_o, _ = omatch.match(y, 8, 3, 31, 32)
+    ws = api.workspace(p, C, H, W, dev())
+    idx, dist = api.hts_match(T(y), p, want_dist=True, ws=ws)
+    nfb = int(api.hts_match_fallback_count(p, C, H, W, ws).item())
+    log("fallback references", nfb, "of", len(idx_o))
+    np.testing.assert_array_equal(idx.cpu().numpy(), idx_o)
+    np.testing.assert_array_equal(dist.cpu().numpy(), dist_o)
+    if kind == "half_flat":
+        assert 0 < nfb < len(idx_o)
+    elif kind == "flat":
+        assert nfb == len(idx_o)
+    else:   # corner windows hold about 128 in-phase candidates, which fit
+        assert nfb >= len(idx_o) - 8
+
+
+def test_batch_with_overflowing_shortlists_equals_per_image():
+    """The exact-scan fallback inside the batched graph: flat and noisy
+    images together; batch outputs equal hts_denoise bit for bit and the
+    per-image fallback counts agree."""
+    p = P(stride=3, window=31, K=32)
+    imgs = [np.full((3, 48, 56), 120.0, np.float32), synth.tiny(31, 3, 64, 60, sigma=15.0),
+            _two_level(3, 40, 72), synth.tiny(32, 3, 50, 50, sigma=30.0)]
+    imgs[3][:, 10:40, 5:45] = 60.0
+    sig = [10.0, 15.0, 12.0, 30.0]
+    xs = [T(y) for y in imgs]
+    outs = [torch.empty_like(x) for x in xs]
+    wsb = torch.empty(api.batch_workspace_size(p, xs, outs, sig), dtype=torch.uint8,
+                      device=dev())
+    api.hts_denoise_batch(xs, sig, p, outs=outs, ws=wsb)
+    cb = api.hts_batch_fallback_counts(p, xs, outs, sig, wsb).cpu().numpy()
+    for i, (x, s) in enumerate(zip(xs, sig)):
+        ws = api.workspace(p, 3, x.shape[1], x.shape[2], dev())
+        o = api.hts_denoise(x, s, p, ws=ws)
+        ce = int(api.hts_match_fallback_count(p, 3, x.shape[1], x.shape[2], ws).item())
+        log("batch image", i, "fallback", int(cb[i]), ce)
+        assert torch.equal(o, outs[i])
+        assert int(cb[i]) == ce
+    assert cb[0] > 0 and cb[2] > 0 and cb[3] > 0
+
+
 def test_match_mixed_guide_planes_repeatable():
     # RGB tiles whose references mix the green and the R+G+B guide are
     # matched plane by plane; the references of the other plane must not
@@ -274,6 +341,50 @@ def test_filter_subrange_and_aggregate_match_denoise():
     S = of.haar_group(of.tsvd_forward(G, UF, VF), 8)
     est = of.tsvd_inverse(of.haar_group_inverse(np.where(masks[:half], S, 0.0), 8), UF, VF)
     assert np.abs(a["group_est"].cpu().numpy() - est).max() <= PIX_TOL
+
+
+@pytest.mark.parametrize("impl", [0, 1 << 6], ids=["mfma", "valu"])
+def test_filter_and_adjoint_take_an_idx_from_a_larger_window(impl):
+    """hts_filter and hts_denoise_backward accept any grouping: here the
+    groups of a window-25 match filtered with window-9 parameters, so many
+    patches lie outside the work group's accumulation tile (they go straight
+    to the image); entries that are not valid patch corners count at the
+    nearest one.  num / cnt and the frozen adjoint must equal the oracle's on
+    that grouping."""
+    y = synth.tiny(4242, 3, 56, 60, sigma=20.0)
+    x = T(y)
+    _, st = api.hts_denoise(x, 20.0, P(stride=3, window=25, K=16), save=True)
+    idx = st["idx"].cpu().numpy().astype(np.int64)
+    pn = P(stride=3, window=9, K=16, tune=impl)
+    r = api.hts_filter(x, 20.0, st["idx"], st["U"], st["V"], pn, want_masks=True)
+    torch.cuda.synchronize()
+    n_ref = len(idx)
+    masks = opipe.unpack_masks(r["masks"].cpu().numpy().view(np.uint32), n_ref, 16, 3)
+    o = opipe.denoise(y, 20.0, 8, 3, 9, 16, 2.7, idx=idx, U=st["U"].cpu().numpy(),
+                      V=st["V"].cpu().numpy(), mask=masks)
+    np.testing.assert_array_equal(r["cnt"].cpu().numpy(), o["cnt"])
+    err = np.abs(r["num"].cpu().numpy() / o["cnt"][None] - o["out"]).max()
+    log("filter with a window-25 idx under window-9 params", impl, err, o["n_override"])
+    assert err <= PIX_TOL
+    assert o["max_override_margin"] <= DELTA_REL * o["tau"]
+    # frozen adjoint on the same grouping
+    g = np.random.default_rng(5).normal(size=y.shape)
+    st2 = dict(st, masks=r["masks"], cnt=r["cnt"])
+    gin, _ = api.hts_denoise_backward(T(g), st2, pn)
+    ref = oadj.frozen_adjoint(g, idx, masks, st["U"].cpu().numpy(), st["V"].cpu().numpy(),
+                              o["cnt"], 16)
+    assert np.abs(gin.cpu().numpy() - ref).max() <= 1e-4 * max(1.0, np.abs(ref).max())
+    # entries past the last valid column count at the nearest valid corner
+    bad = st["idx"].clone()
+    Wd, Wp = 60, 60 - 7
+    sel = bad[:, 5] % Wd == Wp - 1
+    bad[sel, 5] += 3                      # x = W - 5: not a patch corner
+    rb = api.hts_filter(x, 20.0, bad, st["U"], st["V"], pn)
+    torch.cuda.synchronize()
+    assert sel.any().item()
+    assert torch.equal(rb["cnt"], r["cnt"])
+    # float atomics into num: the order of additions sets the last bits
+    assert (rb["num"] - r["num"]).abs().max().item() <= 1e-5 * r["num"].abs().max().item()
 
 
 # ---------------------------------------------------------------- adjoint

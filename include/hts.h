@@ -366,6 +366,22 @@ hts_status hts_denoise_backward(const hts_params* p, const float* grad_out,
                                 int32_t W, float* grad_in, float* grad_tau_mult, void* ws,
                                 size_t ws_bytes, void* stream);
 
+/* hts_denoise for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same stages and kernels, with the workspace taken from a fixed scratch
+ * array of HTS_NOALLOC_SCRATCH_BYTES in the library's device code object
+ * (one per GPU, held from the load of the library until the process ends)
+ * instead of a caller buffer.  noisy / out as in hts_denoise; no state is
+ * exported.  No device memory is allocated or freed by this call.
+ * Images whose hts_workspace_size exceeds the scratch (e.g. RGB above about
+ * 1024 x 1024 at K = 32, stride 3) return HTS_ERR_WORKSPACE and launch
+ * nothing.  Every call on a GPU uses that GPU's one scratch array, which
+ * keeps the last call's contents (each call clears what it reads first):
+ * calls that overlap on one GPU, from any stream or thread, race. */
+#define HTS_NOALLOC_SCRATCH_BYTES ((size_t)96 << 20)
+hts_status hts_denoise_noalloc(const hts_params* p, const float* noisy, int32_t C, int32_t H,
+                               int32_t W, float sigma, float* out, void* stream);
+
 /* Autotuner: time the launch schedules of the match and filter stages on
  * the current device for this parameter set and image shape, remember the
  * fastest (in memory, and in the cache file `cache_path` when non-null),

@@ -198,6 +198,17 @@ def hts_denoise_backward(grad_out, st, p: Params, ws=None):
     return gin, gtau
 
 
+def hts_denoise_noalloc(noisy: torch.Tensor, sigma: float, p: Params, out=None):
+    """hts_denoise on the library's fixed device scratch (no workspace)."""
+    x = _img(noisy)
+    C, H, W = x.shape
+    out = torch.empty_like(x) if out is None else out
+    pc = p.c()
+    L.check("hts_denoise_noalloc", L.load().hts_denoise_noalloc(
+        ctypes.byref(pc), _ptr(x), C, H, W, float(sigma), _ptr(out), _stream(x.device)))
+    return out
+
+
 def hts_match_fallback_count(p: Params, C: int, H: int, W: int, ws: torch.Tensor) -> torch.Tensor:
     """References of the last hts_match / hts_denoise on workspace ws whose
     certified shortlist overflowed (matched by the exact window scan).

@@ -4,15 +4,20 @@ One step = Algorithm 1 (grouping, global basis, collaborative filtering,
 aggregation) over every image of the batched workload: 64 RGB images with
 sides drawn from {256, 384, 512, 768, 1024} and sigma ~ U[5, 50] (synthetic
 stand-ins for the paper's photo datasets), ps 8, stride 3, window 31, K 32,
-lambda 2.7.  Inputs are resident in HBM before the timed region.
+lambda 2.7, through hts_denoise_batch (one captured graph per step).  Inputs
+are resident in HBM before the timed region.
 
 Prints one JSON line: the BF16-match throughput (value), the plain FP32-path
-throughput and their ratio at equal PSNR, achieved HBM GB/s, a roofline
-entry for the dominant kernel (the fused filter, timed live with HIP
-events on its stream) and the FP64 oracle timed on a bounded CPU sample.
+throughput and their ratio at equal PSNR, achieved HBM GB/s, roofline
+entries for the fused filter (the dominant kernel) and for the BF16 match,
+both timed with HIP events on the stream their batched launch runs on, the
+shortlist fallback and threshold-override counts, the 24 MPix single image
+and the differentiable 16-image configuration, and the FP64 oracle timed on
+bounded CPU samples.
 """
 import argparse
 import ctypes
+import hashlib
 import json
 import os
 import subprocess
@@ -32,15 +37,19 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--stage-steps", type=int, default=3,
+                    help="stage-by-stage batches timed for the roofline entries")
     ap.add_argument("--workload", default="batch64",
                     choices=["batch64", "rgb512", "gray256", "large24"])
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-path comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-adaptive", action="store_true",
+    ap.add_argument("--no-extensions", "--no-adaptive", dest="no_extensions",
+                    action="store_true",
                     help="skip the A-Haar-tSVD, weighted-aggregation, Fourier-threshold, "
                          "spectral-tube and video timings")
-    ap.add_argument("--batch-api", type=int, default=1,
-                    help="1: hts_denoise_batch (one graph); 0: one hts_denoise per image")
+    ap.add_argument("--no-large", action="store_true", help="skip the 4000x6000 RGB image")
+    ap.add_argument("--no-diff", action="store_true",
+                    help="skip the 16 x 512^2 RGB forward + adjoint timing")
     ap.add_argument("--tune", type=int, default=0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device three times and exit (the "
@@ -54,86 +63,198 @@ def workload(name):
             "large24": synth.large_24mpix}[name]()
 
 
+# ---------------------------------------------------------------- work models
 def filter_flops_per_group(C, K):
-    """Algorithmic flops of Eq. 18-20 for one group, computed per group
-    ("direct" form): K * 2 * T (forward and inverse projection of every slot,
-    T = 2048 flops for c = 1, 11776 for c = 3: the real f = 0 pair, the complex
-    f = 1 pair and the 3-point DFT / IDFT) + 2 * 2K c 64 (Haar and its inverse,
-    fast form) + 2 K c 64 (threshold and accumulation)."""
+    """Flops of Eq. 18-20 for one group computed per group ("direct"):
+    K * 2 * T (forward and inverse projection of every slot; T = 2048 for
+    c = 1, 11776 for c = 3: the real f = 0 pair, the complex f = 1 pair and the
+    3-point DFT / IDFT) + 2 * 2K c 64 (Haar and its inverse, fast form)
+    + 2 K c 64 (threshold and accumulation)."""
     T = 2048 if C == 1 else 11776
     return K * 2 * T + 2 * 2 * K * C * 64 + 2 * K * C * 64
 
 
 def filter_flops_reorg(C, K, H, W, n_ref):
-    """The same result with the linear projection done once per valid patch
-    position instead of once per slot (the least work any realisation needs)."""
+    """The least work any realisation needs: the (linear, global)
+    projection once per valid patch position instead of once per slot, plus
+    the per-group Haar, threshold and accumulation."""
     T = 2048 if C == 1 else 11776
     return (H - 7) * (W - 7) * 2 * T + n_ref * (2 * 2 * K * C * 64 + 2 * K * C * 64)
 
 
-def kernel_name(C, K, valu):
-    """rocprofv3 name of the single-image (eager) forward filter launch."""
+def ref_positions(n_valid, s):
+    pos = list(range(0, n_valid, s))
+    if pos[-1] != n_valid - 1:
+        pos.append(n_valid - 1)
+    return pos
+
+
+def window_candidates(H, W, s, w):
+    """Candidates of every reference's truncated window (the reference
+    itself excluded), summed over the reference grid; separable per axis."""
+    r = (w - 1) // 2
+
+    def axis(n):
+        pos = ref_positions(n, s)
+        return sum(min(n - 1, p + r) - max(0, p - r) + 1 for p in pos), len(pos)
+
+    sy, ny = axis(H - 7)
+    sx, nx = axis(W - 7)
+    return sy * sx - ny * nx, ny * nx
+
+
+def filter_kernel_name(C, K, valu, batch):
+    b = 1 if batch else 0
     if valu:
         spl = {2: 1, 4: 1, 8: 1, 16: 2, 32: 4, 64: 8}[K]
-        return f"void hts::k_filter<{C}, {spl}, 0, 0, 0, 0, 0>(hts::Launch)"
-    return f"void hts::k_filter_mfma<{K}, 0, 0, 0>(hts::Launch)"
+        return f"void hts::k_filter<{C}, {spl}, 0, 0, {b}, 0, 0>(hts::Launch)"
+    return f"void hts::k_filter_mfma<{K}, 0, 0, {b}>(hts::Launch)"
 
 
-# HBM traffic of the filter launches timed for the roofline, from two
-# rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE; KiB per
-# dispatch, averaged over the 64 eager launches) scaled by the factor the same
-# counters give for a plain device copy of known size.  Valid only for the
-# kernel sources they were taken on (SHA-256 over the files below).
-TRAFFIC_SOURCES = ["paper_2508_10307_amd/csrc/k_filter.hip",
+def match_kernel_name(C, s, w, mode, terms):
+    """The instantiation launch_match picks (LDS geometry of a 4x4 reference
+    tile: two guide-plane slots when they fit beside a second work group;
+    lower bounds cached in registers for up to 36 blocks per wavefront)."""
+    def geom(npl):
+        r = (w - 1) // 2
+        ryc, rxc = 3 * s + 2 * r + 1, 3 * s + 2 * r + 1
+        rxp = (rxc + 7) // 8 * 8
+        ry2 = (ryc + 1) // 2 * 2
+        pitch = rxp + 7
+        pitch += ((8 - pitch) % 16 + 16) % 16
+        rgn = (ry2 + 7) * pitch * 4
+        plane = 2 * rgn + 2 * ry2 * rxp * 4
+        return npl * plane + max(16 * 64 * 2 * 4, 16 * 128 * 4) + 768, ryc, rxp
+    npl = 2 if C == 3 and geom(2)[0] <= 80 * 1024 else 1
+    _, ryc, rxp = geom(npl)
+    cache = 1 if ((ryc + 1) // 2 * (rxp // 8) + 3) // 4 <= 36 else 0
+    m, t = (1, 1) if mode == 1 else (0, terms)
+    return f"void hts::k_match<{m}, {t}, {cache}, {npl}>(hts::Launch)"
+
+
+# ---------------------------------------------------------------- counters
+# Figures that only a profiler run gives, per kernel, from the rocprofv3
+# summaries in profiles/: HBM bytes per launch (FETCH_SIZE x 2 + WRITE_SIZE,
+# calibrated on a plain device copy) and MfmaUtil.  Each holds only for the
+# kernel sources it was taken on (SHA-256 over the files below).
+PROFILE_SOURCES = ["paper_2508_10307_amd/csrc/k_filter.hip",
                    "paper_2508_10307_amd/csrc/filter_valu.h",
                    "paper_2508_10307_amd/csrc/k_filter_mfma.hip",
+                   "paper_2508_10307_amd/csrc/k_match.hip",
                    "paper_2508_10307_amd/csrc/hts_device.h",
                    "paper_2508_10307_amd/csrc/hts_internal.h"]
-TRAFFIC = {    # kernel name -> (sources sha256, bytes per launch)
-    "void hts::k_filter<3, 4, 0, 0, 0, 0, 0>(hts::Launch)":
-        ("8d72426f6c5f232e17577a578c9416c967b4f27c9ce1e0a7787e6e3e7160fb68", 58522454),
-}
+PROFILED = {}   # kernel name -> (sources sha256, {"hbm_bytes": ..., "mfma_util_pct": ...})
 
 
 def sources_sha():
-    import hashlib
     h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
+    for f in PROFILE_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def cpu_baseline(wl_name):
-    """Oracle (plain FP64 NumPy) on a bounded sample: the top-left crop of at
-    most 384x384 pixels of the workload's first image (about 10-15 s of CPU
-    work), in a single-threaded child process."""
-    code = r"""
-import os, sys, time, json
+def profiled(kernel, key):
+    e = PROFILED.get(kernel)
+    if e and e[0] == sources_sha():
+        return e[1].get(key)
+    return None
+
+
+# ---------------------------------------------------------------- CPU baseline
+ORACLE_CHILD = r"""
+import sys, time, json
 sys.path.insert(0, %r)
 import numpy as np
 from paper_2508_10307_amd import synth
 from oracle import pipeline
 wl = {"batch64": synth.batch64, "rgb512": synth.rgb_512_pg, "gray256": synth.gray_256,
       "large24": synth.large_24mpix}[%r]()
-im, q = wl.images[0], wl.params
-y = np.ascontiguousarray(im.noisy[:, :384, :384])
+im, q = wl.images[%d %% len(wl.images)], wl.params
+y = np.ascontiguousarray(im.noisy[:, :%d, :%d])
 t = time.perf_counter()
 pipeline.denoise(y, im.sigma, q.ps, q.stride, q.window, q.K, q.tau_mult)
 dt = time.perf_counter() - t
-print(json.dumps({"sec": dt, "mpix": y.shape[1] * y.shape[2] / 1e6, "h": y.shape[1], "w": y.shape[2]}))
-""" % (ROOT, wl_name)
-    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
-                       timeout=600)
-    if r.returncode != 0:
-        return {"error": r.stderr[-400:]}
-    d = json.loads(r.stdout.strip().splitlines()[-1])
-    return {"value": d["mpix"] / d["sec"], "unit": "MPix/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle denoise of the {d['h']}x{d['w']} top-left crop of image 0 "
-                      f"({d['sec']:.1f} s, one thread)"}
+print(json.dumps({"sec": dt, "mpix": y.shape[1] * y.shape[2] / 1e6, "h": y.shape[1],
+                  "w": y.shape[2]}))
+"""
 
 
+def _oracle_children(wl_name, crops, threads=1):
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads), OPENBLAS_NUM_THREADS=str(threads),
+               MKL_NUM_THREADS=str(threads))
+    procs = [subprocess.Popen([sys.executable, "-c", ORACLE_CHILD % (ROOT, wl_name, i, h, w)],
+                              stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env)
+             for i, (h, w) in enumerate(crops)]
+    res = []
+    for p in procs:
+        out, err = p.communicate(timeout=900)
+        if p.returncode != 0:
+            raise RuntimeError(err[-400:])
+        res.append(json.loads(out.strip().splitlines()[-1]))
+    return res
+
+
+def cpu_baseline(wl_name):
+    """The FP64 oracle (plain NumPy, test infrastructure) on bounded samples
+    of the workload: one thread on the 384x384 top-left crop of image 0, and
+    all cores (one single-threaded process per core, at most 16, the CPU
+    share of one GPU) on the 256x256 top-left crops of images 0..n-1, timed
+    from the first start to the last end."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    try:
+        one = _oracle_children(wl_name, [(384, 384)])[0]
+        n = max(1, min(16, avail))
+        t0 = time.perf_counter()
+        many = _oracle_children(wl_name, [(256, 256)] * n)
+        wall = time.perf_counter() - t0
+    except Exception as e:   # noqa: BLE001 - report, do not fail the bench line
+        return {"error": str(e)[-400:]}
+    mp = sum(r["mpix"] for r in many)
+    return {"value": round(mp / wall, 5), "unit": "MPix/s", "cores": n, "kind": "oracle",
+            "sample": f"{n} single-threaded processes, oracle denoise of the 256x256 top-left "
+                      f"crop of images 0..{n - 1} ({wall:.1f} s wall for {mp:.3f} MPix)",
+            "cpu": f"{model}, {os.cpu_count()} logical CPUs, {avail} available",
+            "single_thread": {"value": round(one["mpix"] / one["sec"], 5), "unit": "MPix/s",
+                              "cores": 1,
+                              "sample": f"384x384 top-left crop of image 0 ({one['sec']:.1f} s)"}}
+
+
+def parity_sample(wl, dev):
+    """The GPU against the oracle on the 256x256 top-left crop of image 0:
+    match indices (bit-exact), and the denoised crop with the oracle's own
+    match and basis and the GPU's keep-masks where the two disagree
+    (threshold-kink overrides, counted with their largest margin)."""
+    import numpy as np
+    import torch
+    from oracle import pipeline
+    from paper_2508_10307_amd import api
+    im, q = wl.images[0], wl.params
+    y = np.ascontiguousarray(im.noisy[:, :256, :256])
+    p = api.Params(stride=q.stride, window=q.window, K=q.K, tau_mult=q.tau_mult)
+    out, st = api.hts_denoise(torch.from_numpy(y).to(dev), im.sigma, p, save=True)
+    idx = st["idx"].cpu().numpy().astype(np.int64)
+    C = y.shape[0]
+    masks = pipeline.unpack_masks(st["masks"].cpu().numpy().view(np.uint32), len(idx), q.K, C)
+    r = pipeline.denoise(y, im.sigma, q.ps, q.stride, q.window, q.K, q.tau_mult, mask=masks)
+    return {"crop": [C, 256, 256], "idx_bit_exact": bool(np.array_equal(idx, r["idx"])),
+            "max_abs_pixel_err": float(np.abs(out.cpu().numpy() - r["out"]).max()),
+            "threshold_overrides": int(r["n_override"]),
+            "coefficients": int(masks.size),
+            "max_override_margin_over_tau": float(r["max_override_margin"] / r["tau"])
+            if r["tau"] > 0 else 0.0,
+            "basis": "oracle's own (FP64 eigh)"}
+
+
+# ---------------------------------------------------------------- main
 def main():
     args = parse()
     if args.gpus != 1:
@@ -155,12 +276,15 @@ def main():
     from paper_2508_10307_amd import _lib as L
     from paper_2508_10307_amd import api
 
+    def note(*a):
+        print("#", *a, file=sys.stderr, flush=True)
+
     dev = torch.device("cuda:0")
     t0 = time.time()
     wl = workload(args.workload)
     q = wl.params
-    print(f"# workload {wl.name}: {len(wl.images)} images, {wl.mpix:.2f} MPix "
-          f"(generated in {time.time() - t0:.1f} s)", file=sys.stderr, flush=True)
+    note(f"workload {wl.name}: {len(wl.images)} images, {wl.mpix:.2f} MPix "
+         f"(generated in {time.time() - t0:.1f} s)")
     xs = [torch.from_numpy(im.noisy).to(dev) for im in wl.images]
     sig = [im.sigma for im in wl.images]
     outs = [torch.empty_like(x) for x in xs]
@@ -175,33 +299,17 @@ def main():
         tw = max(x.shape[2] for x in xs)
         tune = api.hts_autotune(api.Params(stride=q.stride, window=q.window, K=q.K,
                                            tau_mult=q.tau_mult), C, th, tw)
-        print(f"# autotuned schedule {tune} in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+        note(f"autotuned schedule {tune} in {time.time() - t0:.1f} s")
 
     def params(mode):
         return api.Params(stride=q.stride, window=q.window, K=q.K, tau_mult=q.tau_mult,
                           match_mode=mode, tune=tune)
 
-    def make_runner(mode):
-        p = params(mode)
-        if args.batch_api:
-            ws = torch.empty(api.batch_workspace_size(p, xs, outs, sig), dtype=torch.uint8,
-                             device=dev)
-            return lambda: api.hts_denoise_batch(xs, sig, p, outs=outs, ws=ws)
-        wss = [api.workspace(p, C, x.shape[1], x.shape[2], dev) for x in xs]
-        pc = p.c()
-        lib = L.load()
+    def batch_ws(p):
+        return torch.empty(api.batch_workspace_size(p, xs, outs, sig), dtype=torch.uint8,
+                           device=dev)
 
-        def run():
-            stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
-            for x, o, s, ws in zip(xs, outs, sig, wss):
-                st = lib.hts_denoise(ctypes.byref(pc), ctypes.c_void_p(x.data_ptr()), C,
-                                     x.shape[1], x.shape[2], float(s), ctypes.c_void_p(o.data_ptr()),
-                                     None, None, None, None, None, ctypes.c_void_p(ws.data_ptr()),
-                                     ws.numel(), stream)
-                L.check("hts_denoise", st)
-        return run
-
-    def timed(run, steps, warmup):
+    def timed(run, steps, warmup, label):
         for _ in range(warmup):
             run()
         torch.cuda.synchronize()
@@ -209,7 +317,7 @@ def main():
         e0.record()
         for i in range(steps):
             run()
-            print(f"# step {i + 1}/{steps}", file=sys.stderr, flush=True)
+            note(f"{label} step {i + 1}/{steps}")
         e1.record()
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / steps
@@ -221,73 +329,126 @@ def main():
             n += im.clean.size
         return 10 * np.log10(255.0 ** 2 / (tot / n))
 
-    run_bf16 = make_runner(L.HTS_MATCH_BF16)
-    ms = timed(run_bf16, args.steps, args.warmup)
+    # ---- headline: hts_denoise_batch (one graph replay per step) ----
+    p16 = params(L.HTS_MATCH_BF16)
+    ws16 = batch_ws(p16)
+    ms = timed(lambda: api.hts_denoise_batch(xs, sig, p16, outs=outs, ws=ws16), args.steps,
+               args.warmup, "bf16")
     psnr_bf16 = psnr_all()
     out_bf16 = [o.clone() for o in outs]
+    fb = api.hts_batch_fallback_counts(p16, xs, outs, sig, ws16).cpu().numpy()
     mpix = wl.mpix
     value = mpix / (ms / 1e3)
 
     fp32 = None
+    p32 = params(L.HTS_MATCH_FP32)
     if not args.no_fp32:
-        run_fp32 = make_runner(L.HTS_MATCH_FP32)
-        ms32 = timed(run_fp32, max(1, args.steps // 2), 1)
+        ws32 = batch_ws(p32)
+        ms32 = timed(lambda: api.hts_denoise_batch(xs, sig, p32, outs=outs, ws=ws32),
+                     max(1, args.steps // 2), 1, "fp32")
         psnr_fp32 = psnr_all()
         same = all(torch.equal(a, b) for a, b in zip(out_bf16, outs))
-        fp32 = {"value": mpix / (ms32 / 1e3), "ms_per_step": ms32, "psnr_db": psnr_fp32,
-                "outputs_bitwise_equal": same, "speedup_bf16_vs_fp32": ms32 / ms}
+        fp32 = {"value": round(mpix / (ms32 / 1e3), 3), "ms_per_step": round(ms32, 3),
+                "psnr_db": round(psnr_fp32, 4), "outputs_bitwise_equal": same,
+                "speedup_bf16_vs_fp32": round(ms32 / ms, 4), "target_speedup": 3.0}
+        del ws32
 
-    # ---- A-Haar-tSVD: the same batch with the noise-level vote per image ----
-    # (each image is its own sub-image, sigma_est = its noise level, 16 sampled
-    # groups per image drawn with seed 0; adds one vote kernel to the graph)
-    adaptive = None
-    if not args.no_adaptive and args.batch_api:
+    # ---- stage-by-stage batches: the same kernels launched one by one on
+    # the current stream, HIP events at the stage boundaries ----
+    def staged(p, steps):
+        ws = batch_ws(p)
+        tot = np.zeros(len(api.BATCH_STAGES))
+        for i in range(steps + 1):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
+            api.hts_denoise_batch_staged(xs, sig, p, outs, ws, ev)
+            torch.cuda.synchronize()
+            if i > 0:   # the first batch warms up
+                tot += [ev[k].elapsed_time(ev[k + 1]) for k in range(6)]
+        same = all(torch.equal(a, b) for a, b in zip(out_bf16, outs))
+        return dict(zip(api.BATCH_STAGES, (tot / steps).tolist())), same
+
+    stage16, same16 = staged(p16, args.stage_steps)
+    note("stages bf16 " + json.dumps({k: round(v, 3) for k, v in stage16.items()}))
+    stage32 = None
+    if not args.no_fp32:
+        stage32, _ = staged(p32, args.stage_steps)
+        note("stages fp32 " + json.dumps({k: round(v, 3) for k, v in stage32.items()}))
+
+    # ---- roofline of the dominant kernel: the batched fused filter ----
+    valu = ((tune >> 6) & 3) == 1 or C != 3 or q.K not in (4, 8, 16, 32)
+    n_refs, cands, freorg, fdirect, fbytes = 0, 0, 0.0, 0.0, 0.0
+    for x in xs:
+        _, H, W = x.shape
+        c, n = window_candidates(H, W, q.stride, q.window)
+        cands += c
+        n_refs += n
+        freorg += filter_flops_reorg(C, q.K, H, W, n)
+        fdirect += n * filter_flops_per_group(C, q.K)
+        fbytes += C * H * W * 4 * 2 + n * q.K * 4    # read y + idx, write the numerator
+    fk = filter_kernel_name(C, q.K, valu, True)
+    f_ms = stage16["filter"]
+    achieved = freorg / (f_ms / 1e3) / 1e12
+    roof = {"kernel": fk, "bound": "alu", "achieved": round(achieved, 3),
+            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+            "traffic": profiled(fk, "hbm_bytes"),
+            "avg_launch_ms": round(f_ms, 4), "launches": args.stage_steps,
+            "flops_per_launch": freorg,
+            "flops_model": "reorg: Eq. 18 projection once per valid patch position + per-group "
+                           "Haar, threshold and accumulation",
+            "achieved_direct_count": round(fdirect / (f_ms / 1e3) / 1e12, 3),
+            "algorithmic_bytes_per_launch": fbytes,
+            "achieved_hbm_gbps_algorithmic": round(fbytes / (f_ms / 1e3) / 1e9, 2)}
+    mk = match_kernel_name(C, q.stride, q.window, 0, 1 if ((tune >> 4) & 3) == 1 else 3)
+    m_ms = stage16["match"]
+    mflops = 2.0 * 64 * cands
+    m_ach = mflops / (m_ms / 1e3) / 1e12
+    match_roof = {"kernel": mk, "bound": "mfma", "achieved": round(m_ach, 3),
+                  "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                  "frac": round(m_ach / PEAK_BF16_TFLOPS, 5), "avg_launch_ms": round(m_ms, 4),
+                  "flops_per_launch": mflops,
+                  "flops_model": "2 * 64 per (reference, candidate of its truncated window), "
+                                 "dot form with exact norms",
+                  "candidates": cands, "references": n_refs,
+                  "mfma_util_pct": profiled(mk, "mfma_util_pct"),
+                  "target_frac": 0.5}
+    if stage32:
+        match_roof["fp32_ssd_ms"] = round(stage32["match"], 4)
+        match_roof["stage_speedup_bf16_vs_fp32"] = round(stage32["match"] / m_ms, 3)
+
+    ext = {}
+    if not args.no_extensions:
+        # ---- A-Haar-tSVD: the same batch with the noise-level vote per image
+        # (each image its own sub-image, sigma_est = its noise level, 16
+        # sampled groups per image drawn with seed 0) ----
         pa = params(L.HTS_MATCH_BF16)
         subs = [(0, 0, x.shape[1], x.shape[2]) for x in xs]
         smp = torch.from_numpy(api.draw_samples(subs, pa, 16, seed=0)).to(dev)
-        ws_a = torch.empty(api.batch_workspace_size(pa, xs, outs, sig), dtype=torch.uint8,
-                           device=dev)
+        ws_a = batch_ws(pa)
         res = {}
 
         def run_ad():
             res["r"] = api.hts_denoise_batch_adaptive(xs, sig, smp, pa, outs=outs, ws=ws_a)
 
-        msa = timed(run_ad, max(1, args.steps // 2), 1)
+        msa = timed(run_ad, max(1, args.steps // 2), 1, "adaptive")
         sh = res["r"][1].cpu().numpy()
-        adaptive = {"value": mpix / (msa / 1e3), "ms_per_step": round(msa, 3),
-                    "overhead_ms": round(msa - ms, 3), "n_samples": 16,
-                    "images_adjusted": int(sum(1 for a, b in zip(sh, sig)
-                                               if abs(float(a) - float(b)) > 0))}
+        ext["adaptive"] = {"value": round(mpix / (msa / 1e3), 3), "ms_per_step": round(msa, 3),
+                           "overhead_ms": round(msa - ms, 3), "n_samples": 16,
+                           "images_adjusted": int(sum(1 for a, b in zip(sh, sig)
+                                                      if abs(float(a) - float(b)) > 0))}
         del ws_a
-
-    # ---- weighted aggregation (Eq. 2 with w_g = 1/max(1, kept coefficients)) ----
-    weighted = fourier = None
-    if not args.no_adaptive and args.batch_api:
-        pw = params(L.HTS_MATCH_BF16)
-        pw.flags = L.HTS_FLAG_WEIGHTED
-        ws_w = torch.empty(api.batch_workspace_size(pw, xs, outs, sig), dtype=torch.uint8,
-                           device=dev)
-        msw = timed(lambda: api.hts_denoise_batch(xs, sig, pw, outs=outs, ws=ws_w),
-                    max(1, args.steps // 2), 1)
-        weighted = {"value": mpix / (msw / 1e3), "ms_per_step": round(msw, 3),
-                    "psnr_db": round(psnr_all(), 4)}
-        del ws_w
-        # channel-Fourier magnitude threshold (whole conjugate pairs)
-        pf = params(L.HTS_MATCH_BF16)
-        pf.flags = L.HTS_FLAG_FOURIER_THRESHOLD
-        ws_f = torch.empty(api.batch_workspace_size(pf, xs, outs, sig), dtype=torch.uint8,
-                           device=dev)
-        msf = timed(lambda: api.hts_denoise_batch(xs, sig, pf, outs=outs, ws=ws_f),
-                    max(1, args.steps // 2), 1)
-        fourier = {"value": mpix / (msf / 1e3), "ms_per_step": round(msf, 3),
-                   "psnr_db": round(psnr_all(), 4)}
-        del ws_f
-
-    # ---- spectral tubes: one HSI-shaped image (520 x 696 x 34 bands, the
-    # size of the paper's real-HSI scenes), synthetic, AWGN sigma = 25, the
-    # same method parameters; general band-count path of hts_denoise ----
-    tubes = None
-    if not args.no_adaptive:
+        # ---- weighted aggregation and the channel-Fourier threshold ----
+        for key, flag in (("weighted", L.HTS_FLAG_WEIGHTED),
+                          ("fourier_threshold", L.HTS_FLAG_FOURIER_THRESHOLD)):
+            pf = params(L.HTS_MATCH_BF16)
+            pf.flags = flag
+            ws_f = batch_ws(pf)
+            msf = timed(lambda: api.hts_denoise_batch(xs, sig, pf, outs=outs, ws=ws_f),
+                        max(1, args.steps // 2), 1, key)
+            ext[key] = {"value": round(mpix / (msf / 1e3), 3), "ms_per_step": round(msf, 3),
+                        "psnr_db": round(psnr_all(), 4)}
+            del ws_f
+        # ---- spectral tubes: one 520 x 696 x 34 image (the size of the
+        # paper's real-HSI scenes), synthetic, AWGN sigma = 25 ----
         from paper_2508_10307_amd import synth
         Ct, Ht, Wt = 34, 520, 696
         clean_t = synth.clean_image(4242, 0, Ct, Ht, Wt, 40)
@@ -299,20 +460,15 @@ def main():
         def run_t():
             res_t["o"] = api.hts_denoise(xt, 25.0, pt, ws=ws_t)
 
-        mst = timed(run_t, 3, 1)
+        mst = timed(run_t, 3, 1, "tubes")
         mse_t = float(((res_t["o"].double().cpu().numpy() - clean_t) ** 2).mean())
-        tubes = {"value": round(Ht * Wt / 1e6 / (mst / 1e3), 3), "unit": "MPix/s",
-                 "ms_per_image": round(mst, 3), "shape": [Ct, Ht, Wt],
-                 "psnr_db": round(10 * np.log10(255.0 ** 2 / mse_t), 4)}
+        ext["spectral_tubes"] = {"value": round(Ht * Wt / 1e6 / (mst / 1e3), 3), "unit": "MPix/s",
+                                 "ms_per_image": round(mst, 3), "shape": [Ct, Ht, Wt],
+                                 "psnr_db": round(10 * np.log10(255.0 ** 2 / mse_t), 4)}
         del ws_t, xt
-
-    # ---- video: 8 synthetic 540 x 960 RGB frames (the frame size of the
-    # paper's Set8 clips) of one scene translating by (1, 2) px per frame,
-    # AWGN sigma = 25 drawn per frame, spatio-temporal search over frames
-    # t-2..t+2, K = 32, w = 21 ----
-    vid = None
-    if not args.no_adaptive:
-        from paper_2508_10307_amd import synth
+        # ---- video: 8 synthetic 540 x 960 RGB frames (the frame size of the
+        # paper's Set8 clips) of one scene translating by (1, 2) px per frame,
+        # AWGN sigma = 25 per frame, search over frames t-2..t+2, K 32, w 21 ----
         Tv, Hv, Wv = 8, 540, 960
         clean_v = synth.clean_video(4343, Tv, 3, Hv, Wv, 40)
         xv = torch.from_numpy(np.stack([synth.add_awgn(4343, t, clean_v[t], 25.0)
@@ -323,76 +479,91 @@ def main():
         def run_v():
             res_v["o"] = api.hts_denoise_video(xv, 25.0, pv, dt=2)
 
-        msv = timed(run_v, 2, 1)
+        msv = timed(run_v, 2, 1, "video")
         mse_v = float(((res_v["o"].double().cpu().numpy() - clean_v) ** 2).mean())
-        vid = {"value": round(Tv * Hv * Wv / 1e6 / (msv / 1e3), 3), "unit": "MPix/s",
-               "ms_per_clip": round(msv, 3), "shape": [Tv, 3, Hv, Wv], "dt": 2,
-               "psnr_db": round(10 * np.log10(255.0 ** 2 / mse_v), 4)}
+        ext["video"] = {"value": round(Tv * Hv * Wv / 1e6 / (msv / 1e3), 3), "unit": "MPix/s",
+                        "ms_per_clip": round(msv, 3), "shape": [Tv, 3, Hv, Wv], "dt": 2,
+                        "psnr_db": round(10 * np.log10(255.0 ** 2 / mse_v), 4)}
         del xv
 
-    # ---- roofline of the dominant kernel: the fused filter, timed live ----
-    # One eager launch per image (the same filter the batched graph runs, as
-    # its single-image instantiation), timed with HIP events on its stream:
-    # hts_filter without num/cnt runs the Fourier-slice kernel (a few us) and
-    # the filter, which adds into the workspace.  The per-image matches are
-    # timed alongside for the stage ratio.
-    p = params(L.HTS_MATCH_BF16)
-    pc = p.c()
-    p32 = params(L.HTS_MATCH_FP32).c()
-    lib = L.load()
-    stream_h = torch.cuda.current_stream(dev)
-    sh = ctypes.c_void_p(stream_h.cuda_stream)
-    ftime, fflops, freorg, mtime, mtime32 = 0.0, 0.0, 0.0, 0.0, 0.0
-    for x, s in zip(xs, sig):
-        Cx, H, W = x.shape
-        ws = api.workspace(p, Cx, H, W, dev)
-        ny, nx = api.ref_grid(H, W, p)
-        idx = torch.empty((ny * nx, p.K), dtype=torch.int32, device=dev)
-        U = torch.empty((Cx, 8, 8), device=dev)
-        V = torch.empty_like(U)
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
-        ev[0].record(stream_h)
-        L.check("hts_match", lib.hts_match(ctypes.byref(p32), ctypes.c_void_p(x.data_ptr()), Cx, H, W,
-                                           ctypes.c_void_p(idx.data_ptr()), None, None,
-                                           ctypes.c_void_p(ws.data_ptr()), ws.numel(), sh))
-        ev[1].record(stream_h)
-        ev[2].record(stream_h)
-        L.check("hts_match", lib.hts_match(ctypes.byref(pc), ctypes.c_void_p(x.data_ptr()), Cx, H, W,
-                                           ctypes.c_void_p(idx.data_ptr()), None, None,
-                                           ctypes.c_void_p(ws.data_ptr()), ws.numel(), sh))
-        ev[3].record(stream_h)
-        L.check("hts_basis", lib.hts_basis(ctypes.byref(pc), ctypes.c_void_p(x.data_ptr()), Cx, H, W,
-                                           ctypes.c_void_p(U.data_ptr()), ctypes.c_void_p(V.data_ptr()),
-                                           None, None, None, ctypes.c_void_p(ws.data_ptr()),
-                                           ws.numel(), sh))
-        ev[4].record(stream_h)
-        L.check("hts_filter", lib.hts_filter(
-            ctypes.byref(pc), ctypes.c_void_p(x.data_ptr()), Cx, H, W, float(s),
-            ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(U.data_ptr()),
-            ctypes.c_void_p(V.data_ptr()), 0, ny * nx, None, None, None, None,
-            ctypes.c_void_p(ws.data_ptr()), ws.numel(), sh))
-        ev[5].record(stream_h)
-        torch.cuda.synchronize()
-        mtime32 += ev[0].elapsed_time(ev[1])
-        mtime += ev[2].elapsed_time(ev[3])
-        ftime += ev[4].elapsed_time(ev[5])
-        fflops += ny * nx * filter_flops_per_group(Cx, q.K)
-        freorg += filter_flops_reorg(Cx, q.K, H, W, ny * nx)
-    n_launch = len(xs)
-    avg_ms = ftime / n_launch
-    flops_launch = fflops / n_launch
-    achieved = flops_launch / (avg_ms / 1e3) / 1e12
-    valu = ((tune >> 6) & 3) == 1 or C != 3 or q.K not in (4, 8, 16, 32)
-    kname = kernel_name(C, q.K, valu)
-    traffic = None
-    if kname in TRAFFIC and TRAFFIC[kname][0] == sources_sha():
-        traffic = TRAFFIC[kname][1]
-    roof = {"kernel": kname, "bound": "alu", "achieved": round(achieved, 2),
-            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
-            "avg_launch_ms": round(avg_ms, 4), "flops_per_launch": flops_launch,
-            "flops_model": "Eq. 18-20 per group (direct)", "launches": n_launch,
-            "achieved_reorg_equiv": round(freorg / n_launch / (avg_ms / 1e3) / 1e12, 2)}
+    # ---- the 24 MPix single image (RGB 4000 x 6000, 400 blobs, AWGN
+    # sigma = 15, stride 2, window 39, K 32), BF16 and FP32 matching ----
+    large = None
+    if not args.no_large:
+        from paper_2508_10307_amd import synth
+        t0 = time.time()
+        wlg = synth.large_24mpix()
+        img = wlg.images[0]
+        ql = wlg.params
+        note(f"large image generated in {time.time() - t0:.1f} s")
+        xl = torch.from_numpy(img.noisy).to(dev)
+        _, Hl, Wl = xl.shape
+        large = {"workload": wlg.name, "shape": [3, Hl, Wl], "stride": ql.stride,
+                 "window": ql.window, "K": ql.K}
+        for name, mode in (("bf16", L.HTS_MATCH_BF16), ("fp32", L.HTS_MATCH_FP32)):
+            pl = api.Params(stride=ql.stride, window=ql.window, K=ql.K, tau_mult=ql.tau_mult,
+                            match_mode=mode)
+            ws_l = api.workspace(pl, 3, Hl, Wl, dev)
+            res_l = {}
+
+            def run_l():
+                res_l["o"] = api.hts_denoise(xl, img.sigma, pl, ws=ws_l)
+
+            msl = timed(run_l, 2, 1, f"large {name}")
+            ent = {"value": round(Hl * Wl / 1e6 / (msl / 1e3), 3), "unit": "MPix/s",
+                   "ms_per_image": round(msl, 3),
+                   "hbm_gbps_algorithmic": round(2 * xl.numel() * 4 / (msl / 1e3) / 1e9, 2),
+                   "fallback_references": int(api.hts_match_fallback_count(
+                       pl, 3, Hl, Wl, ws_l).item())}
+            if name == "bf16":
+                mse = float(((res_l["o"].double() - torch.from_numpy(img.clean).to(dev)) ** 2)
+                            .mean().item())
+                ent["psnr_db"] = round(10 * np.log10(255.0 ** 2 / mse), 4)
+                out_l = res_l["o"].clone()
+            else:
+                ent["outputs_bitwise_equal_to_bf16"] = bool(torch.equal(res_l["o"], out_l))
+            large[name] = ent
+            del ws_l, res_l
+        large["speedup_bf16_vs_fp32"] = round(large["fp32"]["ms_per_image"]
+                                              / large["bf16"]["ms_per_image"], 4)
+        del xl, out_l
+
+    # ---- the differentiable configuration: 16 RGB 512 x 512, AWGN
+    # sigma = 25, K 16; forward with the state the adjoint needs, the MSE
+    # loss gradient, and the frozen adjoint (one call per image) ----
+    diff = None
+    if not args.no_diff:
+        from paper_2508_10307_amd import synth
+        wld = synth.diff_batch16()
+        qd = wld.params
+        pd = api.Params(stride=qd.stride, window=qd.window, K=qd.K, tau_mult=qd.tau_mult,
+                        tune=0)
+        xd = [torch.from_numpy(im.noisy).to(dev) for im in wld.images]
+        cd = [torch.from_numpy(im.clean.astype(np.float32)).to(dev) for im in wld.images]
+        wsd = api.workspace(pd, 3, 512, 512, dev)
+        states, grads, loss = [None] * 16, [None] * 16, {}
+
+        def fwd():
+            tot = 0.0
+            for i, x in enumerate(xd):
+                o, states[i] = api.hts_denoise(x, wld.images[i].sigma, pd, save=True, ws=wsd)
+                d = o - cd[i]
+                tot = tot + (d * d).sum()
+                grads[i] = d * (2.0 / (16 * d.numel()))
+            loss["v"] = tot / (16 * xd[0].numel())
+
+        def bwd():
+            for i in range(16):
+                api.hts_denoise_backward(grads[i], states[i], pd, ws=wsd)
+
+        ms_f = timed(fwd, 2, 1, "diff forward")
+        ms_b = timed(bwd, 2, 1, "diff adjoint")
+        diff = {"workload": wld.name, "images": 16, "shape": [3, 512, 512], "K": qd.K,
+                "forward_ms": round(ms_f, 3), "adjoint_ms": round(ms_b, 3),
+                "value": round(16 * 512 * 512 / 1e6 / ((ms_f + ms_b) / 1e3), 3),
+                "unit": "MPix/s (forward + adjoint)", "loss_mse": round(loss["v"].item(), 4),
+                "adjoint_calls": "one hts_denoise_backward per image"}
+        del wsd
 
     hbm_bytes = sum(2 * x.numel() * 4 for x in xs)    # read y + write x_hat (algorithmic)
     line = {
@@ -403,22 +574,24 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "images": len(xs), "mpix_per_step": round(mpix, 3),
                    "ps": 8, "stride": q.stride, "window": q.window, "K": q.K,
-                   "lambda": q.tau_mult, "api": "hts_denoise_batch" if args.batch_api else "hts_denoise",
-                   "tune": tune, "parallelism": "single GPU"},
+                   "lambda": q.tau_mult, "api": "hts_denoise_batch", "tune": tune,
+                   "parallelism": "single GPU"},
         "psnr_db": round(psnr_bf16, 4),
         "hbm_gbps": round(hbm_bytes / (ms / 1e3) / 1e9, 2),
         "fp32_path": fp32,
-        "stage_ms": {"match_bf16_sum": round(mtime, 3), "match_fp32_sum": round(mtime32, 3),
-                     "match_stage_speedup_bf16_vs_fp32": round(mtime32 / mtime, 3),
-                     "filter_sum": round(ftime, 3)},
-        "adaptive": adaptive,
-        "weighted": weighted,
-        "fourier_threshold": fourier,
-        "spectral_tubes": tubes,
-        "video": vid,
+        "stage_ms": {"bf16": {k: round(v, 4) for k, v in stage16.items()},
+                     "fp32": ({k: round(v, 4) for k, v in stage32.items()} if stage32 else None),
+                     "staged_outputs_equal_graph": same16},
+        "fallback_references": {"total": int(fb.sum()), "of": n_refs,
+                                "images_with_any": int((fb > 0).sum())},
+        "large_image": large,
+        "differentiable": diff,
+        "extensions": ext or None,
         "roofline": roof,
+        "match_roofline": match_roof,
     }
     if not args.no_cpu_baseline:
+        line["parity_sample"] = parity_sample(wl, dev)
         line["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(line), flush=True)
 

@@ -317,6 +317,24 @@ hts_status hts_batch_workspace_size(const hts_params* p, const hts_image* imgs, 
 hts_status hts_denoise_batch(const hts_params* p, const hts_image* imgs, int32_t n,
                              void* ws, size_t ws_bytes, void* stream);
 
+/* hts_denoise_batch with its stages launched one by one on `stream` (no
+ * graph, no second stream), recording caller-created HIP events
+ * (hipEvent_t, created with timing enabled) at the stage boundaries, so that
+ * each stage's kernels can be timed with hipEventElapsedTime:
+ *   events[0] start, [1] after quantisation and the Eq. 10 branch,
+ *   [2] after the block matching (Alg. 1 Step 1), [3] after the covariances,
+ *   [4] after the shortlist fallback, coverage counts, eigen-solves and
+ *   Fourier slices (Step 2(1)), [5] after the fused filter and aggregation
+ *   (Step 2(2)-(4) and Step 3, one launch), [6] after the write-back.
+ * The same kernels, schedule and results as hts_denoise_batch.  Synchronises
+ * `stream` once, before the first launch (descriptor upload).
+ * Errors: HTS_ERR_INVALID unless n_events == HTS_BATCH_STAGE_EVENTS and
+ * every event is non-null; otherwise as hts_denoise_batch. */
+#define HTS_BATCH_STAGE_EVENTS 7
+hts_status hts_denoise_batch_staged(const hts_params* p, const hts_image* imgs, int32_t n,
+                                    void* ws, size_t ws_bytes, void* stream, void* const* events,
+                                    int32_t n_events);
+
 /* A-Haar-tSVD noise-level adjustment (Sec. III.D, Eq. 21-22; Algorithm
  * A-Haar-tSVD Step 1) for a caller-supplied sigma_est (the paper's CNN
  * estimator is not part of this library).  For each sampled group (the

@@ -53,6 +53,8 @@ SIGNATURES = {
                               c_vp, c_vp]),
     "hts_denoise": (c_i32, [P, c_vp, c_i32, c_i32, c_i32, c_f32, c_vp, c_vp, c_vp, c_vp, c_vp,
                             c_vp, c_vp, c_sz, c_vp]),
+    "hts_denoise_batch_staged": (c_i32, [P, ctypes.POINTER(HtsImage), c_i32, c_vp, c_sz, c_vp,
+                                         ctypes.POINTER(c_vp), c_i32]),
     "hts_denoise_noalloc": (c_i32, [P, c_vp, c_i32, c_i32, c_i32, c_f32, c_vp, c_vp]),
     "hts_match_fallback_count": (c_i32, [P, c_i32, c_i32, c_i32, c_vp, c_sz, c_vp, c_vp]),
     "hts_batch_fallback_counts": (c_i32, [P, ctypes.POINTER(HtsImage), c_i32, c_vp, c_sz, c_vp,

@@ -263,6 +263,27 @@ def hts_denoise_batch(noisy: List[torch.Tensor], sigmas, p: Params, outs=None, w
     return outs
 
 
+BATCH_STAGES = ("prep", "match", "cov", "basis", "filter", "finalize")
+
+
+def hts_denoise_batch_staged(noisy: List[torch.Tensor], sigmas, p: Params, outs, ws,
+                             events: Sequence["torch.cuda.Event"]):
+    """hts_denoise_batch launched stage by stage on the current stream,
+    recording the 7 timing events (torch.cuda.Event(enable_timing=True)) at
+    the stage boundaries; stage i lasts events[i] -> events[i + 1]
+    (BATCH_STAGES)."""
+    xs = [_img(x) for x in noisy]
+    dev = xs[0].device
+    for e in events:   # torch creates the HIP event lazily, on first record
+        e.record()
+    arr = _images(xs, outs, sigmas)
+    evs = (L.c_vp * len(events))(*[ctypes.c_void_p(e.cuda_event) for e in events])
+    pc = p.c()
+    L.check("hts_denoise_batch_staged", L.load().hts_denoise_batch_staged(
+        ctypes.byref(pc), arr, len(xs), _ptr(ws), ws.numel(), _stream(dev), evs, len(events)))
+    return outs
+
+
 def _samples(samples, n_rows: int, dev) -> torch.Tensor:
     t = torch.as_tensor(samples, dtype=torch.int32)
     if t.dim() == 1:

@@ -193,7 +193,7 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
   unsigned long long* acc = (unsigned long long*)fsm;          // [NP][RA][CA] fixed point
   float* T = fsm + (glob ? 0 : (2 * NP * RA * CA + 3) / 4 * 4) + wave * TSCRATCH;   // transpose scratch
 
-  for_each_item_t<W_FILT, BATCH>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
+  for_each_item_t<W_FILT, BATCH>(L, [&](const auto& d, int item) __attribute__((always_inline)) {
     const int ntx = (d.nrx + TX - 1) / TX;
     const int iy0 = (item / ntx) * TY, ix0 = (item % ntx) * TX;
     const int iy1 = min(d.nry, iy0 + TY) - 1, ix1 = min(d.nrx, ix0 + TX) - 1;

@@ -446,8 +446,11 @@ Branch branch_for_device() {
 
 // All stages of Algorithm 1 over the batch, as persistent launches sized to
 // the device (work groups loop over the global (image, item) list).
+// ev (nullable, HTS_BATCH_STAGE_EVENTS hipEvent_t): recorded at the stage
+// boundaries; then every stage runs on s (no side stream), in the order of
+// the graph.
 hts_status enqueue_batch(const hts_params* p, int C, const BatchPlan& plan, const ImgDesc* table,
-                         hipStream_t s) {
+                         hipStream_t s, hipEvent_t const* ev = nullptr) {
   const int n = (int)plan.descs.size();
   const int cus = device_cus();
   const Schedule& sc = plan.sc;
@@ -457,9 +460,12 @@ hts_status enqueue_batch(const hts_params* p, int C, const BatchPlan& plan, cons
     L.count_hist = 1;
     return L;
   };
+  auto mark = [&](int i) { return ev ? hipEventRecord(ev[i], s) : hipSuccess; };
+  HIPCHK(mark(0));
   HIPCHK(launch_reset_counters(LK(-1), s));
   HIPCHK(launch_quant(LC(W_PIX), cus * 8, s));
   HIPCHK(launch_gcp(LK(W_REF), cus * 8, s));
+  HIPCHK(mark(1));
   // The covariances depend on the images only: they run on a second stream
   // beside the match (a branch of the captured graph) and join after it.
   // Forked before quantisation instead, so that they also ran beside it and
@@ -467,7 +473,7 @@ hts_status enqueue_batch(const hts_params* p, int C, const BatchPlan& plan, cons
   // 64-image batch; measured, with the same results).  The eigen-solves (one
   // work group per image, a barrier-bound Jacobi) run after the join on
   // their own, so they hold none of the match's compute-unit slots.
-  const Branch br = branch_for_device();
+  const Branch br = ev ? Branch() : branch_for_device();
   hipStream_t bs = s;
   if (br.side) {
     HIPCHK(hipEventRecord(br.fork, s));
@@ -475,7 +481,9 @@ hts_status enqueue_batch(const hts_params* p, int C, const BatchPlan& plan, cons
     bs = br.side;
   }
   HIPCHK(launch_match(LC(W_MATCH), p->match_mode, sc.terms, cus * 2, s));
+  HIPCHK(mark(2));
   HIPCHK(launch_cov(LK(W_COV), cus * 4, bs));
+  HIPCHK(mark(3));
   if (br.side) HIPCHK(hipEventRecord(br.join, bs));
   HIPCHK(launch_match_fallback(LC(-1), cus, s));
   if (plan.descs[0].n_samples > 0) HIPCHK(launch_vote(LK(-1), s));   // A-Haar-tSVD sigma
@@ -484,9 +492,12 @@ hts_status enqueue_batch(const hts_params* p, int C, const BatchPlan& plan, cons
   if (br.side) HIPCHK(hipStreamWaitEvent(s, br.join, 0));
   HIPCHK(launch_eig(LK(-1), s));
   HIPCHK(launch_fbasis(LK(-1), nullptr, nullptr, s));
+  HIPCHK(mark(4));
   if (sc.valu) HIPCHK(launch_filter(LK(W_FILT), sc.fty, sc.ftx, 0, cus * 2, s));
   else HIPCHK(launch_filter_mfma(LK(W_FILT), sc.fty, sc.ftx, 0, cus * 2, s));
+  HIPCHK(mark(5));
   HIPCHK(launch_finalize(LK(W_PIX), cus * 8, s));
+  HIPCHK(mark(6));
   return HTS_OK;
 }
 
@@ -957,6 +968,26 @@ hts_status hts_denoise_batch_adaptive(const hts_params* p, const hts_image* imgs
   if (!samples || !sigma_out || !adapt_args_ok(n_samples, beta)) return HTS_ERR_INVALID;
   const AdaptArgs ad{samples, n_samples, gamma, beta, ranks, sigma_out};
   return denoise_batch_impl(p, imgs, n, ws, ws_bytes, stream, &ad);
+}
+
+hts_status hts_denoise_batch_staged(const hts_params* p, const hts_image* imgs, int32_t n,
+                                    void* ws, size_t ws_bytes, void* stream, void* const* events,
+                                    int32_t n_events) {
+  if (!ws || !events || n_events != HTS_BATCH_STAGE_EVENTS) return HTS_ERR_INVALID;
+  for (int i = 0; i < n_events; ++i)
+    if (!events[i]) return HTS_ERR_INVALID;
+  BatchPlan plan;
+  hts_status st = plan_batch(p, imgs, n, (char*)ws, true, plan);
+  if (st != HTS_OK) return st;
+  if (ws_bytes < plan.bytes) return HTS_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  ImgDesc* table = (ImgDesc*)((char*)ws + plan.table_off);
+  // the table upload reads pageable host memory: wait for it before the
+  // staging vector goes away
+  HIPCHK(hipMemcpyAsync(table, plan.descs.data(), plan.descs.size() * sizeof(ImgDesc),
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return enqueue_batch(p, imgs[0].C, plan, table, s, (hipEvent_t const*)events);
 }
 
 hts_status hts_autotune(const hts_params* p, int32_t C, int32_t H, int32_t W,

@@ -44,8 +44,14 @@ __device__ __forceinline__ void for_each_item(const Launch& L, F&& body) {
   }
 }
 
+// A descriptor read through the constant address space: its fields are
+// invariant for the kernel, so the compiler may load each one where it is
+// used (scalar loads) instead of holding the whole descriptor in registers.
+typedef __attribute__((address_space(4))) const ImgDesc ConstDesc;
+
 // Same, with the single-image / batched choice made at compile time
-// (BATCH = 1: the launch has a descriptor table).
+// (BATCH = 1: the launch has a descriptor table, whose entry reaches the
+// body as a ConstDesc reference).
 template <int KIND, int BATCH, typename F>
 __device__ __forceinline__ void for_each_item_t(const Launch& L, F&& body) {
   const int G = gridDim.x, T = L.total;
@@ -59,8 +65,8 @@ __device__ __forceinline__ void for_each_item_t(const Launch& L, F&& body) {
   }
   for (int w = start; w < end; w += step) {
     if constexpr (BATCH) {
-      int i = find_image(L, KIND, w);
-      const ImgDesc d = L.table[i];
+      const int i = find_image(L, KIND, w);
+      ConstDesc& d = ((ConstDesc*)L.table)[i];
       body(d, w - d.woff[KIND]);
     } else {
       body(L.one, w);
@@ -93,7 +99,8 @@ __device__ inline double fx_to_double(unsigned long long x) {
 // magnitude M of the image to [2^11, 2^12), so the 2^-32 step is relative
 // to M and per-pixel sums of thousands of estimates of size M stay within
 // the 31 integer bits.  1 when the numerator is not fixed point.
-__device__ inline float fx_scale(const ImgDesc& d) {
+template <class Desc>
+__device__ inline float fx_scale(const Desc& d) {
   if (!d.num64 || !d.fxmax) return 1.f;
   const int e = (int)((*d.fxmax >> 23) & 0xffu) - 127;   // M in [2^e, 2^(e+1))
   int k = e == 128 ? 0 : 11 - e;                          // inf / NaN: output is NaN anyway
@@ -135,7 +142,8 @@ __device__ inline void split_pos(int pos, int W, float rW, int& y, int& x) {
 // numerator is fixed point (the write-back turns those pixels into NaN),
 // else by adding NaN to the float numerator; its exported estimates become
 // NaN.  Called by all 64 lanes of a wavefront; lane = patch pixel.
-__device__ inline void poison_group(const ImgDesc& d, const int* gidx, int grel, int K, int C,
+template <class Desc>
+__device__ inline void poison_group(const Desc& d, const int* gidx, int grel, int K, int C,
                                     float rW, int lane) {
   for (int k = 0; k < K; ++k) {
     if (d.group_est)
@@ -160,7 +168,8 @@ __device__ inline void poison_group(const ImgDesc& d, const int* gidx, int grel,
 // group weights times 2^16 in the same fixed point.
 constexpr float WEIGHT_SCALE = 65536.f;
 
-__device__ inline void flush_tile(const ImgDesc& d, const unsigned long long* acc, int C, int RA,
+template <class Desc>
+__device__ inline void flush_tile(const Desc& d, const unsigned long long* acc, int C, int RA,
                                   int CA, int AY0, int AX0, int AH, int AW, bool weighted = false) {
   const int HW = d.H * d.W;
   const int NP = C + (weighted ? 1 : 0);
@@ -187,12 +196,14 @@ __device__ inline void flush_tile(const ImgDesc& d, const unsigned long long* ac
 // from its reference's search window) is added straight into the image
 // numerator, scaled like the tile values (fixed point, or a float numerator
 // when d.num64 is null).  pix is the pixel index y * W + x.
-__device__ inline void add_estimate_global(const ImgDesc& d, int ch, int pix, float v) {
+template <class Desc>
+__device__ inline void add_estimate_global(const Desc& d, int ch, int pix, float v) {
   if (d.num64) atomicAdd(d.num64 + (size_t)ch * d.H * d.W + pix, fx_from_float(v));
   else atomicAdd(d.num + (size_t)ch * d.H * d.W + pix, v);
 }
 // The weight (fixed point, times WEIGHT_SCALE) of such a patch pixel.
-__device__ inline void add_weight_global(const ImgDesc& d, int pix, unsigned long long w) {
+template <class Desc>
+__device__ inline void add_weight_global(const Desc& d, int pix, unsigned long long w) {
   if (d.wsum64) atomicAdd(d.wsum64 + pix, w);
   else if (d.cnt) atomicAdd(d.cnt + pix, (float)(fx_to_double(w) * (1.0 / WEIGHT_SCALE)));
 }

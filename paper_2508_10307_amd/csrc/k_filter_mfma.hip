@@ -108,7 +108,7 @@ __global__ __launch_bounds__(256, K >= 32 ? 1 : 2) void k_filter_mfma(Launch L) 
   const bool swap40 = ((lane >> 5) & 1) != ((lane >> 3) & 1);
   const bool upper32 = lane >= 32;
 
-  for_each_item_t<W_FILT, BATCH>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
+  for_each_item_t<W_FILT, BATCH>(L, [&](const auto& d, int item) __attribute__((always_inline)) {
     const int ntx = (d.nrx + TX - 1) / TX;
     const int iy0 = (item / ntx) * TY, ix0 = (item % ntx) * TX;
     const int iy1 = min(d.nry, iy0 + TY) - 1, ix1 = min(d.nrx, ix0 + TX) - 1;

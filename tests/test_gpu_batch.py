@@ -154,3 +154,26 @@ def test_graph_follows_a_schedule_changed_by_the_autotuner(tmp_path):
     for i, (o, r) in enumerate(zip(outs, ref)):
         log("after autotune", i, SHAPES[i], (o - r).abs().max().item())
         assert torch.equal(o, r)
+
+
+def test_staged_batch_equals_the_graph_and_times_its_stages():
+    """hts_denoise_batch_staged: the same kernels launched one by one with
+    timing events at the stage boundaries; the output equals the graph's bit
+    for bit and every stage has a non-negative duration."""
+    p = api.Params(stride=3, window=15, K=16)
+    imgs, sig = make_batch(31)
+    xs = [T(y) for y in imgs]
+    ref = api.hts_denoise_batch(xs, sig, p)
+    outs = [torch.empty_like(x) for x in xs]
+    ws = torch.empty(api.batch_workspace_size(p, xs, outs, sig), dtype=torch.uint8,
+                     device=dev())
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
+    api.hts_denoise_batch_staged(xs, sig, p, outs, ws, ev)
+    torch.cuda.synchronize()
+    for o, r in zip(outs, ref):
+        assert torch.equal(o, r)
+    ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(6)]
+    log("stage ms", dict(zip(api.BATCH_STAGES, ms)))
+    assert all(m >= 0.0 for m in ms) and ms[1] > 0.0 and ms[4] > 0.0
+    with pytest.raises(RuntimeError):
+        api.hts_denoise_batch_staged(xs, sig, p, outs, ws, ev[:6])

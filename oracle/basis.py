@@ -43,13 +43,18 @@ def covariances(P: np.ndarray):
     lineage the paper follows: in the Fourier domain of the t-product each
     frontal slice of U (V) is the eigenbasis of the row (column) second
     moment of the transformed patches."""
-    C = P.shape[1]
+    n, C, ps = P.shape[0], P.shape[1], P.shape[2]
     Ph = np.fft.fft(P, axis=1)
     CU, CV = [], []
     for f in range(C // 2 + 1):
-        X = Ph[:, f]
-        CU.append(np.einsum("nab,ncb->ac", X, X.conj()))
-        CV.append(np.einsum("nab,nac->bc", X.conj(), X))
+        X = Ph[:, f]                                   # [n, ps, ps]
+        # the sums as one product each: R = [X_1 X_2 ... X_n] (side by side)
+        # gives R R^H = sum X_i X_i^H; S = [X_1; X_2; ...; X_n] (stacked)
+        # gives S^H S = sum X_i^H X_i
+        R = np.moveaxis(X, 0, 1).reshape(ps, n * ps)
+        S = X.reshape(n * ps, ps)
+        CU.append(R @ R.conj().T)
+        CV.append(S.conj().T @ S)
     return CU, CV
 
 

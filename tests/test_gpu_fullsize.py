@@ -10,10 +10,14 @@ compute one by one:
     threshold-kink protocol of the small tests, GPU float basis) and
     averaged (Eq. 2); the pixel must agree within 1e-3.
 The batch output of each image equals its single-image hts_denoise bit for
-bit (the bench's timed path is the batched one).  The same checks on one
-520 x 696 x 34 spectral-tube image through the band-count path and on an
+bit (the bench's timed path is the batched one).  The same checks on the
+4000 x 6000 RGB image (stride 2, window 39), on one 520 x 696 x 34
+spectral-tube image through the band-count path and on an
 eight-frame 540 x 960 RGB video; the gradient of the differentiable
 configuration at sampled pixels."""
+import concurrent.futures
+import multiprocessing
+
 import numpy as np
 import pytest
 import torch
@@ -131,6 +135,123 @@ def test_fullsize_batch_samples_match_the_oracle(batch):
             err = np.abs(out[:, yy, xx] - num / cnt).max()
             log(f"  pixel ({yy},{xx}): {len(gs)} groups, {cnt} estimates, |gpu - oracle| = {err:.2e}")
             assert err <= PIX_TOL
+
+
+def _covariance_part(args):
+    """The oracle's per-frequency covariances over references [b0, b1) of
+    the image saved at path (a worker process of the large-image test)."""
+    path, s, b0, b1 = args
+    y = np.load(path, mmap_mode="r")
+    C, H, W = y.shape
+    ys, xs_, _, _ = ref_grid(H, W, 8, s)
+    a = np.arange(8)
+    CU = CV = None
+    for c0 in range(b0, b1, 100000):
+        c1 = min(b1, c0 + 100000)
+        yy_, xx_ = ys[c0:c1], xs_[c0:c1]
+        P = np.asarray(y)[:, yy_[:, None, None] + a[None, :, None],
+                          xx_[:, None, None] + a[None, None, :]]
+        cu, cv = obasis.covariances(np.ascontiguousarray(np.moveaxis(P, 0, 1)))
+        CU = cu if CU is None else [u + v for u, v in zip(CU, cu)]
+        CV = cv if CV is None else [u + v for u, v in zip(CV, cv)]
+    return CU, CV
+
+
+def test_fullsize_large_image_samples_match_the_oracle(tmp_path):
+    """The 24 MPix configuration (RGB 4000 x 6000, 400 blobs, AWGN sigma = 15,
+    stride 2, window 39, K 32; 5,985,009 references, 766 MB of indices),
+    through hts_denoise as bench.py's large_image object runs it: sampled
+    references against the brute-force window scan (among them the last
+    reference rows and columns and the corners), BF16 and FP32 matching
+    equal over the whole index array, the FP64 basis against the oracle's
+    covariances summed over every reference patch (in chunks), and sampled
+    output pixels recomputed from every group over them."""
+    wl = synth.large_24mpix()
+    im, q = wl.images[0], wl.params
+    y = im.noisy
+    C, H, W = y.shape
+    K, s, w = q.K, q.stride, q.window
+    r = (w - 1) // 2
+    p = api.Params(stride=s, window=w, K=K, tau_mult=q.tau_mult)
+    x = torch.from_numpy(y).to(dev())
+    out, st = api.hts_denoise(x, im.sigma, p, save=True)
+    torch.cuda.synchronize()
+    idx_t = st["idx"]
+    n_ref = idx_t.shape[0]
+    log(f"large image: {H}x{W}, {n_ref} references")
+    assert n_ref == 5985009
+    i32 = api.hts_match(x, api.Params(stride=s, window=w, K=K, match_mode=1))
+    assert torch.equal(i32, idx_t)
+    del i32
+    # sampled references, brute force
+    ys, xs_, ny, nx = ref_grid(H, W, 8, s)
+    qg = omatch.quantize(y)
+    planes = omatch.guide_planes(qg)
+    Hp, Wp = H - 7, W - 7
+    rng = np.random.default_rng(24)
+    sample = list(rng.choice(n_ref, 30, replace=False)) + [0, nx - 1, n_ref - nx, n_ref - 1,
+                                                           (ny // 2) * nx + nx - 1]
+    rows = idx_t[torch.tensor(sample, device=dev())].cpu().numpy().astype(np.int64)
+    green = omatch.gcp_green(qg, ys[sample], xs_[sample], 8, p.gcp_num, p.gcp_den)
+    for j, n in enumerate(sample):
+        ry, rx = int(ys[n]), int(xs_[n])
+        pl = planes[0 if green[j] else 1]
+        ref = pl[ry:ry + 8, rx:rx + 8]
+        c = []
+        for cy in range(max(0, ry - r), min(Hp - 1, ry + r) + 1):
+            for cx in range(max(0, rx - r), min(Wp - 1, rx + r) + 1):
+                if (cy, cx) != (ry, rx):
+                    c.append((int(((pl[cy:cy + 8, cx:cx + 8] - ref) ** 2).sum()), cy * W + cx))
+        c.sort()
+        assert list(rows[j]) == [ry * W + rx] + [v for _, v in c[:K - 1]], n
+    log("  sampled references exact")
+    # FP64 basis: the oracle's covariances of all 6M reference patches, in
+    # 16 CPU worker processes (chunks of the reference list, summed in order)
+    y64 = y.astype(np.float64)
+    np.save(tmp_path / "y.npy", y64)
+    bounds = np.linspace(0, n_ref, 17).astype(int)
+    ctx = multiprocessing.get_context("spawn")
+    with concurrent.futures.ProcessPoolExecutor(16, mp_context=ctx) as ex:
+        parts = list(ex.map(_covariance_part, [(str(tmp_path / "y.npy"), s, int(b0), int(b1))
+                                               for b0, b1 in zip(bounds[:-1], bounds[1:])]))
+    CU = [sum(pt[0][f] for pt in parts) for f in range(C // 2 + 1)]
+    CV = [sum(pt[1][f] for pt in parts) for f in range(C // 2 + 1)]
+    _, _, Uo, Vo, _, _ = obasis.basis_from_covariances(CU, CV, C)
+    _, _, U64, V64, _ = api.hts_basis(x, p, want_fp64=True)
+    np.testing.assert_allclose(U64.cpu().numpy(), Uo, atol=1e-9)
+    np.testing.assert_allclose(V64.cpu().numpy(), Vo, atol=1e-9)
+    log("  FP64 basis within 1e-9")
+    # sampled output pixels (groups found on the device)
+    UF = obasis.fourier_from_real(st["U"].cpu().numpy().astype(np.float64))
+    VF = obasis.fourier_from_real(st["V"].cpu().numpy().astype(np.float64))
+    tau = q.tau_mult * im.sigma
+    py_t, px_t = idx_t // W, idx_t % W
+    nw = K * C * 2
+    for yy, xx in [(int(rng.integers(0, H)), int(rng.integers(0, W))) for _ in range(2)] + \
+            [(H - 1, W - 1), (0, 0)]:
+        cov_t = (py_t <= yy) & (yy < py_t + 8) & (px_t <= xx) & (xx < px_t + 8)
+        gs_t = torch.nonzero(cov_t.any(dim=1)).flatten()
+        gs = gs_t.cpu().numpy()
+        gidx = idx_t[gs_t].cpu().numpy().astype(np.int64)
+        wsel = (gs_t[:, None] * nw + torch.arange(nw, device=dev())[None]).flatten()
+        words = st["masks"][wsel].cpu().numpy().view(np.uint32)
+        gpy, gpx = np.divmod(gidx, W)
+        cover = (gpy <= yy) & (yy < gpy + 8) & (gpx <= xx) & (xx < gpx + 8)
+        S = of.haar_group(of.tsvd_forward(of.gather_groups(y64, gidx, 8), UF, VF), K)
+        M = np.stack([group_masks(words, gi, K, C) for gi in range(len(gs))])
+        diff = M != (np.abs(S) >= tau)
+        if diff.any():
+            assert np.abs(np.abs(S[diff]) - tau).max() <= DELTA_REL * tau
+        est = of.tsvd_inverse(of.haar_group_inverse(np.where(M, S, 0.0), K), UF, VF)
+        num, cnt = np.zeros(C), 0
+        for gi in range(len(gs)):
+            for k in np.nonzero(cover[gi])[0]:
+                num += est[gi, k, :, yy - gpy[gi, k], xx - gpx[gi, k]]
+                cnt += 1
+        o = out[:, yy, xx].cpu().numpy()
+        err = np.abs(o - num / cnt).max()
+        log(f"  pixel ({yy},{xx}): {len(gs)} groups, {cnt} estimates, |gpu - oracle| = {err:.2e}")
+        assert err <= PIX_TOL
 
 
 def test_fullsize_spectral_tube_samples_match_the_oracle():

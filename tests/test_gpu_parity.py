@@ -240,8 +240,11 @@ def test_basis_fp64(C, H, W, s):
 
 
 # ---------------------------------------------------------------- filter + denoise
-def parity_denoise(y, sigma, p, tau_mult=None, label=""):
-    """Run hts_denoise and check it against the oracle (R13 protocol)."""
+def parity_denoise(y, sigma, p, tau_mult=None, label="", own_basis=False):
+    """Run hts_denoise and check it against the oracle (R13 protocol).
+    own_basis: the oracle learns its own FP64 basis (eigh) instead of taking
+    the GPU's float one; the eigenvalues must then be well separated (a
+    relative gap of at least 1e-9), else the comparison is not defined."""
     x = T(y)
     out, st = api.hts_denoise(x, sigma, p, save=True)
     torch.cuda.synchronize()
@@ -251,8 +254,16 @@ def parity_denoise(y, sigma, p, tau_mult=None, label=""):
     np.testing.assert_array_equal(idx, idx_o)
     U, V = st["U"].cpu().numpy(), st["V"].cpu().numpy()
     masks = opipe.unpack_masks(st["masks"].cpu().numpy().view(np.uint32), len(idx), p.K, C)
-    r = opipe.denoise(y, sigma, 8, p.stride, p.window, p.K, p.tau_mult, idx=idx, U=U, V=V,
-                      mask=masks)
+    if own_basis:
+        r = opipe.denoise(y, sigma, 8, p.stride, p.window, p.K, p.tau_mult, idx=idx, mask=masks)
+        for ev in (r["eigU"], r["eigV"]):
+            gap = np.min(-np.diff(ev, axis=1) / np.abs(ev).max(axis=1, keepdims=True))
+            log(label, "smallest relative eigen-gap", gap)
+            assert gap >= 1e-9
+        assert np.abs(r["U"] - U).max() <= 1e-5 and np.abs(r["V"] - V).max() <= 1e-5
+    else:
+        r = opipe.denoise(y, sigma, 8, p.stride, p.window, p.K, p.tau_mult, idx=idx, U=U, V=V,
+                          mask=masks)
     tau = p.tau_mult * sigma
     log(label, "overrides", r["n_override"], "max margin", r["max_override_margin"], "tau", tau)
     assert r["max_override_margin"] <= DELTA_REL * max(tau, 1.0)
@@ -265,11 +276,12 @@ def parity_denoise(y, sigma, p, tau_mult=None, label=""):
     return out, st, r
 
 
-def test_denoise_gray256():
+@pytest.mark.parametrize("own_basis", [False, True], ids=["gpu_basis", "oracle_basis"])
+def test_denoise_gray256(own_basis):
     wl = synth.gray_256()
     im, q = wl.images[0], wl.params
     p = P(stride=q.stride, window=q.window, K=q.K, tau_mult=q.tau_mult)
-    out, _, _ = parity_denoise(im.noisy, im.sigma, p, label="gray256")
+    out, _, _ = parity_denoise(im.noisy, im.sigma, p, label="gray256", own_basis=own_basis)
     psnr = lambda a: 10 * np.log10(255 ** 2 / np.mean((a - im.clean) ** 2))
     log("psnr noisy", psnr(im.noisy), "denoised", psnr(out.cpu().numpy()))
 
@@ -282,11 +294,12 @@ def test_denoise_small(C, H, W, s, w, K):
     parity_denoise(y, 20.0, P(stride=s, window=w, K=K), label=f"small{C}x{H}x{W}")
 
 
-def test_denoise_rgb512_poisson_gauss():
+@pytest.mark.parametrize("own_basis", [False, True], ids=["gpu_basis", "oracle_basis"])
+def test_denoise_rgb512_poisson_gauss(own_basis):
     wl = synth.rgb_512_pg()
     im, q = wl.images[0], wl.params
     p = P(stride=q.stride, window=q.window, K=q.K, tau_mult=q.tau_mult)
-    parity_denoise(im.noisy, im.sigma, p, label="rgb512")
+    parity_denoise(im.noisy, im.sigma, p, label="rgb512", own_basis=own_basis)
 
 
 @pytest.mark.parametrize("C", [1, 3])

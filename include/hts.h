@@ -396,7 +396,7 @@ hts_status hts_denoise_backward(const hts_params* p, const float* grad_out,
  * nothing.  Every call on a GPU uses that GPU's one scratch array, which
  * keeps the last call's contents (each call clears what it reads first):
  * calls that overlap on one GPU, from any stream or thread, race. */
-#define HTS_NOALLOC_SCRATCH_BYTES ((size_t)96 << 20)
+#define HTS_NOALLOC_SCRATCH_BYTES ((size_t)192 << 20)
 hts_status hts_denoise_noalloc(const hts_params* p, const float* noisy, int32_t C, int32_t H,
                                int32_t W, float sigma, float* out, void* stream);
 

@@ -241,6 +241,9 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
       // (0 * inf and 0 * NaN are NaN)
       float nf = 0.f;
       int nkeep = 0;   // kept coefficients of the group (weighted aggregation)
+      // Lane (kl, a) takes row a of each of its slots' patches as row
+      // projections (d.rowp: the row after the channel DFT, times V_F):
+      // X[j][q] = q-th part (c = 3: f = 0, Re f = 1, Im f = 1) of P^ V_F.
       float X[SPL][C][8];
       int py[SPL], px[SPL];
 #pragma unroll
@@ -252,13 +255,17 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
         split_pos(pos, d.W, rW, py[j], px[j]);
         py[j] = min(max(py[j], 0), d.Hp - 1);
         px[j] = min(max(px[j], 0), d.Wp - 1);
-        const float* src = d.img + (py[j] + a) * d.W + px[j];
+        const float4* src =
+            (const float4*)(d.rowp + ((size_t)(py[j] + a) * d.Wp + px[j]) * (8 * C));
 #pragma unroll
         for (int ch = 0; ch < C; ++ch)
 #pragma unroll
-          for (int b = 0; b < 8; ++b) {
-            const float v = src[ch * HW + b];
-            X[j][ch][b] = active ? v : 0.f;
+          for (int h = 0; h < 2; ++h) {
+            const float4 v = src[2 * ch + h];
+            X[j][ch][4 * h + 0] = active ? v.x : 0.f;
+            X[j][ch][4 * h + 1] = active ? v.y : 0.f;
+            X[j][ch][4 * h + 2] = active ? v.z : 0.f;
+            X[j][ch][4 * h + 3] = active ? v.w : 0.f;
           }
       }
 
@@ -267,30 +274,28 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
       for (int j = 0; j < SPL; ++j) {
         __builtin_amdgcn_sched_barrier(0);  // keep one slot's temporaries live at a time
         if (C == 1) {
-#pragma unroll
-          for (int b = 0; b < 8; ++b) nf = fmaf(X[j][0][b], 0.f, nf);
+          // y = row a of P V (a non-finite pixel makes it non-finite)
           float y[8];
-          mv<false>(X[j][0], fb, FB_V0T, 1.f, y);   // y[b] = sum_t x[t] V[t][b]
+#pragma unroll
+          for (int b = 0; b < 8; ++b) {
+            y[b] = X[j][0][b];
+            nf = fmaf(y[b], 0.f, nf);
+          }
           transpose_rc(T, kl, a, y);
           float z[8];
           mv<false>(y, fb, FB_U0T, 1.f, z);   // z[i] = sum_r y[r] U[r][i]
 #pragma unroll
           for (int i = 0; i < 8; ++i) X[j][0][i] = z[i];
         } else {
-          float f0[8], f1r[8], f1i[8];
+          // Y = P^ V_F, row a: f = 0 real, f = 1 complex
+          float y0[8], y1r[8], y1i[8];
 #pragma unroll
           for (int b = 0; b < 8; ++b) {
-            const float p0 = X[j][0][b], p1 = X[j][1][b], p2 = X[j][2][b];
-            f0[b] = p0 + p1 + p2;
-            nf = fmaf(f0[b], 0.f, nf);
-            f1r[b] = p0 - 0.5f * (p1 + p2);
-            f1i[b] = HALF_SQRT3 * (p2 - p1);
+            y0[b] = X[j][0][b];
+            y1r[b] = X[j][1][b];
+            y1i[b] = X[j][2][b];
+            nf = fmaf(y0[b], 0.f, nf);
           }
-          float y0[8], y1r[8], y1i[8];
-          // Y = P^ V_F: f = 0 real, f = 1 complex (one real slice per pass)
-          mv<false>(f0, fb, FB_V0T, 1.f, y0);
-          // y1 = V_F(1)^T P^(1) per row: (V1R + i V1I)^T (f1r + i f1i)
-          cmv(f1r, f1i, fb, FB_V1RT, FB_V1IT, 1.f, FB_V1PT, y1r, y1i);
           transpose_rc(T, kl, a, y0);
           transpose_rc(T, kl, a, y1r);
           transpose_rc(T, kl, a, y1i);

@@ -99,7 +99,7 @@ hts_status make_geo(const hts_params* p, int C, int H, int W, Geo& g) {
 // Workspace carve-up for one image.
 struct Carve {
   size_t gplanes, green, idx, fb_list, fb_count, cov, basis64, basis, fbasis, num, num64, cnt, hist,
-      poison, fxmax, wsum64, gbasis, ufg, gscratch, total;
+      poison, fxmax, wsum64, gbasis, rowp, ufg, gscratch, total;
 };
 
 Carve carve(const Geo& g) {
@@ -123,6 +123,7 @@ Carve carve(const Geo& g) {
   c.wsum64 = o; o += al((size_t)g.H * g.W * 8);
   c.gbasis = o; o += al((size_t)4 * 128 * 8);   // covariance cotangents of the basis derivative
   const bool gen = general_c(g.C);
+  c.rowp = o; o += gen ? 0 : al((size_t)g.H * g.Wp * rowp_floats(g.C) * 4);
   c.ufg = o; o += gen ? al((size_t)2 * n_freq(g.C) * 128 * 8) : 0;
   c.gscratch = o;
   o += gen ? al((size_t)gen_filter_grid(g.n_ref, g.K, g.C) * g.K * g.C * 64 * 4) : 0;
@@ -164,6 +165,7 @@ ImgDesc make_desc(const Geo& g, const hts_params* p, char* ws, const Carve& c, c
   d.wsum64 = weighted(p) ? (unsigned long long*)(ws + c.wsum64) : nullptr;
   d.ufg = general_c(g.C) ? (double*)(ws + c.ufg) : nullptr;
   d.gscratch = general_c(g.C) ? (float*)(ws + c.gscratch) : nullptr;
+  d.rowp = general_c(g.C) ? nullptr : (float*)(ws + c.rowp);
   d.H = g.H; d.W = g.W; d.Hp = g.Hp; d.Wp = g.Wp;
   d.nry = g.nry; d.nrx = g.nrx; d.n_ref = g.n_ref;
   d.ref_begin = 0; d.ref_count = g.n_ref;
@@ -293,6 +295,7 @@ hts_status run_filter(const hts_params* p, int C, const Schedule& sc, ImgDesc d,
     return HTS_OK;
   }
   HIPCHK(launch_fbasis(make_launch(p, C, d, -1, sc.fty, sc.ftx), U, V, s));
+  if (sc.valu) HIPCHK(launch_rowproj(make_launch(p, C, d, W_PIX, sc.fty, sc.ftx), 0, s));
   const Launch L = make_launch(p, C, d, W_FILT, sc.fty, sc.ftx);
   if (sc.valu) HIPCHK(launch_filter(L, sc.fty, sc.ftx, adjoint, 0, s));
   else HIPCHK(launch_filter_mfma(L, sc.fty, sc.ftx, adjoint, 0, s));
@@ -492,6 +495,7 @@ hts_status enqueue_batch(const hts_params* p, int C, const BatchPlan& plan, cons
   if (br.side) HIPCHK(hipStreamWaitEvent(s, br.join, 0));
   HIPCHK(launch_eig(LK(-1), s));
   HIPCHK(launch_fbasis(LK(-1), nullptr, nullptr, s));
+  if (sc.valu) HIPCHK(launch_rowproj(LK(W_PIX), cus * 8, s));
   HIPCHK(mark(4));
   if (sc.valu) HIPCHK(launch_filter(LK(W_FILT), sc.fty, sc.ftx, 0, cus * 2, s));
   else HIPCHK(launch_filter_mfma(LK(W_FILT), sc.fty, sc.ftx, 0, cus * 2, s));
@@ -1097,7 +1101,7 @@ struct VideoPlan {
   VideoGeo v;
   int n_ref, np, NF, grid;
   size_t stacked, sout, gplanes, idx, cov, basis64, basis, fbasis, ufg, num64, cnt, hist, poison,
-      fxmax, fb_count, gscratch, total;
+      fxmax, fb_count, gscratch, rowp, total;
 };
 
 hts_status plan_video(const hts_params* p, int T, int C, int H, int W, int dt, VideoPlan& vp) {
@@ -1131,6 +1135,7 @@ hts_status plan_video(const hts_params* p, int T, int C, int H, int W, int dt, V
   vp.fxmax = o; o += al(4);
   vp.fb_count = o; o += al(4);
   vp.gscratch = o; o += al((size_t)vp.grid * p->K * C * 64 * 4);
+  vp.rowp = o; o += general_c(C) ? 0 : al((size_t)T * H * vp.f.Wp * rowp_floats(C) * 4);
   vp.total = o;
   return HTS_OK;
 }
@@ -1179,6 +1184,7 @@ hts_status hts_denoise_video(const hts_params* p, const float* frames, int32_t T
   d.poison = (uint8_t*)(b + vp.poison);
   d.fxmax = (uint32_t*)(b + vp.fxmax);
   d.gscratch = (float*)(b + vp.gscratch);
+  d.rowp = general_c(C) ? nullptr : (float*)(b + vp.rowp);
   d.masks = masks_out;
   d.H = TH; d.W = W; d.Hp = TH - PS + 1; d.Wp = W - PS + 1;
   d.nry = vp.f.nry; d.nrx = vp.f.nrx; d.n_ref = vp.n_ref;
@@ -1230,6 +1236,7 @@ hts_status hts_denoise_video(const hts_params* p, const float* frames, int32_t T
     // c = 1, 3: the vector-ALU filter over tiles of the stacked reference
     // grid (T * nry rows), with global aggregation
     HIPCHK(launch_fbasis(LS(d, -1), nullptr, nullptr, s));
+    HIPCHK(launch_rowproj(LS(d, W_PIX), 0, s));
     ImgDesc dv = d;
     dv.nry = T * vp.f.nry;
     Launch Lv = LS(dv, -1);

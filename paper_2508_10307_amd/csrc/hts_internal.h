@@ -71,6 +71,7 @@ struct ImgDesc {
   float* sigma_dev;        // [1] adjusted sigma; when set, the filter's tau is tau_mult * *sigma_dev
   unsigned long long* wsum64; // [H][W] weight sums (fixed point, 2^-48 units) of the weighted
                               // aggregation; nullable (then weights go to cnt, or are uniform)
+  float* rowp;             // c = 1, 3: row projections [H][Wp][8 C] (see launch_rowproj)
   double* ufg;             // general c: [2 * (C/2+1)][re/im][64] Fourier-domain eigenvectors
   float* gscratch;         // general c: filter scratch, [work group][K][C][64]
   int32_t woff[W_NKIND];   // first global work item of each kind (batched)
@@ -179,6 +180,14 @@ hipError_t launch_gbasis(const Launch& L, const float* g, const double* U64, con
 hipError_t launch_zero_accum(const Launch& L, int grid, hipStream_t s);
 hipError_t launch_filter(const Launch& L, int shape_ty, int shape_tx, int adjoint, int grid,
                          hipStream_t s);
+// Row projections for the vector-ALU filter (c = 1, 3): for every image row
+// y and valid column start x, the 8-pixel row of the patch at (y, x) after
+// the channel DFT, times the Fourier slices of V (the first product of the
+// t-SVD projection, P^ V_F, which depends only on the row and the column
+// start): d.rowp[(y * Wp + x) * 8C + 8q + b], q = 0 (f = 0; c = 1: the row
+// itself), 1, 2 (real and imaginary part of f = 1).  Work items W_PIX.
+hipError_t launch_rowproj(const Launch& L, int grid, hipStream_t s);
+__host__ __device__ inline int rowp_floats(int C) { return 8 * C; }
 hipError_t launch_finalize(const Launch& L, int grid, hipStream_t s);
 hipError_t launch_scatter_est(const Launch& L, hipStream_t s);
 hipError_t launch_adjoint_prep(const Launch& L, int grid, hipStream_t s);

@@ -67,6 +67,65 @@ hipError_t launch_filter(const Launch& L, int ty, int tx, int adjoint, int grid,
   return masks ? launch_filter_c<3, 0, 1, 0>(L, g, lds, s) : launch_filter_c<3, 0, 0, 0>(L, g, lds, s);
 }
 
+// Row projections (the first product of the filter's t-SVD projection,
+// hoisted out of the group loop): one thread per (row y, column start x),
+// x < Wp.  The row's 8 pixels of every channel go through the channel DFT
+// and the products with the V slices in exactly the order the filter used
+// to apply them per slot, so every estimate keeps its bits.  A non-finite
+// pixel makes all 8 C values of every row window over it non-finite (each
+// V column has a non-zero entry), which the filter's poison check sees.
+template <int C>
+__global__ __launch_bounds__(256) void k_rowproj(Launch L) {
+  for_each_item<W_PIX>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
+    const int HW = d.H * d.W;
+    const int p0 = item * PIX_CHUNK;
+    const int p1 = min(HW, p0 + PIX_CHUNK);
+    const cfloat* fb = uniform_ptr(d.fbasis);
+    for (int p = p0 + (int)threadIdx.x; p < p1; p += blockDim.x) {
+      const int y = p / d.W, x = p - y * d.W;
+      if (x >= d.Wp) continue;
+      const float* src = d.img + (size_t)y * d.W + x;
+      float* dst = d.rowp + ((size_t)y * d.Wp + x) * (8 * C);
+      if (C == 1) {
+        float xr[8], yv[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) xr[b] = src[b];
+        mv<false>(xr, fb, FB_V0T, 1.f, yv);   // y[b] = sum_t x[t] V[t][b]
+#pragma unroll
+        for (int b = 0; b < 8; ++b) dst[b] = yv[b];
+      } else {
+        float f0[8], f1r[8], f1i[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          const float q0 = src[b], q1 = src[HW + b], q2 = src[2 * HW + b];
+          f0[b] = q0 + q1 + q2;
+          f1r[b] = q0 - 0.5f * (q1 + q2);
+          f1i[b] = HALF_SQRT3 * (q2 - q1);
+        }
+        float y0[8], y1r[8], y1i[8];
+        mv<false>(f0, fb, FB_V0T, 1.f, y0);
+        // y1 = V_F(1)^T P^(1) per row: (V1R + i V1I)^T (f1r + i f1i)
+        cmv(f1r, f1i, fb, FB_V1RT, FB_V1IT, 1.f, FB_V1PT, y1r, y1i);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          dst[b] = y0[b];
+          dst[8 + b] = y1r[b];
+          dst[16 + b] = y1i[b];
+        }
+      }
+    }
+  });
+}
+
+hipError_t launch_rowproj(const Launch& L, int grid, hipStream_t s) {
+  if (L.total <= 0) return hipSuccess;
+  const int g = xcd_grid(grid > 0 && grid < L.total ? grid : L.total);
+  if (L.C == 1) hipLaunchKernelGGL(k_rowproj<1>, dim3(g), dim3(256), 0, s, L);
+  else if (L.C == 3) hipLaunchKernelGGL(k_rowproj<3>, dim3(g), dim3(256), 0, s, L);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 // Stand-alone aggregation of precomputed group estimates (Eq. 2 numerator
 // and denominator): one wavefront per group, lane = slot-row.
 __global__ __launch_bounds__(256) void k_scatter_est(Launch L, const float* est, int C) {

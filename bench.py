@@ -498,11 +498,14 @@ def main():
         note(f"large image generated in {time.time() - t0:.1f} s")
         xl = torch.from_numpy(img.noisy).to(dev)
         _, Hl, Wl = xl.shape
+        # schedule: the autotuner on a 1024 x 1024 crop shape with these parameters
+        tl = api.hts_autotune(api.Params(stride=ql.stride, window=ql.window, K=ql.K,
+                                         tau_mult=ql.tau_mult), 3, 1024, 1024)
         large = {"workload": wlg.name, "shape": [3, Hl, Wl], "stride": ql.stride,
-                 "window": ql.window, "K": ql.K}
+                 "window": ql.window, "K": ql.K, "tune": tl}
         for name, mode in (("bf16", L.HTS_MATCH_BF16), ("fp32", L.HTS_MATCH_FP32)):
             pl = api.Params(stride=ql.stride, window=ql.window, K=ql.K, tau_mult=ql.tau_mult,
-                            match_mode=mode)
+                            match_mode=mode, tune=tl)
             ws_l = api.workspace(pl, 3, Hl, Wl, dev)
             res_l = {}
 
@@ -536,8 +539,10 @@ def main():
         from paper_2508_10307_amd import synth
         wld = synth.diff_batch16()
         qd = wld.params
+        td = api.hts_autotune(api.Params(stride=qd.stride, window=qd.window, K=qd.K,
+                                         tau_mult=qd.tau_mult), 3, 512, 512)
         pd = api.Params(stride=qd.stride, window=qd.window, K=qd.K, tau_mult=qd.tau_mult,
-                        tune=0)
+                        tune=td)
         xd = [torch.from_numpy(im.noisy).to(dev) for im in wld.images]
         cd = [torch.from_numpy(im.clean.astype(np.float32)).to(dev) for im in wld.images]
         wsd = api.workspace(pd, 3, 512, 512, dev)
@@ -558,7 +563,7 @@ def main():
 
         ms_f = timed(fwd, 2, 1, "diff forward")
         ms_b = timed(bwd, 2, 1, "diff adjoint")
-        diff = {"workload": wld.name, "images": 16, "shape": [3, 512, 512], "K": qd.K,
+        diff = {"workload": wld.name, "images": 16, "shape": [3, 512, 512], "K": qd.K, "tune": td,
                 "forward_ms": round(ms_f, 3), "adjoint_ms": round(ms_b, 3),
                 "value": round(16 * 512 * 512 / 1e6 / ((ms_f + ms_b) / 1e3), 3),
                 "unit": "MPix/s (forward + adjoint)", "loss_mse": round(loss["v"].item(), 4),

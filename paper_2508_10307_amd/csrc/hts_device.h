@@ -49,6 +49,12 @@ __device__ __forceinline__ void for_each_item(const Launch& L, F&& body) {
 // used (scalar loads) instead of holding the whole descriptor in registers.
 typedef __attribute__((address_space(4))) const ImgDesc ConstDesc;
 
+// for_each_item for bodies that take the descriptor as `const auto&`: a
+// batched launch passes its table entry as a ConstDesc reference (fields
+// loaded where used instead of held in registers).
+template <int KIND, typename F>
+__device__ __forceinline__ void for_each_item_cd(const Launch& L, F&& body);
+
 // Same, with the single-image / batched choice made at compile time
 // (BATCH = 1: the launch has a descriptor table, whose entry reaches the
 // body as a ConstDesc reference).
@@ -65,6 +71,28 @@ __device__ __forceinline__ void for_each_item_t(const Launch& L, F&& body) {
   }
   for (int w = start; w < end; w += step) {
     if constexpr (BATCH) {
+      const int i = find_image(L, KIND, w);
+      ConstDesc& d = ((ConstDesc*)L.table)[i];
+      body(d, w - d.woff[KIND]);
+    } else {
+      body(L.one, w);
+    }
+  }
+}
+
+template <int KIND, typename F>
+__device__ __forceinline__ void for_each_item_cd(const Launch& L, F&& body) {
+  const int G = gridDim.x, T = L.total;
+  int start = blockIdx.x, step = G, end = T;
+  if (G >= 8 && (G & 7) == 0) {
+    const int chunk = (T + 7) >> 3;
+    const int x = blockIdx.x & 7;
+    start = x * chunk + (blockIdx.x >> 3);
+    step = G >> 3;
+    end = min(T, (x + 1) * chunk);
+  }
+  for (int w = start; w < end; w += step) {
+    if (L.table) {
       const int i = find_image(L, KIND, w);
       ConstDesc& d = ((ConstDesc*)L.table)[i];
       body(d, w - d.woff[KIND]);

@@ -94,7 +94,7 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
   const int s = L.stride;
   const int K = L.K;
 
-  for_each_item<W_MATCH>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
+  for_each_item_cd<W_MATCH>(L, [&](const auto& d, int item) __attribute__((always_inline)) {
     const int ntx = (d.nrx + MATCH_TX - 1) / MATCH_TX;
     const int iy0 = (item / ntx) * MATCH_TY, ix0 = (item % ntx) * MATCH_TX;
     const int iy1 = min(d.nry, iy0 + MATCH_TY) - 1, ix1 = min(d.nrx, ix0 + MATCH_TX) - 1;

@@ -143,7 +143,12 @@ PROFILE_SOURCES = ["paper_2508_10307_amd/csrc/k_filter.hip",
                    "paper_2508_10307_amd/csrc/k_match.hip",
                    "paper_2508_10307_amd/csrc/hts_device.h",
                    "paper_2508_10307_amd/csrc/hts_internal.h"]
-PROFILED = {}   # kernel name -> (sources sha256, {"hbm_bytes": ..., "mfma_util_pct": ...})
+PROFILED = {   # kernel name -> (sources sha256, figures)
+    "void hts::k_filter<3, 4, 0, 0, 1, 0, 0>(hts::Launch)":
+        ("e4a4a6c5683249161f7b56c0b04d7a8845cd1d8c7e792527332e849caae66d7d", {"hbm_bytes": 9468426524}),
+    "void hts::k_match<0, 3, 1, 2>(hts::Launch)":
+        ("e4a4a6c5683249161f7b56c0b04d7a8845cd1d8c7e792527332e849caae66d7d", {"hbm_bytes": 2367757104, "mfma_util_pct": 6.01}),
+}
 
 
 def sources_sha():
@@ -410,6 +415,7 @@ def main():
                                  "dot form with exact norms",
                   "candidates": cands, "references": n_refs,
                   "mfma_util_pct": profiled(mk, "mfma_util_pct"),
+                  "traffic": profiled(mk, "hbm_bytes"),
                   "target_frac": 0.5}
     if stage32:
         match_roof["fp32_ssd_ms"] = round(stage32["match"], 4)

@@ -68,9 +68,18 @@ def batch():
 
 
 def picks(wl):
+    """Six images: the largest, the smallest, a middle one, and the most
+    elongated ones (W / H largest and smallest), plus the one with the
+    highest noise level."""
     areas = [im.noisy.shape[1] * im.noisy.shape[2] for im in wl.images]
     order = np.argsort(areas, kind="stable")
-    return [int(order[-1]), int(order[len(order) // 2]), int(order[0])]
+    aspect = np.argsort([im.noisy.shape[2] / im.noisy.shape[1] for im in wl.images], kind="stable")
+    noisiest = int(np.argmax([im.sigma for im in wl.images]))
+    out = []
+    for i in (order[-1], order[0], order[len(order) // 2], aspect[-1], aspect[0], noisiest):
+        if int(i) not in out:
+            out.append(int(i))
+    return out
 
 
 def test_fullsize_batch_samples_match_the_oracle(batch):
@@ -92,7 +101,7 @@ def test_fullsize_batch_samples_match_the_oracle(batch):
         planes = omatch.guide_planes(qg)
         green = omatch.gcp_green(qg, ys, xs_, 8, p.gcp_num, p.gcp_den)
         Hp, Wp = H - 7, W - 7
-        for n in rng.choice(len(ys), 40, replace=False):
+        for n in rng.choice(len(ys), 60, replace=False):
             ry, rx = int(ys[n]), int(xs_[n])
             pl = planes[0 if green[n] else 1]
             ref = pl[ry:ry + 8, rx:rx + 8]
@@ -114,7 +123,7 @@ def test_fullsize_batch_samples_match_the_oracle(batch):
         tau = p.tau_mult * sig[i]
         py, px = np.divmod(idx, W)
         out = outs[i].cpu().numpy()
-        for _ in range(4):
+        for _ in range(6):
             yy, xx = int(rng.integers(0, H)), int(rng.integers(0, W))
             cover = (py <= yy) & (yy < py + 8) & (px <= xx) & (xx < px + 8)
             gs = np.nonzero(cover.any(axis=1))[0]

@@ -163,11 +163,11 @@ __device__ inline float haar_unscale(int k, int K) {
 // MASKS = 1 exports the keep-masks (when d.masks is set).
 // WT = 1: weighted aggregation (a separate instantiation, so that the
 // uniform one keeps its register budget).
-// WT = 2: uniform weights without the LDS tile: every estimate row is
-// transposed through the wavefront's scratch and added straight into the
-// image numerator (64-bit fixed point, eight consecutive pixels per patch
-// and instruction), for groups whose patches may lie anywhere in the image
-// (the stacked frames of a video).
+// WT = 2: uniform weights without the LDS tile, for groups whose patches
+// may lie anywhere in the image (the stacked frames of a video): every slot's
+// estimate, scaled for the fixed-point conversion, is exported to its record
+// d.group_est[(g K + k) C + ch][row][col], and the aggregation gathers them
+// per output tile afterwards (k_gather_tiles).
 // FT = 1 (c = 3): threshold in the channel-Fourier domain (whole conjugate
 // pairs by their orthonormal magnitude) instead of Eq. 19 on the real core:
 // the channel IDFT after the projection and the DFT before the inverse are
@@ -509,15 +509,13 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
 #pragma unroll
           for (int b = 0; b < 8; ++b) nf = fmaf(out[ch][b], 0.f, nf);
         if (glob) {
-          // lane (kl, a) receives column a of its patch: row i goes to
-          // pixel (py + i, px + a)
+          // row a of the slot's estimate into its export record
+          if (active) {
+            float4* ge = (float4*)(d.group_est + (((size_t)grel * K + kl * SPL + j) * C) * PS2 + a * 8);
 #pragma unroll
-          for (int ch = 0; ch < C; ++ch) {
-            transpose_rc(T, kl, a, out[ch]);
-            if (active) {
-              unsigned long long* colp = d.num64 + (size_t)ch * HW + (size_t)py[j] * d.W + px[j] + a;
-#pragma unroll
-              for (int i = 0; i < 8; ++i) atomicAdd(colp + (size_t)i * d.W, fx_from_float(out[ch][i]));
+            for (int ch = 0; ch < C; ++ch) {
+              ge[ch * (PS2 / 4)] = make_float4(out[ch][0], out[ch][1], out[ch][2], out[ch][3]);
+              ge[ch * (PS2 / 4) + 1] = make_float4(out[ch][4], out[ch][5], out[ch][6], out[ch][7]);
             }
           }
         } else if (active) {

@@ -1101,7 +1101,7 @@ struct VideoPlan {
   VideoGeo v;
   int n_ref, np, NF, grid;
   size_t stacked, sout, gplanes, idx, cov, basis64, basis, fbasis, ufg, num64, cnt, hist, poison,
-      fxmax, fb_count, gscratch, rowp, total;
+      fxmax, fb_count, gscratch, rowp, est, gscr, list, total;
 };
 
 hts_status plan_video(const hts_params* p, int T, int C, int H, int W, int dt, VideoPlan& vp) {
@@ -1113,6 +1113,7 @@ hts_status plan_video(const hts_params* p, int T, int C, int H, int W, int dt, V
     return HTS_ERR_UNSUPPORTED;
   const long long px = (long long)T * H * W;
   if (px * C >= (1LL << 31) || (long long)T * vp.f.n_ref * p->K >= (1LL << 31)) return HTS_ERR_UNSUPPORTED;
+  if (!general_c(C) && !gather_supported(px)) return HTS_ERR_UNSUPPORTED;
   vp.n_ref = T * vp.f.n_ref;
   vp.np = C == 3 ? 2 : 1;
   vp.NF = n_freq(C);
@@ -1136,6 +1137,11 @@ hts_status plan_video(const hts_params* p, int T, int C, int H, int W, int dt, V
   vp.fb_count = o; o += al(4);
   vp.gscratch = o; o += al((size_t)vp.grid * p->K * C * 64 * 4);
   vp.rowp = o; o += general_c(C) ? 0 : al((size_t)T * H * vp.f.Wp * rowp_floats(C) * 4);
+  // c = 1, 3: every slot's estimate, then the corner buckets of the gather
+  const size_t slots = general_c(C) ? 0 : (size_t)vp.n_ref * p->K;
+  vp.est = o; o += al(slots * C * 64 * 4);
+  vp.gscr = o; o += general_c(C) ? 0 : al(gather_scratch_ints(px) * 4);
+  vp.list = o; o += al(slots * 4);
   vp.total = o;
   return HTS_OK;
 }
@@ -1239,6 +1245,7 @@ hts_status hts_denoise_video(const hts_params* p, const float* frames, int32_t T
     HIPCHK(launch_rowproj(LS(d, W_PIX), 0, s));
     ImgDesc dv = d;
     dv.nry = T * vp.f.nry;
+    dv.group_est = (float*)(b + vp.est);   // every slot's estimate, exported
     Launch Lv = LS(dv, -1);
     Lv.fty = VIDEO_FTY;
     Lv.ftx = VIDEO_FTX;
@@ -1247,6 +1254,9 @@ hts_status hts_denoise_video(const hts_params* p, const float* frames, int32_t T
   }
   HIPCHK(launch_zero_hist(LS(d, W_PIX), 0, s));
   HIPCHK(launch_count_hist(LS(d, W_REF), 0, s));
+  if (!general_c(C))   // the estimates, bucketed by corner, gathered per output tile
+    HIPCHK(launch_gather(LS(d, -1), (const float*)(b + vp.est), (int*)(b + vp.gscr),
+                         (int*)(b + vp.list), s));
   HIPCHK(launch_count_box(LS(d, W_BOX), 0, s));
   HIPCHK(launch_finalize(LS(d, W_PIX), 0, s));
   HIPCHK(launch_stack(out, d.out, T, C, H, W, true, s));

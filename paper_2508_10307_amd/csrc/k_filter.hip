@@ -160,12 +160,13 @@ hipError_t launch_scatter_est(const Launch& L, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Global aggregation (WT = 2): the groups of a tile may reach beyond its
+// Export instantiation (WT = 2): the groups of a tile may reach beyond its
 // search windows (the stacked frames of a video), so there is no LDS tile,
-// only the transpose scratch; no group estimates.
+// only the transpose scratch; every slot's estimate goes to L.one.group_est
+// (fixed-point scaled; k_gather_tiles adds them up).
 hipError_t launch_filter_stacked(const Launch& L, hipStream_t s) {
   if (L.total <= 0) return hipSuccess;
-  if (L.table || L.one.group_est || !L.one.num64 || (L.C != 1 && L.C != 3)) return hipErrorInvalidValue;
+  if (L.table || !L.one.group_est || !L.one.num64 || (L.C != 1 && L.C != 3)) return hipErrorInvalidValue;
   const int g = xcd_grid(L.total);
   const size_t lds = 4 * TSCRATCH * sizeof(float);
   const bool masks = L.one.masks != nullptr;

@@ -438,6 +438,15 @@ def hts_denoise_backward_basis(noisy, grad_out, st, p: Params, grad_in, basis64=
     return grad_in
 
 
+def video_workspace_size(p: Params, T: int, C: int, H: int, W: int, dt: int) -> int:
+    """hts_video_workspace_size: bytes of the workspace of a T-frame clip."""
+    pc = p.c()
+    n = L.c_sz()
+    L.check("hts_video_workspace_size", L.load().hts_video_workspace_size(
+        ctypes.byref(pc), T, C, H, W, int(dt), ctypes.byref(n)))
+    return n.value
+
+
 def hts_denoise_video(frames: torch.Tensor, sigma: float, p: Params, dt: int = 1, save=False,
                       ws=None):
     """Video denoising with spatio-temporal search over frames t-dt..t+dt.

@@ -153,3 +153,22 @@ def test_translating_clip_matches_oracle():
     err = np.abs(out.cpu().numpy() - r["out"]).max()
     log(f"  max |gpu - oracle| = {err:.3e}")
     assert err <= PIX_TOL
+
+
+@pytest.mark.parametrize("C", [1, 3])
+def test_video_non_finite_pixel_poisons_the_sequence(C):
+    """The sequence basis is learned from every frame, so one non-finite
+    pixel makes the basis, every group and with them every output pixel NaN
+    (the image path's rule), through the exported estimates and the gather as
+    well; a clean clip afterwards on the same workspace is unaffected."""
+    f = clip(3, C, 24, 26, 3100 + C)
+    p = api.Params(stride=3, window=9, K=8)
+    ws = torch.empty(api.video_workspace_size(p, 3, C, 24, 26, 1), dtype=torch.uint8,
+                     device=dev())
+    clean_out = api.hts_denoise_video(T_(f), 20.0, p, dt=1, ws=ws)
+    fi = f.copy()
+    fi[1, 0, 10, 12] = np.inf
+    bad = api.hts_denoise_video(T_(fi), 20.0, p, dt=1, ws=ws)
+    assert torch.isnan(bad).all()
+    again = api.hts_denoise_video(T_(f), 20.0, p, dt=1, ws=ws)
+    assert torch.equal(again, clean_out)

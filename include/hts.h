@@ -384,6 +384,43 @@ hts_status hts_denoise_backward(const hts_params* p, const float* grad_out,
                                 int32_t W, float* grad_in, float* grad_tau_mult, void* ws,
                                 size_t ws_bytes, void* stream);
 
+/* The state one image's backward pass needs (as hts_denoise exports it):
+ * device buffers owned by the caller, all non-null.
+ *   idx   [n_ref][K] int32;  masks  bit-packed as in hts_filter for all
+ *   n_ref groups (n_ref K C 2 words);  U, V  [C][ps][ps];  cnt  [H][W]. */
+typedef struct {
+  int32_t* idx;
+  uint32_t* masks;
+  float* U;
+  float* V;
+  float* cnt;
+} hts_state;
+
+/* hts_denoise_batch that also writes every image's backward state into
+ * states[i] (host array of n): the values hts_denoise writes through its
+ * idx_out, masks_out, U_out, V_out and cnt_out for that image alone, bit for
+ * bit.  Uniform aggregation with the real-domain threshold only (the masks
+ * of Eq. 19).  Captured into its own HIP graph per parameter set, like
+ * hts_denoise_batch; the state pointers may change between calls.  Same
+ * workspace as hts_denoise_batch.  Errors: HTS_ERR_UNSUPPORTED with
+ * HTS_FLAG_WEIGHTED or HTS_FLAG_FOURIER_THRESHOLD; HTS_ERR_INVALID for a
+ * null states or a null state pointer; otherwise as hts_denoise_batch. */
+hts_status hts_denoise_batch_save(const hts_params* p, const hts_image* imgs,
+                                  const hts_state* states, int32_t n, void* ws, size_t ws_bytes,
+                                  void* stream);
+
+/* hts_denoise_backward for n images at once: imgs[i].noisy is grad_out of
+ * image i and imgs[i].out receives its grad_in (the two may be the same
+ * buffer); imgs[i].sigma is ignored; states[i] is the frozen state of that
+ * image (from hts_denoise_batch_save or hts_denoise).  The same values as n
+ * hts_denoise_backward calls, bit for bit; the stages run as persistent
+ * launches over all images, captured into a HIP graph per parameter set.
+ * Same workspace as hts_denoise_batch over these images.  Errors as
+ * hts_denoise_batch_save. */
+hts_status hts_denoise_batch_backward(const hts_params* p, const hts_image* imgs,
+                                      const hts_state* states, int32_t n, void* ws,
+                                      size_t ws_bytes, void* stream);
+
 /* hts_denoise for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * the same stages and kernels, with the workspace taken from a fixed scratch

@@ -37,6 +37,10 @@ class HtsImage(ctypes.Structure):
                 ("sigma", c_f32)]
 
 
+class HtsState(ctypes.Structure):
+    _fields_ = [("idx", c_vp), ("masks", c_vp), ("U", c_vp), ("V", c_vp), ("cnt", c_vp)]
+
+
 P = ctypes.POINTER(HtsParams)
 
 # name -> (restype, argtypes); every entry point declared in include/hts.h
@@ -62,6 +66,10 @@ SIGNATURES = {
     "hts_batch_workspace_size": (c_i32, [P, ctypes.POINTER(HtsImage), c_i32,
                                          ctypes.POINTER(c_sz)]),
     "hts_denoise_batch": (c_i32, [P, ctypes.POINTER(HtsImage), c_i32, c_vp, c_sz, c_vp]),
+    "hts_denoise_batch_save": (c_i32, [P, ctypes.POINTER(HtsImage), ctypes.POINTER(HtsState),
+                                       c_i32, c_vp, c_sz, c_vp]),
+    "hts_denoise_batch_backward": (c_i32, [P, ctypes.POINTER(HtsImage),
+                                           ctypes.POINTER(HtsState), c_i32, c_vp, c_sz, c_vp]),
     "hts_denoise_grad_tau": (c_i32, [P, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_i32, c_i32,
                                      c_f32, c_f32, c_vp, c_vp, c_sz, c_vp]),
     "hts_adapt_sigma": (c_i32, [P, c_vp, c_i32, c_i32, c_i32, c_vp, c_vp, c_i32, c_f32, c_f32,

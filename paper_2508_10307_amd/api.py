@@ -155,6 +155,26 @@ def hts_aggregate(p: Params, C, H, W, num, cnt, group_est=None, idx=None, ref_be
     return out
 
 
+def new_state(p: Params, C: int, H: int, W: int, dev) -> dict:
+    """Device buffers for one image's backward state: dict(idx, masks, U, V,
+    cnt) in the layouts of hts_state."""
+    ny, nx = ref_grid(H, W, p)
+    n_ref = ny * nx
+    return {"idx": torch.empty((n_ref, p.K), dtype=torch.int32, device=dev),
+            "masks": torch.zeros(mask_words(n_ref, p.K, C), dtype=torch.int32, device=dev),
+            "U": torch.empty((C, 8, 8), dtype=torch.float32, device=dev),
+            "V": torch.empty((C, 8, 8), dtype=torch.float32, device=dev),
+            "cnt": torch.empty((H, W), dtype=torch.float32, device=dev)}
+
+
+def _states(states) -> "ctypes.Array":
+    arr = (L.HtsState * len(states))()
+    for i, st in enumerate(states):
+        arr[i] = L.HtsState(st["idx"].data_ptr(), st["masks"].data_ptr(), st["U"].data_ptr(),
+                            st["V"].data_ptr(), st["cnt"].data_ptr())
+    return arr
+
+
 def hts_denoise(noisy, sigma, p: Params, save=False, ws=None):
     """Algorithm 1 end to end.  With save=True also returns the state the
     adjoint needs: dict(idx, masks, U, V, cnt)."""
@@ -162,15 +182,7 @@ def hts_denoise(noisy, sigma, p: Params, save=False, ws=None):
     C, H, W = x.shape
     dev = x.device
     out = torch.empty_like(x)
-    st = None
-    if save:
-        ny, nx = ref_grid(H, W, p)
-        n_ref = ny * nx
-        st = {"idx": torch.empty((n_ref, p.K), dtype=torch.int32, device=dev),
-              "masks": torch.zeros(mask_words(n_ref, p.K, C), dtype=torch.int32, device=dev),
-              "U": torch.empty((C, 8, 8), dtype=torch.float32, device=dev),
-              "V": torch.empty((C, 8, 8), dtype=torch.float32, device=dev),
-              "cnt": torch.empty((H, W), dtype=torch.float32, device=dev)}
+    st = new_state(p, C, H, W, dev) if save else None
     g = st or {}
     ws = workspace(p, C, H, W, dev) if ws is None else ws
     pc = p.c()
@@ -261,6 +273,43 @@ def hts_denoise_batch(noisy: List[torch.Tensor], sigmas, p: Params, outs=None, w
     L.check("hts_denoise_batch", L.load().hts_denoise_batch(
         ctypes.byref(pc), arr, len(xs), _ptr(ws), ws.numel(), _stream(dev)))
     return outs
+
+
+def hts_denoise_batch_save(noisy: List[torch.Tensor], sigmas, p: Params, outs=None, states=None,
+                           ws=None):
+    """hts_denoise_batch that also writes each image's backward state.
+    Returns (outs, states), states a list of dicts as new_state makes."""
+    xs = [_img(x) for x in noisy]
+    dev = xs[0].device
+    outs = [torch.empty_like(x) for x in xs] if outs is None else outs
+    if states is None:
+        states = [new_state(p, *x.shape, dev) for x in xs]
+    if ws is None:
+        ws = torch.empty(batch_workspace_size(p, xs, outs, sigmas), dtype=torch.uint8, device=dev)
+    arr = _images(xs, outs, sigmas)
+    sarr = _states(states)
+    pc = p.c()
+    L.check("hts_denoise_batch_save", L.load().hts_denoise_batch_save(
+        ctypes.byref(pc), arr, sarr, len(xs), _ptr(ws), ws.numel(), _stream(dev)))
+    return outs, states
+
+
+def hts_denoise_batch_backward(grads: List[torch.Tensor], states, p: Params, grad_ins=None,
+                               ws=None):
+    """Frozen-map adjoint of a batch (hts_denoise_backward per image, in one
+    graph-captured pipeline).  Returns the list of input gradients."""
+    gs = [_img(g, "grad_out") for g in grads]
+    dev = gs[0].device
+    grad_ins = [torch.empty_like(g) for g in gs] if grad_ins is None else grad_ins
+    sig = [0.0] * len(gs)
+    if ws is None:
+        ws = torch.empty(batch_workspace_size(p, gs, grad_ins, sig), dtype=torch.uint8, device=dev)
+    arr = _images(gs, grad_ins, sig)
+    sarr = _states(states)
+    pc = p.c()
+    L.check("hts_denoise_batch_backward", L.load().hts_denoise_batch_backward(
+        ctypes.byref(pc), arr, sarr, len(gs), _ptr(ws), ws.numel(), _stream(dev)))
+    return grad_ins
 
 
 BATCH_STAGES = ("prep", "match", "cov", "basis", "filter", "finalize")

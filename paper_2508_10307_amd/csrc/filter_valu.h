@@ -532,9 +532,10 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
 #pragma unroll
               for (int b = 0; b < 8; ++b) atomicAdd(wrow + b, fxw);
             }
-          } else if constexpr (!BATCH) {
-            // (batched launches filter the groups of their own match, which
-            // always lie inside the tile: no cold path, no register cost)
+          } else if constexpr (!BATCH || ADJ) {
+            // (the batched forward filters the groups of its own match, which
+            // always lie inside the tile: no cold path, no register cost; the
+            // batched adjoint takes the caller's indices and keeps it)
             const int pix = (py[j] + a) * d.W + px[j];
             for (int ch = 0; ch < C; ++ch)
               for (int b = 0; b < 8; ++b) add_estimate_global(d, ch, pix + b, out[ch][b]);

@@ -452,8 +452,10 @@ Branch branch_for_device() {
 // ev (nullable, HTS_BATCH_STAGE_EVENTS hipEvent_t): recorded at the stage
 // boundaries; then every stage runs on s (no side stream), in the order of
 // the graph.
+// save: the filter also writes every image's keep-masks (d.masks) and the
+// basis is copied out to d.U_ext / d.V_ext.
 hts_status enqueue_batch(const hts_params* p, int C, const BatchPlan& plan, const ImgDesc* table,
-                         hipStream_t s, hipEvent_t const* ev = nullptr) {
+                         hipStream_t s, hipEvent_t const* ev = nullptr, bool save = false) {
   const int n = (int)plan.descs.size();
   const int cus = device_cus();
   const Schedule& sc = plan.sc;
@@ -495,13 +497,42 @@ hts_status enqueue_batch(const hts_params* p, int C, const BatchPlan& plan, cons
   if (br.side) HIPCHK(hipStreamWaitEvent(s, br.join, 0));
   HIPCHK(launch_eig(LK(-1), s));
   HIPCHK(launch_fbasis(LK(-1), nullptr, nullptr, s));
+  if (save) HIPCHK(launch_copy_basis(LK(-1), 1, s));
   if (sc.valu) HIPCHK(launch_rowproj(LK(W_PIX), cus * 8, s));
   HIPCHK(mark(4));
-  if (sc.valu) HIPCHK(launch_filter(LK(W_FILT), sc.fty, sc.ftx, 0, cus * 2, s));
-  else HIPCHK(launch_filter_mfma(LK(W_FILT), sc.fty, sc.ftx, 0, cus * 2, s));
+  Launch Lf = LK(W_FILT);
+  Lf.batch_masks = save ? 1 : 0;
+  if (sc.valu) HIPCHK(launch_filter(Lf, sc.fty, sc.ftx, 0, cus * 2, s));
+  else HIPCHK(launch_filter_mfma(Lf, sc.fty, sc.ftx, 0, cus * 2, s));
   HIPCHK(mark(5));
   HIPCHK(launch_finalize(LK(W_PIX), cus * 8, s));
   HIPCHK(mark(6));
+  return HTS_OK;
+}
+
+// The frozen-map adjoint of every image of the batch (descriptors as
+// hts_denoise_batch_backward builds them: img = the workspace buffer that
+// receives r, num = grad_out, out = grad_in, idx / masks_in / cnt / U_ext /
+// V_ext = the caller's state), in the order of hts_denoise_backward.
+hts_status enqueue_batch_backward(const hts_params* p, int C, const BatchPlan& plan,
+                                  const ImgDesc* table, hipStream_t s) {
+  const int n = (int)plan.descs.size();
+  const int cus = device_cus();
+  const Schedule& sc = plan.sc;
+  auto LK = [&](int kind) {
+    Launch L = batch_launch(p, C, table, n, kind >= 0 ? plan.totals[kind] : 0, sc);
+    L.adjoint = 1;
+    return L;
+  };
+  HIPCHK(launch_reset_counters(LK(-1), s));          // fxmax = 0
+  HIPCHK(launch_adjoint_prep(LK(W_PIX), cus * 8, s));  // r = g / cnt, max |r|
+  HIPCHK(launch_zero_accum(LK(W_PIX), cus * 8, s));    // keeps the caller's cnt
+  HIPCHK(launch_copy_basis(LK(-1), 0, s));
+  HIPCHK(launch_fbasis(LK(-1), nullptr, nullptr, s));
+  if (sc.valu) HIPCHK(launch_rowproj(LK(W_PIX), cus * 8, s));
+  if (sc.valu) HIPCHK(launch_filter(LK(W_FILT), sc.fty, sc.ftx, 1, cus * 2, s));
+  else HIPCHK(launch_filter_mfma(LK(W_FILT), sc.fty, sc.ftx, 1, cus * 2, s));
+  HIPCHK(launch_finalize(LK(W_PIX), cus * 8, s));      // grad_in = numerator
   return HTS_OK;
 }
 
@@ -524,8 +555,9 @@ hipStream_t g_capture_stream[64] = {nullptr};
 // (or a cache file) may change between calls, and a graph captured for the
 // old schedule would launch the filter over the old tile grid.
 std::string graph_key(const hts_params* p, const Schedule& sc, const hts_image* imgs, int n,
-                      const void* ws, bool adaptive) {
-  std::string k = adaptive ? "A|" : "|";
+                      const void* ws, const char* tag) {
+  std::string k = tag;
+  k += "|";
   char buf[160];
   int dev = 0;
   (void)hipGetDevice(&dev);
@@ -893,30 +925,17 @@ struct AdaptArgs {
   float* sigma_out;         // device [n]
 };
 
-static hts_status denoise_batch_impl(const hts_params* p, const hts_image* imgs, int32_t n,
-                                     void* ws, size_t ws_bytes, void* stream,
-                                     const AdaptArgs* ad) {
-  if (!ws) return HTS_ERR_INVALID;
-  BatchPlan plan;
-  hts_status st = plan_batch(p, imgs, n, (char*)ws, true, plan);
-  if (st != HTS_OK) return st;
-  if (ws_bytes < plan.bytes) return HTS_ERR_WORKSPACE;
-  if (ad) {
-    for (int i = 0; i < n; ++i) {
-      ImgDesc& d = plan.descs[i];
-      d.samples = ad->samples + (size_t)i * ad->n_samples;
-      d.n_samples = ad->n_samples;
-      d.gamma = ad->gamma;
-      d.beta = ad->beta;
-      d.ranks = ad->ranks ? ad->ranks + (size_t)i * ad->n_samples : nullptr;
-      d.sigma_dev = ad->sigma_out + i;
-    }
-  }
-  hipStream_t s = (hipStream_t)stream;
-  const int C = imgs[0].C;
-  ImgDesc* table = (ImgDesc*)((char*)ws + plan.table_off);
+}  // extern "C"
+
+namespace {
+
+// Uploads the descriptor table of `plan` and replays the graph of `key`,
+// capturing it first (enq(stream) enqueues the stages); eager launches on
+// the caller's stream if capture or instantiation fails.
+template <class Enq>
+hts_status replay_batch(const std::string& key, const BatchPlan& plan, ImgDesc* table,
+                               hipStream_t s, Enq&& enq) {
   std::lock_guard<std::mutex> lk(g_graph_mu);
-  const std::string key = graph_key(p, plan.sc, imgs, n, ws, ad != nullptr);
   if (g_graphs.size() >= 64 && !g_graphs.count(key)) {
     // bounded cache: drop every entry (after the device is idle) and start over
     HIPCHK(hipDeviceSynchronize());
@@ -941,28 +960,119 @@ static hts_status denoise_batch_impl(const hts_params* p, const hts_image* imgs,
     hipStream_t cs = g_capture_stream[dev];
     hipGraph_t graph = nullptr;
     HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    hts_status est = enqueue_batch(p, C, plan, table, cs);
+    hts_status est = enq(cs);
     const hipError_t ce = hipStreamEndCapture(cs, &graph);
     if (est != HTS_OK || ce != hipSuccess || !graph) {
       if (graph) (void)hipGraphDestroy(graph);
       (void)hipGetLastError();
-      return enqueue_batch(p, C, plan, table, s);   // eager launches on the caller's stream
+      return enq(s);   // eager launches on the caller's stream
     }
     const hipError_t ie = hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (ie != hipSuccess) {
       e.exec = nullptr;
       (void)hipGetLastError();
-      return enqueue_batch(p, C, plan, table, s);
+      return enq(s);
     }
   }
   HIPCHK(hipGraphLaunch(e.exec, s));
   return HTS_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+static hts_status denoise_batch_impl(const hts_params* p, const hts_image* imgs, int32_t n,
+                                     void* ws, size_t ws_bytes, void* stream,
+                                     const AdaptArgs* ad, const hts_state* states = nullptr) {
+  if (!ws) return HTS_ERR_INVALID;
+  BatchPlan plan;
+  hts_status st = plan_batch(p, imgs, n, (char*)ws, true, plan);
+  if (st != HTS_OK) return st;
+  if (ws_bytes < plan.bytes) return HTS_ERR_WORKSPACE;
+  for (int i = 0; i < n; ++i) {
+    ImgDesc& d = plan.descs[i];
+    if (ad) {
+      d.samples = ad->samples + (size_t)i * ad->n_samples;
+      d.n_samples = ad->n_samples;
+      d.gamma = ad->gamma;
+      d.beta = ad->beta;
+      d.ranks = ad->ranks ? ad->ranks + (size_t)i * ad->n_samples : nullptr;
+      d.sigma_dev = ad->sigma_out + i;
+    }
+    if (states) {   // the match, the coverage counts and the filter write the caller's state
+      d.idx = states[i].idx;
+      d.masks = states[i].masks;
+      d.cnt = states[i].cnt;
+      d.U_ext = states[i].U;
+      d.V_ext = states[i].V;
+    }
+  }
+  const int C = imgs[0].C;
+  ImgDesc* table = (ImgDesc*)((char*)ws + plan.table_off);
+  const std::string key = graph_key(p, plan.sc, imgs, n, ws, ad ? "A" : states ? "S" : "");
+  return replay_batch(key, plan, table, (hipStream_t)stream, [&](hipStream_t cs) {
+    return enqueue_batch(p, C, plan, table, cs, nullptr, states != nullptr);
+  });
+}
+
+static bool states_ok(const hts_state* states, int32_t n) {
+  if (!states || n < 1) return false;
+  for (int i = 0; i < n; ++i) {
+    const hts_state& t = states[i];
+    if (!t.idx || !t.masks || !t.U || !t.V || !t.cnt) return false;
+  }
+  return true;
+}
+
 hts_status hts_denoise_batch(const hts_params* p, const hts_image* imgs, int32_t n, void* ws,
                              size_t ws_bytes, void* stream) {
   return denoise_batch_impl(p, imgs, n, ws, ws_bytes, stream, nullptr);
+}
+
+hts_status hts_denoise_batch_save(const hts_params* p, const hts_image* imgs,
+                                  const hts_state* states, int32_t n, void* ws, size_t ws_bytes,
+                                  void* stream) {
+  if (!p || !imgs || n < 1) return HTS_ERR_INVALID;
+  if (weighted(p) || fourier(p, imgs[0].C)) return HTS_ERR_UNSUPPORTED;   // masks of Eq. 19 only
+  if (!states_ok(states, n)) return HTS_ERR_INVALID;
+  return denoise_batch_impl(p, imgs, n, ws, ws_bytes, stream, nullptr, states);
+}
+
+hts_status hts_denoise_batch_backward(const hts_params* p, const hts_image* imgs,
+                                      const hts_state* states, int32_t n, void* ws,
+                                      size_t ws_bytes, void* stream) {
+  if (!p || !imgs || n < 1 || !ws) return HTS_ERR_INVALID;
+  if (weighted(p) || fourier(p, imgs[0].C)) return HTS_ERR_UNSUPPORTED;   // adjoint of Eq. 19-20, 2
+  if (!states_ok(states, n)) return HTS_ERR_INVALID;
+  std::vector<hts_image> gi(imgs, imgs + n);   // sigma plays no part in the adjoint
+  for (auto& im : gi) im.sigma = 0.f;
+  BatchPlan plan;
+  hts_status st = plan_batch(p, gi.data(), n, (char*)ws, true, plan);
+  if (st != HTS_OK) return st;
+  if (ws_bytes < plan.bytes) return HTS_ERR_WORKSPACE;
+  for (int i = 0; i < n; ++i) {
+    ImgDesc& d = plan.descs[i];
+    d.fb_count = nullptr;   // the forward's fallback counts stay readable
+    d.img = d.num;   // r = grad_out / cnt (workspace)
+    d.num = const_cast<float*>(imgs[i].noisy);
+    d.out = imgs[i].out;
+    d.sigma = 0.f;
+    d.tau = 0.f;
+    d.idx = states[i].idx;
+    d.masks_in = states[i].masks;
+    d.masks = nullptr;
+    d.cnt = states[i].cnt;
+    d.U_ext = states[i].U;
+    d.V_ext = states[i].V;
+  }
+  const int C = imgs[0].C;
+  ImgDesc* table = (ImgDesc*)((char*)ws + plan.table_off);
+  const std::string key = graph_key(p, plan.sc, gi.data(), n, ws, "B");
+  return replay_batch(key, plan, table, (hipStream_t)stream, [&](hipStream_t cs) {
+    return enqueue_batch_backward(p, C, plan, table, cs);
+  });
 }
 
 hts_status hts_denoise_batch_adaptive(const hts_params* p, const hts_image* imgs, int32_t n,

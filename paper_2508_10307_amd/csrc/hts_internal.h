@@ -72,6 +72,8 @@ struct ImgDesc {
   unsigned long long* wsum64; // [H][W] weight sums (fixed point, 2^-48 units) of the weighted
                               // aggregation; nullable (then weights go to cnt, or are uniform)
   float* rowp;             // c = 1, 3: row projections [H][Wp][8 C] (see launch_rowproj)
+  float* U_ext;            // [C][8][8] caller's basis copy (batched state export / import)
+  float* V_ext;
   double* ufg;             // general c: [2 * (C/2+1)][re/im][64] Fourier-domain eigenvectors
   float* gscratch;         // general c: filter scratch, [work group][K][C][64]
   int32_t woff[W_NKIND];   // first global work item of each kind (batched)
@@ -104,6 +106,9 @@ struct Launch {
   int32_t fty, ftx;        // filter tile shape (references)
   int32_t count_hist;      // 1: k_quant clears hist and the match adds every group's
                            // slot corners to it (the coverage histogram)
+  int32_t batch_masks;     // batched filter launch: export the keep-masks (d.masks)
+  int32_t adjoint;         // batched adjoint: k_adjoint_prep reads d.num and writes
+                           // d.out; k_zero_accum keeps cnt; k_finalize divides by 1
 };
 
 // Match-kernel LDS geometry for a 4x4 reference tile at stride s and window
@@ -174,6 +179,10 @@ hipError_t launch_vote(const Launch& L, hipStream_t s);
 hipError_t launch_taugrad(const Launch& L, const float* g, double* partial, float kappa, float* out,
                           int grid, hipStream_t s);
 hipError_t launch_fbasis(const Launch& L, const float* U, const float* V, hipStream_t s);
+// Basis copies between the workspace (d.basis, U then V) and the caller's
+// d.U_ext / d.V_ext of every image that has them: to_ext = 1 exports,
+// 0 imports.
+hipError_t launch_copy_basis(const Launch& L, int to_ext, hipStream_t s);
 hipError_t launch_gbasis(const Launch& L, const float* g, const double* U64, const double* V64,
                          const double* eig, double* partial, int grid, double* M, float* grad,
                          hipStream_t s);

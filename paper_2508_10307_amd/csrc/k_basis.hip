@@ -285,6 +285,26 @@ hipError_t launch_eig(const Launch& L, hipStream_t s) {
   hipLaunchKernelGGL(k_eig, dim3(n), dim3(256), 0, s, L);
   return hipGetLastError();
 }
+__global__ void k_copy_basis(Launch L, int to_ext) {
+  const int nimg = L.table ? L.n_img : 1;
+  const int n = L.C * 64;
+  for (int im = blockIdx.x; im < nimg; im += gridDim.x) {
+    const ImgDesc& d = L.table ? L.table[im] : L.one;
+    for (int e = threadIdx.x; e < 2 * n; e += blockDim.x) {
+      float* ext = e < n ? d.U_ext : d.V_ext;
+      if (!ext) continue;
+      if (to_ext) ext[e % n] = d.basis[e];
+      else d.basis[e] = ext[e % n];
+    }
+  }
+}
+
+hipError_t launch_copy_basis(const Launch& L, int to_ext, hipStream_t s) {
+  const int n = L.table ? L.n_img : 1;
+  hipLaunchKernelGGL(k_copy_basis, dim3(n < 65535 ? n : 65535), dim3(256), 0, s, L, to_ext);
+  return hipGetLastError();
+}
+
 hipError_t launch_fbasis(const Launch& L, const float* U, const float* V, hipStream_t s) {
   const int n = L.table ? L.n_img : 1;
   hipLaunchKernelGGL(k_fbasis, dim3(n), dim3(128), 0, s, L, U, V);

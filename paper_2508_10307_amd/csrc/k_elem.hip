@@ -74,13 +74,13 @@ __global__ __launch_bounds__(256) void k_gcp(Launch L) {
 __global__ void k_reset_counters(Launch L) {
   if (!L.table) {
     if (threadIdx.x == 0) {
-      *L.one.fb_count = 0;
+      if (L.one.fb_count) *L.one.fb_count = 0;
       if (L.one.fxmax) *L.one.fxmax = 0;
     }
     return;
   }
   for (int i = threadIdx.x; i < L.n_img; i += blockDim.x) {
-    *L.table[i].fb_count = 0;
+    if (L.table[i].fb_count) *L.table[i].fb_count = 0;
     if (L.table[i].fxmax) *L.table[i].fxmax = 0;
   }
 }
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(256) void k_zero_accum(Launch L) {
       } else {
         for (int c = 0; c < L.C; ++c) d.num[c * HW + p] = 0.0f;
       }
-      if (d.cnt) d.cnt[p] = 0.0f;
+      if (d.cnt && !L.adjoint) d.cnt[p] = 0.0f;   // the adjoint's cnt is the caller's state
       if (d.poison) d.poison[p] = 0;
       if (d.wsum64) d.wsum64[p] = 0ull;
     }
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void k_finalize(Launch L) {
     for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
       if (d.num64) {
         const double den = d.wsum64 ? fx_to_double(d.wsum64[p]) * (1.0 / WEIGHT_SCALE)
-                                    : (d.cnt ? (double)d.cnt[p] : 1.0);
+                                    : (d.cnt && !L.adjoint ? (double)d.cnt[p] : 1.0);
         const double c = den * (double)fx_scale(d);
         const bool bad = d.poison && d.poison[p];
         for (int ch = 0; ch < L.C; ++ch)
@@ -135,19 +135,23 @@ __global__ __launch_bounds__(256) void k_finalize(Launch L) {
   });
 }
 
-// Adjoint input: r = g / cnt into the workspace image buffer (d.out holds g,
-// d.num receives r; see hts_denoise_backward).
+// Adjoint input: r = g / cnt (and max |r|).  Single image: g = d.img, r into
+// the workspace buffer d.num (see hts_denoise_backward).  Batched adjoint
+// (L.adjoint): g = d.num (the caller's gradient), r into d.img (the
+// workspace buffer the filter then reads).
 __global__ __launch_bounds__(256) void k_adjoint_prep(Launch L) {
   for_each_item<W_PIX>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
     const int HW = d.H * d.W;
     const int p0 = item * PIX_CHUNK;
     const int p1 = min(HW, p0 + PIX_CHUNK);
+    const float* g = L.adjoint ? d.num : d.img;
+    float* rr = L.adjoint ? const_cast<float*>(d.img) : d.num;
     uint32_t mb = 0;
     for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
       float inv = 1.0f / d.cnt[p];
       for (int c = 0; c < L.C; ++c) {
-        const float r = d.img[c * HW + p] * inv;
-        d.num[c * HW + p] = r;
+        const float r = g[c * HW + p] * inv;
+        rr[c * HW + p] = r;
         mb = max(mb, abs_bits(r));
       }
     }

@@ -43,10 +43,11 @@ hipError_t launch_filter(const Launch& L, int ty, int tx, int adjoint, int grid,
   const int g = xcd_grid(grid > 0 && grid < L.total ? grid : L.total);
   const bool wt = !adjoint && (L.flags & HTS_FLAG_WEIGHTED);
   const size_t lds = filter_lds_bytes(L.C, L.K, L.stride, L.window, ty, tx, wt);
-  // batched launches (descriptor table) never export masks nor run the adjoint
+  // batched launches (descriptor table) export masks when L.batch_masks is
+  // set (uniform weights, Eq. 19 only) and run the adjoint when asked
   const bool batch = L.table != nullptr;
-  if (batch && adjoint) return hipErrorInvalidValue;
-  const bool masks = !batch && L.one.masks;
+  const bool masks = batch ? L.batch_masks != 0 : L.one.masks != nullptr;
+  if (batch && masks && (wt || (L.flags & HTS_FLAG_FOURIER_THRESHOLD))) return hipErrorInvalidValue;
   if (L.C == 3 && !adjoint && (L.flags & HTS_FLAG_FOURIER_THRESHOLD))
     return launch_filter_ft(L, g, lds, batch, masks, wt, s);
   if (wt) {   // weighted aggregation: no adjoint
@@ -58,12 +59,12 @@ hipError_t launch_filter(const Launch& L, int ty, int tx, int adjoint, int grid,
     return masks ? launch_filter_c<3, 0, 1, 0, 1>(L, g, lds, s) : launch_filter_c<3, 0, 0, 0, 1>(L, g, lds, s);
   }
   if (L.C == 1) {
-    if (batch) return launch_filter_c<1, 0, 0, 1>(L, g, lds, s);
-    if (adjoint) return launch_filter_c<1, 1, 0, 0>(L, g, lds, s);
+    if (adjoint) return batch ? launch_filter_c<1, 1, 0, 1>(L, g, lds, s) : launch_filter_c<1, 1, 0, 0>(L, g, lds, s);
+    if (batch) return masks ? launch_filter_c<1, 0, 1, 1>(L, g, lds, s) : launch_filter_c<1, 0, 0, 1>(L, g, lds, s);
     return masks ? launch_filter_c<1, 0, 1, 0>(L, g, lds, s) : launch_filter_c<1, 0, 0, 0>(L, g, lds, s);
   }
-  if (batch) return launch_filter_c<3, 0, 0, 1>(L, g, lds, s);
-  if (adjoint) return launch_filter_c<3, 1, 0, 0>(L, g, lds, s);
+  if (adjoint) return batch ? launch_filter_c<3, 1, 0, 1>(L, g, lds, s) : launch_filter_c<3, 1, 0, 0>(L, g, lds, s);
+  if (batch) return masks ? launch_filter_c<3, 0, 1, 1>(L, g, lds, s) : launch_filter_c<3, 0, 0, 1>(L, g, lds, s);
   return masks ? launch_filter_c<3, 0, 1, 0>(L, g, lds, s) : launch_filter_c<3, 0, 0, 0>(L, g, lds, s);
 }
 

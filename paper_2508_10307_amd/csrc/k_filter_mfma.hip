@@ -427,7 +427,7 @@ __global__ __launch_bounds__(256, K >= 32 ? 1 : 2) void k_filter_mfma(Launch L) 
             atomicAdd(a0, fx_from_float(o0));
             atomicAdd(a0 + RA * CA, fx_from_float(o1));
             atomicAdd(a0 + 2 * RA * CA, fx_from_float(o2));
-          } else if constexpr (!BATCH) {   // outside the tile's reach: straight to the image
+          } else if constexpr (!BATCH || ADJ) {   // outside the tile's reach: straight to the image
             const int pix = (py + 4 * (q & 1) + j) * d.W + px + n8;
             add_estimate_global(d, 0, pix, o0);
             add_estimate_global(d, 1, pix, o1);
@@ -461,15 +461,19 @@ hipError_t launch_filter_mfma(const Launch& L, int ty, int tx, int adjoint, int 
   if (L.total <= 0) return hipSuccess;
   const int g = xcd_grid(grid > 0 && grid < L.total ? grid : L.total);
   const size_t lds = filter_mfma_lds_bytes(L.stride, L.window, ty, tx);
-  // batched launches (descriptor table) never export masks nor run the adjoint
+  // batched launches (descriptor table) export masks when L.batch_masks is
+  // set and run the adjoint when asked
   const bool batch = L.table != nullptr;
-  if (batch && adjoint) return hipErrorInvalidValue;
-  const bool masks = !batch && L.one.masks;
+  const bool masks = batch ? L.batch_masks != 0 : L.one.masks != nullptr;
 #define HTS_FM(KK)                                                                             \
   case KK:                                                                                     \
-    if (batch) hipLaunchKernelGGL((k_filter_mfma<KK, 0, 0, 1>), dim3(g), dim3(256), lds, s, L);   \
-    else if (adjoint) hipLaunchKernelGGL((k_filter_mfma<KK, 1, 0, 0>), dim3(g), dim3(256), lds, s, L); \
-    else if (masks) hipLaunchKernelGGL((k_filter_mfma<KK, 0, 1, 0>), dim3(g), dim3(256), lds, s, L); \
+    if (adjoint) {                                                                             \
+      if (batch) hipLaunchKernelGGL((k_filter_mfma<KK, 1, 0, 1>), dim3(g), dim3(256), lds, s, L); \
+      else hipLaunchKernelGGL((k_filter_mfma<KK, 1, 0, 0>), dim3(g), dim3(256), lds, s, L);  \
+    } else if (batch) {                                                                        \
+      if (masks) hipLaunchKernelGGL((k_filter_mfma<KK, 0, 1, 1>), dim3(g), dim3(256), lds, s, L); \
+      else hipLaunchKernelGGL((k_filter_mfma<KK, 0, 0, 1>), dim3(g), dim3(256), lds, s, L);  \
+    } else if (masks) hipLaunchKernelGGL((k_filter_mfma<KK, 0, 1, 0>), dim3(g), dim3(256), lds, s, L); \
     else hipLaunchKernelGGL((k_filter_mfma<KK, 0, 0, 0>), dim3(g), dim3(256), lds, s, L);      \
     break;
   switch (L.K) {

@@ -152,6 +152,21 @@ def test_calls_reject_null_pointers_and_small_workspace(lib):
     bad = api.Params(K=12).c()
     assert lib.hts_match(ctypes.byref(bad), FAKE, 1, 64, 64, FAKE, None, None, FAKE, need,
                          None) == L.HTS_ERR_INVALID
+    # batched forward with state and batched adjoint: null states or state
+    # pointers, and the aggregation / threshold variants without masks
+    imgs = (L.HtsImage * 1)(L.HtsImage(FAKE.value, FAKE.value, 3, 64, 64, 10.0))
+    good = L.HtsState(FAKE.value, FAKE.value, FAKE.value, FAKE.value, FAKE.value)
+    states = (L.HtsState * 1)(good)
+    nulls = (L.HtsState * 1)(L.HtsState(FAKE.value, None, FAKE.value, FAKE.value, FAKE.value))
+    for fn in (lib.hts_denoise_batch_save, lib.hts_denoise_batch_backward):
+        assert fn(bp, imgs, None, 1, FAKE, 1 << 40, None) == L.HTS_ERR_INVALID
+        assert fn(bp, imgs, nulls, 1, FAKE, 1 << 40, None) == L.HTS_ERR_INVALID
+        assert fn(bp, imgs, states, 0, FAKE, 1 << 40, None) == L.HTS_ERR_INVALID
+        for flags in (L.HTS_FLAG_WEIGHTED, L.HTS_FLAG_FOURIER_THRESHOLD):
+            pf = api.Params(flags=flags).c()
+            assert fn(ctypes.byref(pf), imgs, states, 1, FAKE, 1 << 40,
+                      None) == L.HTS_ERR_UNSUPPORTED
+        assert fn(bp, imgs, states, 1, FAKE, 16, None) == L.HTS_ERR_WORKSPACE
 
 
 def test_workspace_grows_with_image():

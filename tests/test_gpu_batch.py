@@ -177,3 +177,137 @@ def test_staged_batch_equals_the_graph_and_times_its_stages():
     assert all(m >= 0.0 for m in ms) and ms[1] > 0.0 and ms[4] > 0.0
     with pytest.raises(RuntimeError):
         api.hts_denoise_batch_staged(xs, sig, p, outs, ws, ev[:6])
+
+
+# ------------------------------------------------- batched forward state and adjoint
+def _state_equal(a, b):
+    for k in ("idx", "masks", "U", "V", "cnt"):
+        assert torch.equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("tune", [1, 1 | (1 << 6)], ids=["mfma", "valu"])
+def test_batch_save_writes_the_per_image_state(tune):
+    """hts_denoise_batch_save: outputs and every image's idx, masks, U, V and
+    cnt equal those of hts_denoise(save) on that image alone, bit for bit
+    (the batch's mask buffers start all ones, so every word is written)."""
+    p = api.Params(stride=3, window=15, K=16, tune=tune)
+    imgs, sig = make_batch(41)
+    xs = [T(y) for y in imgs]
+    states = [api.new_state(p, *x.shape, dev()) for x in xs]
+    for st in states:
+        st["masks"].fill_(-1)
+    outs, states = api.hts_denoise_batch_save(xs, sig, p, states=states)
+    torch.cuda.synchronize()
+    for i, (x, s) in enumerate(zip(xs, sig)):
+        o, st = api.hts_denoise(x, s, p, save=True)
+        log("batch save", i, SHAPES[i])
+        assert torch.equal(outs[i], o)
+        _state_equal(states[i], st)
+    # the plain batch is unchanged beside it
+    for o, r in zip(api.hts_denoise_batch(xs, sig, p), outs):
+        assert torch.equal(o, r)
+
+
+@pytest.mark.parametrize("tune", [1, 1 | (1 << 6)], ids=["mfma", "valu"])
+def test_batch_backward_equals_per_image_adjoint(tune):
+    """hts_denoise_batch_backward gives each image's hts_denoise_backward
+    bit for bit, on graph replays with new gradients and swapped states,
+    and with grad_in written over grad_out."""
+    p = api.Params(stride=3, window=15, K=16, tune=tune)
+    imgs, sig = make_batch(43)
+    xs = [T(y) for y in imgs]
+    _, states = api.hts_denoise_batch_save(xs, sig, p)
+    imgs2, sig2 = make_batch(44)   # the same shapes, other images: other state buffers
+    _, states2 = api.hts_denoise_batch_save([T(y) for y in imgs2], sig2, p)
+    rng = np.random.default_rng(9)
+    n = len(xs)
+    ws = None
+    for rep in range(3):
+        gs = [T(rng.normal(size=x.shape)) for x in xs]
+        sts = states2 if rep == 1 else states
+        gins = [torch.empty_like(g) for g in gs]
+        if ws is None:
+            ws = torch.empty(api.batch_workspace_size(p, gs, gins, [0.0] * n), dtype=torch.uint8,
+                             device=dev())
+        api.hts_denoise_batch_backward(gs, sts, p, grad_ins=gins, ws=ws)
+        torch.cuda.synchronize()
+        for i in range(n):
+            ref, gtau = api.hts_denoise_backward(gs[i], sts[i], p)
+            assert torch.equal(gins[i], ref), (rep, i)
+            assert gtau.item() == 0.0
+        x2 = torch.randn(64, 64, device=dev())   # other GPU work between replays
+        (x2 @ x2).sum().item()
+    # in place: grad_in over grad_out
+    gs = [T(rng.normal(size=x.shape)) for x in xs]
+    refs = [api.hts_denoise_backward(g, st, p)[0] for g, st in zip(gs, states)]
+    api.hts_denoise_batch_backward(gs, states, p, grad_ins=gs, ws=ws)
+    torch.cuda.synchronize()
+    for g, r in zip(gs, refs):
+        assert torch.equal(g, r)
+
+
+def test_batch_backward_adjoint_identity_and_oracle():
+    """<D a, z> = <a, D^T z> for the frozen linear map D of every image
+    (oracle frozen_forward), and one image's D^T z against the oracle's
+    frozen adjoint."""
+    from oracle import adjoint as oadj
+    p = api.Params(stride=3, window=15, K=16)
+    imgs, sig = make_batch(45)
+    xs = [T(y) for y in imgs]
+    _, states = api.hts_denoise_batch_save(xs, sig, p)
+    rng = np.random.default_rng(11)
+    zs = [rng.normal(size=y.shape) for y in imgs]
+    gins = api.hts_denoise_batch_backward([T(z) for z in zs], states, p)
+    torch.cuda.synchronize()
+    for i in (0, 2, 4):
+        st = states[i]
+        idx = st["idx"].cpu().numpy().astype(np.int64)
+        masks = opipe.unpack_masks(st["masks"].cpu().numpy().view(np.uint32), len(idx), p.K, 3)
+        U, V, cnt = st["U"].cpu().numpy(), st["V"].cpu().numpy(), st["cnt"].cpu().numpy()
+        a = rng.normal(size=imgs[i].shape)
+        Da, cnt_o = oadj.frozen_forward(a, idx, masks, U, V, p.K)
+        np.testing.assert_array_equal(cnt, cnt_o)
+        gz = gins[i].cpu().numpy().astype(np.float64)
+        lhs, rhs = np.vdot(Da, zs[i]), np.vdot(a, gz)
+        log("batched adjoint dot", i, lhs, rhs)
+        assert abs(lhs - rhs) <= 1e-4 * max(1.0, abs(lhs))
+        ref = oadj.frozen_adjoint(zs[i], idx, masks, U, V, cnt_o, p.K)
+        assert np.abs(gz - ref).max() <= 1e-4 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("tune", [1, 1 | (1 << 6)], ids=["mfma", "valu"])
+def test_batch_backward_takes_an_idx_from_a_larger_window(tune):
+    """The batched adjoint accepts any grouping, as hts_denoise_backward
+    does: groups of a window-25 match under window-9 parameters put patches
+    outside the work group's tile (they go straight to the image)."""
+    y = synth.tiny(4243, 3, 56, 60, sigma=20.0)
+    x = T(y)
+    _, st = api.hts_denoise(x, 20.0, api.Params(stride=3, window=25, K=16), save=True)
+    pn = api.Params(stride=3, window=9, K=16, tune=tune)
+    r = api.hts_filter(x, 20.0, st["idx"], st["U"], st["V"], pn, want_masks=True)
+    st2 = dict(st, masks=r["masks"], cnt=r["cnt"])
+    g = T(np.random.default_rng(6).normal(size=y.shape))
+    ref, _ = api.hts_denoise_backward(g, st2, pn)
+    y2 = synth.tiny(4244, 3, 40, 52, sigma=20.0)
+    _, st3 = api.hts_denoise(T(y2), 20.0, pn, save=True)
+    g2 = T(np.random.default_rng(7).normal(size=y2.shape))
+    ref2, _ = api.hts_denoise_backward(g2, st3, pn)
+    gins = api.hts_denoise_batch_backward([g, g2], [st2, st3], pn)
+    torch.cuda.synchronize()
+    assert torch.equal(gins[0], ref)
+    assert torch.equal(gins[1], ref2)
+
+
+def test_batch_save_and_backward_reject_bad_arguments():
+    p = api.Params(stride=3, window=15, K=16)
+    x = torch.zeros((3, 40, 40), device=dev())
+    st = api.new_state(p, 3, 40, 40, dev())
+    for flags in (1, 2):   # weighted aggregation, channel-Fourier threshold
+        pf = api.Params(stride=3, window=15, K=16, flags=flags)
+        with pytest.raises(RuntimeError):
+            api.hts_denoise_batch_save([x], [10.0], pf, states=[st])
+        with pytest.raises(RuntimeError):
+            api.hts_denoise_batch_backward([x], [st], pf)
+    bad = dict(st, cnt=torch.empty(0, device=dev()))   # data_ptr() of an empty tensor is null
+    with pytest.raises(RuntimeError):
+        api.hts_denoise_batch_backward([x], [bad], p)

@@ -588,6 +588,51 @@ class HaarTSVD(torch.autograd.Function):
         return gin, None, gtau.reshape(()) if ctx.needs_input_grad[2] else None, None, None, None
 
 
+class HaarTSVDBatch(torch.autograd.Function):
+    """HaarTSVD over a batch [N, C, H, W] with one noise level per image:
+    forward = hts_denoise_batch_save, backward = hts_denoise_batch_backward
+    (one graph-captured pipeline each way), the same values as HaarTSVD per
+    image.  tau_mult is shared by the batch: with tau_kappa > 0 its
+    surrogate derivative is the sum of the images' hts_denoise_grad_tau;
+    basis_grad=True adds each image's derivative through its basis."""
+
+    @staticmethod
+    def forward(ctx, noisy, sigmas, tau_mult, p: Params, tau_kappa: float = 0.0,
+                basis_grad: bool = False):
+        q = Params(**{**p.__dict__, "tau_mult": float(tau_mult)})
+        x = noisy.detach()
+        if x.dim() != 4:
+            raise ValueError("noisy must be [N, C, H, W]")
+        x = x.contiguous()
+        sig = [float(v) for v in torch.as_tensor(sigmas, dtype=torch.float64).reshape(-1).tolist()]
+        if len(sig) == 1:
+            sig = sig * x.shape[0]
+        if len(sig) != x.shape[0]:
+            raise ValueError("one sigma per image")
+        out = torch.empty_like(x)
+        _, st = hts_denoise_batch_save(list(x.unbind(0)), sig, q, outs=list(out.unbind(0)))
+        ctx.st, ctx.p, ctx.sig = st, q, sig
+        ctx.kappa = float(tau_kappa)
+        ctx.basis_grad = bool(basis_grad)
+        ctx.noisy = x if (ctx.kappa > 0 or ctx.basis_grad) else None
+        return out
+
+    @staticmethod
+    def backward(ctx, grad):
+        g = grad.contiguous()
+        gin = torch.empty_like(g)
+        gs, gi = list(g.unbind(0)), list(gin.unbind(0))
+        hts_denoise_batch_backward(gs, ctx.st, ctx.p, grad_ins=gi)
+        gtau = torch.zeros(1, dtype=torch.float32, device=g.device)
+        for i in range(len(gs)):
+            if ctx.basis_grad:
+                hts_denoise_backward_basis(ctx.noisy[i], gs[i], ctx.st[i], ctx.p, gi[i])
+            if ctx.kappa > 0:
+                gtau += hts_denoise_grad_tau(ctx.noisy[i], gs[i], ctx.st[i], ctx.sig[i], ctx.p,
+                                             ctx.kappa)
+        return gin, None, gtau.reshape(()) if ctx.needs_input_grad[2] else None, None, None, None
+
+
 def denoise(x: torch.Tensor, sigma: float, **params) -> torch.Tensor:
     """Convenience: denoise one [C, H, W] float32 GPU image."""
     return hts_denoise(x, sigma, Params(**params))

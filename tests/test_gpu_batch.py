@@ -311,3 +311,41 @@ def test_batch_save_and_backward_reject_bad_arguments():
     bad = dict(st, cnt=torch.empty(0, device=dev()))   # data_ptr() of an empty tensor is null
     with pytest.raises(RuntimeError):
         api.hts_denoise_batch_backward([x], [bad], p)
+
+
+def test_autograd_batch_equals_per_image_autograd():
+    """HaarTSVDBatch over [N, C, H, W]: outputs and input gradients equal
+    those of HaarTSVD image by image; the shared threshold multiplier's
+    surrogate derivative is the sum of the images' derivatives, and the
+    basis term adds in as per image."""
+    p = api.Params(stride=3, window=15, K=16)
+    N, C, H, W = 4, 3, 48, 56
+    ys = [synth.tiny(700 + i, C, H, W, sigma=10.0 + 5 * i) for i in range(N)]
+    sig = [10.0 + 5 * i for i in range(N)]
+    clean = torch.stack([T(synth.tiny(700 + i, C, H, W, sigma=0.0)) for i in range(N)])
+    for kappa, basis_grad in ((0.0, False), (0.1, True)):
+        xb = torch.stack([T(y) for y in ys]).requires_grad_(True)
+        tb = torch.tensor(2.7, device=dev(), requires_grad=True)
+        ob = api.HaarTSVDBatch.apply(xb, sig, tb, p, kappa, basis_grad)
+        ((ob - clean) ** 2).sum().backward()
+        outs, grads, gt = [], [], []
+        for i in range(N):
+            xi = T(ys[i]).requires_grad_(True)
+            ti = torch.tensor(2.7, device=dev(), requires_grad=True)
+            oi = api.HaarTSVD.apply(xi, sig[i], ti, p, kappa, basis_grad)
+            ((oi - clean[i]) ** 2).sum().backward()
+            outs.append(oi.detach())
+            grads.append(xi.grad)
+            gt.append(ti.grad.item())
+        torch.cuda.synchronize()
+        assert torch.equal(ob.detach(), torch.stack(outs))
+        assert torch.equal(xb.grad, torch.stack(grads))
+        log("batched autograd", kappa, basis_grad, tb.grad.item(), sum(gt))
+        if kappa == 0.0:
+            assert tb.grad.item() == 0.0
+        else:
+            assert abs(tb.grad.item() - sum(gt)) <= 1e-5 * max(1.0, abs(sum(gt)))
+    with pytest.raises(ValueError):
+        api.HaarTSVDBatch.apply(xb.detach()[0], sig, 2.7, p)
+    with pytest.raises(ValueError):
+        api.HaarTSVDBatch.apply(xb.detach(), sig[:3], 2.7, p)

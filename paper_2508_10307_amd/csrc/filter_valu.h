@@ -190,6 +190,7 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
   constexpr bool glob = WT == 2 && !ADJ;
   constexpr bool ft = FT != 0 && C == 3 && !ADJ;
   constexpr int NP = C + (wtd ? 1 : 0);
+  constexpr bool units = WT != 1 && !ADJ;   // integer-unit numerator (fx_int_units)
   unsigned long long* acc = (unsigned long long*)fsm;          // [NP][RA][CA] fixed point
   float* T = fsm + (glob ? 0 : (2 * NP * RA * CA + 3) / 4 * 4) + wave * TSCRATCH;   // transpose scratch
 
@@ -207,9 +208,8 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
     // adjusted noise level (A-Haar-tSVD) when the descriptor carries one
     const float tau = d.sigma_dev ? L.tau_mult * *d.sigma_dev : d.tau;
     const float rW = 1.0f / (float)d.W;
-    const float fxs = fx_scale(d);                 // fixed-point scale of the estimates
+    const float fxs = fx_scale(d, units);          // fixed-point scale of the estimates
     const float rfxs = 1.f / fxs;
-    const float s3 = fxs * (1.f / 3.f);
     float tauj[SPL], wj[SPL];                      // thresholds and inverse weights of this lane's slots
     float tq0[SPL], tq1[SPL];                      // FT: squared thresholds of f = 0 and of the f = 1 pair
 #pragma unroll
@@ -447,9 +447,14 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
       // the weight plane for every pixel of the group's patches
       const float wg = wtd ? 1.f / (float)max(nkeep, 1) : 1.f;
       const unsigned long long fxw = wtd ? fx_from_float(wg * WEIGHT_SCALE) : 0ull;
-      const float sc1 = fxs * wg, sc3 = s3 * wg, rge = rfxs / wg;
+      const float rge = rfxs / wg;
 
       // ---- inverse t-SVD projection U * S * V^T (Eq. 20) and write-back ----
+      // The V slices of the last product carry the output scale (the
+      // fixed-point scale, times 1/3 for c = 3), so for c = 3 the row comes
+      // out as the fixed-point channel-DFT triple (F0, Re F1, Im F1) / 3 of
+      // the estimate (fx_fourier): the inverse channel DFT moves to the
+      // write-back.
 #pragma unroll
       for (int j = 0; j < SPL; ++j) {
         __builtin_amdgcn_sched_barrier(0);  // keep one slot's temporaries live at a time
@@ -458,9 +463,10 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
           float y[8];
           mv<false>(X[j][0], fb, FB_U0, 1.f, y);   // y[r] = sum_i U[r][i] s[i]
           transpose_cr(T, kl, a, y);
-          mv<false>(y, fb, FB_V0, 1.f, out[0]);    // out[b] = sum_c y[c] V[b][c]
+          mv<false>(y, fb, FB_V0S, 1.f, out[0]);   // out[b] = sum_c y[c] V[b][c] (scaled)
+          if (wtd)
 #pragma unroll
-          for (int b = 0; b < 8; ++b) out[0][b] *= sc1;   // fixed-point scale (a power of two) x weight
+            for (int b = 0; b < 8; ++b) out[0][b] *= wg;
         } else {
           float s0[8], s1r[8], s1i[8];
 #pragma unroll
@@ -484,21 +490,17 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
           transpose_cr(T, kl, a, y0);
           transpose_cr(T, kl, a, y1r);
           transpose_cr(T, kl, a, y1i);
-          // P^ = Y V_F^H: p[b] = sum_c y[c] conj(V[b][c])
-          float p0[8], p1r[8], p1i[8];
-          mv<false>(y0, fb, FB_V0, 1.f, p0);
+          // P^ = Y V_F^H: p[b] = sum_c y[c] conj(V[b][c]) (scaled slices)
+          mv<false>(y0, fb, FB_V0S, 1.f, out[0]);
           // p1 = conj(V_F(1)) y1 per row: (V1R - i V1I)(y1r + i y1i)
-          cmv(y1r, y1i, fb, FB_V1R, FB_V1I, -1.f, FB_V1M, p1r, p1i);
+          cmv(y1r, y1i, fb, FB_V1RS, FB_V1IS, -1.f, FB_V1MS, out[1], out[2]);
+          if (wtd)
 #pragma unroll
-          for (int b = 0; b < 8; ++b) {
-            // scaled by fxs (a power of two) x weight; FT: the Fourier
-            // coefficients were F / 3, so no 1/3 here
-            const float scl = ft ? sc1 : sc3;
-            const float sr = p1r[b], si = p1i[b];
-            out[0][b] = (p0[b] + 2.f * sr) * scl;
-            out[1][b] = (p0[b] - sr - SQRT3 * si) * scl;
-            out[2][b] = (p0[b] - sr + SQRT3 * si) * scl;
-          }
+            for (int b = 0; b < 8; ++b) {
+              out[0][b] *= wg;
+              out[1][b] *= wg;
+              out[2][b] *= wg;
+            }
         }
         const int ly = py[j] + a - AY0, lx = px[j] - AX0;
         // a patch outside the tile's reach (an idx entry that is not from
@@ -525,7 +527,7 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
             for (int ch = 0; ch < C; ++ch) {
               unsigned long long* rowp = acc + (ch * RA + ly) * CA + lx;
 #pragma unroll
-              for (int b = 0; b < 8; ++b) atomicAdd(rowp + b, fx_from_float(out[ch][b]));
+              for (int b = 0; b < 8; ++b) atomicAdd(rowp + b, fx_from<units>(out[ch][b]));
             }
             if (wtd) {
               unsigned long long* wrow = acc + (C * RA + ly) * CA + lx;
@@ -537,17 +539,26 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
             // always lie inside the tile: no cold path, no register cost; the
             // batched adjoint takes the caller's indices and keeps it)
             const int pix = (py[j] + a) * d.W + px[j];
-            for (int ch = 0; ch < C; ++ch)
-              for (int b = 0; b < 8; ++b) add_estimate_global(d, ch, pix + b, out[ch][b]);
+            for (int b = 0; b < 8; ++b) {
+              const float v3[3] = {out[0][b], out[C > 1 ? 1 : 0][b], out[C > 1 ? 2 : 0][b]};
+              add_pixel_global<units>(d, C, pix + b, v3, fxs);
+            }
             if (wtd)
               for (int b = 0; b < 8; ++b) add_weight_global(d, pix + b, fxw);
           }
-          if (d.group_est) {
+          if (d.group_est) {   // image units, unweighted (c = 3: channel DFT inverted)
             float* ge = d.group_est + (((size_t)grel * K + k) * C) * PS2 + a * 8;
 #pragma unroll
-            for (int ch = 0; ch < C; ++ch)
-#pragma unroll
-              for (int b = 0; b < 8; ++b) ge[ch * PS2 + b] = out[ch][b] * rge;   // unweighted
+            for (int b = 0; b < 8; ++b) {
+              if (C == 3) {
+                const float a0 = out[0][b], a1 = out[C > 1 ? 1 : 0][b], a2 = out[C > 1 ? 2 : 0][b];
+                ge[b] = fmaf(2.f, a1, a0) * rge;
+                ge[PS2 + b] = fmaf(-SQRT3, a2, a0 - a1) * rge;
+                ge[2 * PS2 + b] = fmaf(SQRT3, a2, a0 - a1) * rge;
+              } else {
+                ge[b] = out[0][b] * rge;
+              }
+            }
           }
         }
       }
@@ -555,7 +566,7 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
     }
     if (!glob) {
       __syncthreads();
-      flush_tile(d, acc, C, RA, CA, AY0, AX0, AH, AW, wtd);
+      flush_tile(d, acc, C, RA, CA, AY0, AX0, AH, AW, units, fxs, wtd);
     }
   });
 }

@@ -685,6 +685,10 @@ hts_status hts_filter(const hts_params* p, const float* noisy, int32_t C, int32_
   } else {
     d.cnt = nullptr;      // no numerator asked for: no coverage counts either
   }
+  if (fx_int_units(C, p->flags, 0)) {   // the scale of the filter's integer-unit tiles
+    HIPCHK(launch_fill((float*)d.fxmax, 1, 0.f, s));
+    HIPCHK(launch_absmax(make_launch(p, C, d, W_PIX, sc.fty, sc.ftx), 0, s));
+  }
   return run_filter(p, C, sc, d, 0, s, U, V);
 }
 
@@ -807,6 +811,7 @@ hts_status hts_denoise_backward(const hts_params* p, const float* grad_out, cons
   a.cnt = nullptr;
   a.idx = const_cast<int32_t*>(idx);
   a.masks_in = masks;
+  a.num_enc = NUM_FINE;        // the adjoint's numerator in 2^-32 units
   HIPCHK(launch_zero_accum(make_launch(p, C, a, W_PIX, sc.fty, sc.ftx), 0, s));
   st = run_filter(p, C, sc, a, 1, s, U, V);
   if (st != HTS_OK) return st;
@@ -1062,6 +1067,7 @@ hts_status hts_denoise_batch_backward(const hts_params* p, const hts_image* imgs
     d.tau = 0.f;
     d.idx = states[i].idx;
     d.masks_in = states[i].masks;
+    d.num_enc = NUM_FINE;   // the adjoint's numerator in 2^-32 units
     d.masks = nullptr;
     d.cnt = states[i].cnt;
     d.U_ext = states[i].U;
@@ -1426,6 +1432,7 @@ hts_status hts_denoise_video_backward(const hts_params* p, const float* grad_out
   a.fbasis = (float*)(b + vp.fbasis);
   a.gscratch = (float*)(b + vp.gscratch);
   a.out = (float*)(b + vp.stacked);              // grad_out is no longer needed
+  a.num_enc = NUM_FINE | NUM_PIXELS;             // k_filter_gen's pixel sums
   const size_t nb = (size_t)C * PS2 * sizeof(float);
   HIPCHK(hipMemcpyAsync(a.basis, U, nb, hipMemcpyDeviceToDevice, s));
   HIPCHK(hipMemcpyAsync(a.basis + C * PS2, V, nb, hipMemcpyDeviceToDevice, s));

@@ -51,7 +51,8 @@ struct ImgDesc {
   float* basis;            // U[C][8][8], V[C][8][8] (real tensors)
   float* fbasis;           // Fourier slices for the filter, see FB_* offsets
   float* num;              // [C][H][W] float accumulator (caller's, or adjoint input)
-  unsigned long long* num64; // [C][H][W] fixed-point accumulator (2^-32 units), nullable
+  unsigned long long* num64; // [C][H][W] fixed-point accumulator, nullable (encoding:
+                             // fx_int_units, fx_fourier in hts_device.h)
   uint8_t* poison;         // [H][W] 1 where a non-finite estimate landed (with num64)
   uint32_t* fxmax;         // [1] bits of max |input| (sets the fixed-point scale)
   float* cnt;              // [H][W]
@@ -76,6 +77,8 @@ struct ImgDesc {
   float* V_ext;
   double* ufg;             // general c: [2 * (C/2+1)][re/im][64] Fourier-domain eigenvectors
   float* gscratch;         // general c: filter scratch, [work group][K][C][64]
+  int32_t num_enc;         // NUM_FINE | NUM_PIXELS bits: how num64 encodes the sums
+                           // beyond what C and the flags say (fx_int_units, fx_fourier)
   int32_t woff[W_NKIND];   // first global work item of each kind (batched)
   int32_t wcnt[W_NKIND];   // work items of each kind
 };
@@ -92,7 +95,23 @@ constexpr int FB_U0 = 0, FB_V0 = 64, FB_U1R = 128, FB_U1I = 192, FB_V1R = 256, F
 constexpr int FB_V0T = 384, FB_V1RT = 448, FB_V1IT = 512, FB_V1PT = 576;
 constexpr int FB_U0T = 640, FB_U1RT = 704, FB_U1IT = 768, FB_U1MT = 832;
 constexpr int FB_U1P = 896, FB_V1M = 960;
-constexpr int FB_SIZE = 1024;
+// The slices of the inverse right product (V0, V1R, V1I, V1M) scaled by the
+// output scale of the c = 1, 3 filters' estimates: the fixed-point scale
+// times 1/3 for c = 3 (the inverse channel DFT's factor; 1 with the
+// channel-Fourier threshold, whose coefficients already carry it).
+constexpr int FB_V0S = 1024, FB_V1RS = 1088, FB_V1IS = 1152, FB_V1MS = 1216;
+constexpr int FB_SIZE = 1280;
+
+// Encoding of the fixed-point numerator num64 (see hts_device.h): integer
+// units for the forward c = 1, 3 filters with uniform weights, else 2^-32
+// units (NUM_FINE: the frozen adjoints, whose dot-product identity wants
+// more than FP32-level rounding of each estimate); channel-DFT triples for
+// c = 3 unless the band-count filter produced the sums (NUM_PIXELS).
+constexpr int NUM_FINE = 1, NUM_PIXELS = 2;
+__host__ __device__ inline bool fx_int_units(int C, int flags, int enc) {
+  return (C == 1 || C == 3) && !(flags & HTS_FLAG_WEIGHTED) && !(enc & NUM_FINE);
+}
+__host__ __device__ inline bool fx_fourier(int C, int enc) { return C == 3 && !(enc & NUM_PIXELS); }
 
 struct Launch {
   ImgDesc one;             // used when table == nullptr
@@ -200,6 +219,7 @@ __host__ __device__ inline int rowp_floats(int C) { return 8 * C; }
 hipError_t launch_finalize(const Launch& L, int grid, hipStream_t s);
 hipError_t launch_scatter_est(const Launch& L, hipStream_t s);
 hipError_t launch_adjoint_prep(const Launch& L, int grid, hipStream_t s);
+hipError_t launch_absmax(const Launch& L, int grid, hipStream_t s);
 hipError_t launch_synth(float* img, int C, int H, int W, hipStream_t s);
 hipError_t launch_zero_hist(const Launch& L, int grid, hipStream_t s);
 hipError_t launch_fill(float* p, int n, float v, hipStream_t s);   // fill kernel (graph-safe)

@@ -236,11 +236,16 @@ __global__ __launch_bounds__(256) void k_eig(Launch L) {
 // Fourier slices (float) of the real basis tensors for the filter:
 // U_F(f) = sum_j U(:,:,j) exp(-2 pi i f j / c), evaluated in FP64.
 // U_ext / V_ext (single-image launches, nullable) replace the image's own
-// basis as the source.
+// basis as the source.  The scaled V slices (FB_V0S...) carry the filters'
+// output scale: the fixed-point scale of the image's numerator encoding,
+// times 1/3 for c = 3 unless the threshold is the channel-Fourier one.
 __global__ void k_fbasis(Launch L, const float* U_ext, const float* V_ext) {
   const int nimg = L.table ? L.n_img : 1;
   for (int im = blockIdx.x; im < nimg; im += gridDim.x) {
     const ImgDesc d = L.table ? L.table[im] : L.one;
+    const bool ft = L.C == 3 && (L.flags & HTS_FLAG_FOURIER_THRESHOLD);
+    const double osc = (double)fx_scale(d, fx_int_units(L.C, L.flags, d.num_enc)) *
+                       (L.C == 3 && !ft ? 1.0 / 3.0 : 1.0);
     for (int e = threadIdx.x; e < 128; e += blockDim.x) {
       const int uv = e >> 6, ab = e & 63;
       const float* ext = uv ? V_ext : U_ext;
@@ -249,6 +254,7 @@ __global__ void k_fbasis(Launch L, const float* U_ext, const float* V_ext) {
       if (L.C == 1) {
         d.fbasis[(uv ? FB_V0 : FB_U0) + ab] = T[ab];
         d.fbasis[(uv ? FB_V0T : FB_U0T) + tr] = T[ab];
+        if (uv) d.fbasis[FB_V0S + ab] = (float)(osc * (double)T[ab]);
       } else {
         double f0, f1r, f1i;
         dft3((double)T[ab], (double)T[64 + ab], (double)T[128 + ab], f0, f1r, f1i);
@@ -264,6 +270,10 @@ __global__ void k_fbasis(Launch L, const float* U_ext, const float* V_ext) {
         if (uv) {
           d.fbasis[FB_V1PT + tr] = (float)(f1r + f1i);
           d.fbasis[FB_V1M + ab] = (float)(f1r - f1i);
+          d.fbasis[FB_V0S + ab] = (float)(osc * f0);
+          d.fbasis[FB_V1RS + ab] = (float)(osc * f1r);
+          d.fbasis[FB_V1IS + ab] = (float)(osc * f1i);
+          d.fbasis[FB_V1MS + ab] = (float)(osc * (f1r - f1i));
         } else {
           d.fbasis[FB_U1MT + tr] = (float)(q * (f1r - f1i));
           d.fbasis[FB_U1P + ab] = (float)(f1r + f1i);

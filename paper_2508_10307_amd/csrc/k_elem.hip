@@ -46,6 +46,21 @@ __global__ __launch_bounds__(256) void k_quant(Launch L) {
   });
 }
 
+// Magnitude reduction of the filter input alone (bits of max |x| over all
+// channels into *d.fxmax, zeroed by the caller): the fixed-point scale for
+// calls that filter without quantising first.
+__global__ __launch_bounds__(256) void k_absmax(Launch L) {
+  for_each_item<W_PIX>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
+    const int HW = d.H * d.W;
+    const int p0 = item * PIX_CHUNK;
+    const int p1 = min(HW, p0 + PIX_CHUNK);
+    uint32_t mb = 0;
+    for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x)
+      for (int c = 0; c < L.C; ++c) mb = max(mb, abs_bits(d.img[(size_t)c * HW + p]));
+    absmax_to(d.fxmax, mb);
+  });
+}
+
 // Eq. 10 branch of every reference: green guide when
 // num^2 |qG|^2 >= den^2 max(|qR|^2, |qB|^2) on the reference patch (exact int64).
 __global__ __launch_bounds__(256) void k_gcp(Launch L) {
@@ -110,10 +125,11 @@ __global__ __launch_bounds__(256) void k_zero_accum(Launch L) {
 
 // Eq. 2: out = num / cnt (uniform weights) or num / weight sum (weighted
 // aggregation, when the descriptor has the weight plane), from the
-// fixed-point numerator when the descriptor has one (scales divided out,
-// one rounding, in FP64), else from the float numerator.  Without cnt the numerator is
-// converted as it is (the adjoint's output).  Pixels marked in the poison
-// plane become NaN.
+// fixed-point numerator when the descriptor has one (decoded as its encoding
+// says: scales divided out and, for the channel-DFT triples of c = 3, the
+// channel DFT inverted, in FP64 with one rounding), else from the float
+// numerator.  Without cnt the numerator is converted as it is (the
+// adjoint's output).  Pixels marked in the poison plane become NaN.
 __global__ __launch_bounds__(256) void k_finalize(Launch L) {
   for_each_item<W_PIX>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
     const int HW = d.H * d.W;
@@ -121,12 +137,23 @@ __global__ __launch_bounds__(256) void k_finalize(Launch L) {
     const int p1 = min(HW, p0 + PIX_CHUNK);
     for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
       if (d.num64) {
+        const bool units = fx_int_units(L.C, L.flags, d.num_enc);
         const double den = d.wsum64 ? fx_to_double(d.wsum64[p]) * (1.0 / WEIGHT_SCALE)
                                     : (d.cnt && !L.adjoint ? (double)d.cnt[p] : 1.0);
-        const double c = den * (double)fx_scale(d);
+        const double c = den * (double)fx_scale(d, units);
         const bool bad = d.poison && d.poison[p];
-        for (int ch = 0; ch < L.C; ++ch)
-          d.out[ch * HW + p] = bad ? __builtin_nanf("") : (float)(fx_to_double(d.num64[ch * HW + p]) / c);
+        if (fx_fourier(L.C, d.num_enc)) {
+          double x0, x1, x2;
+          fx_idft3(fx_value(d.num64[p], units), fx_value(d.num64[HW + p], units),
+                   fx_value(d.num64[2 * HW + p], units), x0, x1, x2);
+          d.out[p] = bad ? __builtin_nanf("") : (float)(x0 / c);
+          d.out[HW + p] = bad ? __builtin_nanf("") : (float)(x1 / c);
+          d.out[2 * HW + p] = bad ? __builtin_nanf("") : (float)(x2 / c);
+        } else {
+          for (int ch = 0; ch < L.C; ++ch)
+            d.out[ch * HW + p] =
+                bad ? __builtin_nanf("") : (float)(fx_value(d.num64[ch * HW + p], units) / c);
+        }
       } else {
         const float inv = 1.0f / d.cnt[p];
         for (int ch = 0; ch < L.C; ++ch) d.out[ch * HW + p] = d.num[ch * HW + p] * inv;
@@ -239,6 +266,11 @@ hipError_t launch_gcp(const Launch& L, int grid, hipStream_t s) {
 }
 hipError_t launch_reset_counters(const Launch& L, hipStream_t s) {
   hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(256), 0, s, L);
+  return hipGetLastError();
+}
+hipError_t launch_absmax(const Launch& L, int grid, hipStream_t s) {
+  if (L.total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_absmax, dim3(grid_for(L, grid)), dim3(256), 0, s, L);
   return hipGetLastError();
 }
 hipError_t launch_zero_accum(const Launch& L, int grid, hipStream_t s) {

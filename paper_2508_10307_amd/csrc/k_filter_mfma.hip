@@ -121,8 +121,9 @@ __global__ __launch_bounds__(256, K >= 32 ? 1 : 2) void k_filter_mfma(Launch L) 
     // adjusted noise level (A-Haar-tSVD) when the descriptor carries one
     const float tau = d.sigma_dev ? L.tau_mult * *d.sigma_dev : d.tau;
     const float rW = 1.0f / (float)d.W;
-    const float fxs = fx_scale(d);                 // fixed-point scale of the estimates
-    const float s3 = fxs * (1.f / 3.f), rfxs = 1.f / fxs;
+    constexpr bool units = !ADJ;                   // integer units (fx_int_units)
+    const float fxs = fx_scale(d, units);          // fixed-point scale
+    const float rfxs = 1.f / fxs;
     const float sgl = s ? -1.f : 1.f;              // level-1 butterfly: odd slot o - v, even v + o
     const float* fb = d.fbasis;
 
@@ -154,9 +155,10 @@ __global__ __launch_bounds__(256, K >= 32 ? 1 : 2) void k_filter_mfma(Launch L) 
         Ai1[ks] = wd * ur + wo * ui;
         Ai0[ks] = wd * u0;
       }
-      {  // inverse right: k = (ri = ks/2, b = 2q + ks%2), column n = (ro = s, t = n8)
+      {  // inverse right: k = (ri = ks/2, b = 2q + ks%2), column n = (ro = s, t = n8);
+         // the slices carry the output scale (the fixed-point scale / 3)
         const int ri = ks >> 1, b = 2 * q + (ks & 1), ro = s, t = n8;
-        const float vr = fb[FB_V1R + t * 8 + b], vi = fb[FB_V1I + t * 8 + b], v0 = fb[FB_V0 + t * 8 + b];
+        const float vr = fb[FB_V1RS + t * 8 + b], vi = fb[FB_V1IS + t * 8 + b], v0 = fb[FB_V0S + t * 8 + b];
         const float wd = ri == ro ? 1.f : 0.f, wo = ri == ro ? 0.f : (ri == 0 ? -1.f : 1.f);
         Bi1[ks] = wd * vr + wo * vi;
         Bi0[ks] = wd * v0;
@@ -394,7 +396,9 @@ __global__ __launch_bounds__(256, K >= 32 ? 1 : 2) void k_filter_mfma(Launch L) 
       }
 
       __builtin_amdgcn_sched_barrier(0);
-      // ---- pair exchange, inverse channel DFT and write-back ----
+      // ---- pair exchange and write-back of the fixed-point channel-DFT
+      // triple (F0, Re F1, Im F1) / 3 (the write-back of the image inverts
+      // the channel DFT) ----
       // lane (q, n): rows (s' = q/2, r = 4(q%2) + j), column t = n8; lanes with n < 8
       // finish block 2p, lanes with n >= 8 block 2p+1.
       const int hb = s;
@@ -416,35 +420,32 @@ __global__ __launch_bounds__(256, K >= 32 ? 1 : 2) void k_filter_mfma(Launch L) 
           const float p0 = X[NB + p][j];
           const float pr = hb ? recv : X[2 * p][j];
           const float pi = hb ? X[2 * p + 1][j] : recv;
-          const float o0 = (p0 + 2.f * pr) * s3;   // scaled by fxs (a power of two)
-          const float o1 = (p0 - pr - SQ3 * pi) * s3;
-          const float o2 = (p0 - pr + SQ3 * pi) * s3;
+          const float o0 = p0, o1 = pr, o2 = pi;
           nf = fmaf(o0, 0.f, nf);
           nf = fmaf(o1, 0.f, nf);
           nf = fmaf(o2, 0.f, nf);
           if (inside) {
             unsigned long long* a0 = acc + (ly0 + j) * CA + lx;
-            atomicAdd(a0, fx_from_float(o0));
-            atomicAdd(a0 + RA * CA, fx_from_float(o1));
-            atomicAdd(a0 + 2 * RA * CA, fx_from_float(o2));
+            atomicAdd(a0, fx_from<units>(o0));
+            atomicAdd(a0 + RA * CA, fx_from<units>(o1));
+            atomicAdd(a0 + 2 * RA * CA, fx_from<units>(o2));
           } else if constexpr (!BATCH || ADJ) {   // outside the tile's reach: straight to the image
             const int pix = (py + 4 * (q & 1) + j) * d.W + px + n8;
-            add_estimate_global(d, 0, pix, o0);
-            add_estimate_global(d, 1, pix, o1);
-            add_estimate_global(d, 2, pix, o2);
+            const float v3[3] = {o0, o1, o2};
+            add_pixel_global<units>(d, C, pix, v3, fxs);
           }
-          if (d.group_est) {
+          if (d.group_est) {   // image units: the channel DFT inverted
             float* ge = d.group_est + (((size_t)grel * K + k) * C) * PS2 + (4 * (q & 1) + j) * 8 + n8;
-            ge[0] = o0 * rfxs;
-            ge[PS2] = o1 * rfxs;
-            ge[2 * PS2] = o2 * rfxs;
+            ge[0] = fmaf(2.f, o1, o0) * rfxs;
+            ge[PS2] = fmaf(-SQ3, o2, o0 - o1) * rfxs;
+            ge[2 * PS2] = fmaf(SQ3, o2, o0 - o1) * rfxs;
           }
         }
       }
       if (__ballot(nf != 0.f)) poison_group(d, gidx, grel, K, C, rW, lane);
     }
     __syncthreads();
-    flush_tile(d, acc, C, RA, CA, AY0, AX0, AH, AW);
+    flush_tile(d, acc, C, RA, CA, AY0, AX0, AH, AW, units, fxs);
   });
 }
 

@@ -2,8 +2,8 @@
 // whose patches may lie anywhere in the image (the stacked frames of a
 // video, where a group takes patches from several frames and no window tile
 // covers them).  The filter writes every slot's estimate to its record
-// est[s][ch][8][8] (s = g K + k, already multiplied by the fixed-point
-// scale); then
+// est[s][ch][8][8] (s = g K + k, in the integer-unit encoding of the
+// numerator: scaled, and for c = 3 the channel-DFT triples); then
 //  1. the slots are bucketed by their patch corner: an exclusive scan of
 //     the corner histogram (hist, the same counts the coverage uses) gives
 //     each corner's first entry, and one pass writes every slot id into its
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(512) void k_gather_tiles(Launch L, const float* est
       for (int u = 0; u < GT_SLOTS; ++u)
         if (in[u])
 #pragma unroll
-          for (int ch = 0; ch < C; ++ch) atomicAdd(&acc[ch][ly[u]][lx[u]], fx_from_float(v[u][ch]));
+          for (int ch = 0; ch < C; ++ch) atomicAdd(&acc[ch][ly[u]][lx[u]], fx_from_units(v[u][ch]));
     }
   }
   __syncthreads();

@@ -280,7 +280,7 @@ __global__ __launch_bounds__(64) void k_filter_gen(Launch L) {
   const float* fb = d.fbasis;
   float* S = d.gscratch + (size_t)blockIdx.x * K * C * 64;
   const float tau = d.tau;
-  const float fxs = fx_scale(d) / (float)C;
+  const float fxs = fx_scale(d, false) / (float)C;   // 2^-32 units
   for (int m = threadIdx.x; m < C; m += blockDim.x) {
     double sn, cs;
     sincospi(2.0 * (double)m / (double)C, &sn, &cs);

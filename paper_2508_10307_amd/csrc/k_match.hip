@@ -435,14 +435,18 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
       // The values are non-negative floats (or +inf), ordered as their bit
       // patterns, which lie below 2^31.  T is the largest pattern t with
       // #{values < t} <= K-2, i.e. the (K-1)-th smallest value; it is built
-      // bit by bit from the top, counting with ballots.
+      // bit by bit from the top, counting with ballots.  Each step only sets
+      // lower bits, so the first 15 steps fix bits 30..16 of T for good; with
+      // the cached bounds pass 2 compares those 16 bits alone, and the
+      // search stops there.
+      constexpr int T_LOW_BIT = CACHE ? 16 : 0;
       for (int t = wv; t < 16; t += 4) {
         if (!(rinfo[t * 8] & pm)) continue;
         const unsigned v0 = __float_as_uint(tl[t * 128 + lane]);
         const unsigned v1 = __float_as_uint(tl[t * 128 + 64 + lane]);
         const int g = K - 2;
         unsigned pre = 0;
-        for (int bit = 30; bit >= 0; --bit) {
+        for (int bit = 30; bit >= T_LOW_BIT; --bit) {
           const unsigned cand = pre | (1u << bit);
           const int c = __popcll(__ballot(v0 < cand)) + __popcll(__ballot(v1 < cand));
           pre = c <= g ? cand : pre;

@@ -143,11 +143,18 @@ PROFILE_SOURCES = ["paper_2508_10307_amd/csrc/k_filter.hip",
                    "paper_2508_10307_amd/csrc/k_match.hip",
                    "paper_2508_10307_amd/csrc/hts_device.h",
                    "paper_2508_10307_amd/csrc/hts_internal.h"]
-PROFILED = {   # kernel name -> (sources sha256, figures)
+# kernel name -> (sha256 of PROFILE_SOURCES, {tune word: figures}): HBM bytes
+# per launch (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, rocprofv3) and
+# MfmaUtil of the batch64 step, reported only for the sources and schedule
+# they were taken on (profiles/ has the summaries and commands).
+PROFILED = {
     "void hts::k_filter<3, 4, 0, 0, 1, 0, 0>(hts::Launch)":
-        ("e4a4a6c5683249161f7b56c0b04d7a8845cd1d8c7e792527332e849caae66d7d", {"hbm_bytes": 9468426524}),
+        ("ed4c1481f56d5d896758f12106fd90d70f087e8241aabd17849c16d9b28329f0",
+         {98: {"hbm_bytes": 9719447016}, 99: {"hbm_bytes": 20354210653}}),
     "void hts::k_match<0, 3, 1, 2>(hts::Launch)":
-        ("e4a4a6c5683249161f7b56c0b04d7a8845cd1d8c7e792527332e849caae66d7d", {"hbm_bytes": 2367757104, "mfma_util_pct": 6.01}),
+        ("ed4c1481f56d5d896758f12106fd90d70f087e8241aabd17849c16d9b28329f0",
+         {98: {"hbm_bytes": 2064882162, "mfma_util_pct": 6.17},
+          99: {"hbm_bytes": 2065055631, "mfma_util_pct": 6.17}}),
 }
 
 
@@ -159,10 +166,10 @@ def sources_sha():
     return h.hexdigest()
 
 
-def profiled(kernel, key):
+def profiled(kernel, key, tune):
     e = PROFILED.get(kernel)
     if e and e[0] == sources_sha():
-        return e[1].get(key)
+        return e[1].get(tune, {}).get(key)
     return None
 
 
@@ -260,6 +267,27 @@ def parity_sample(wl, dev):
 
 
 # ---------------------------------------------------------------- main
+def shortlist_summary(h, K):
+    """Percentiles of the certified shortlist sizes (entries re-ranked per
+    reference) from the match's histogram; the last bin counts overflows."""
+    import numpy as np
+    sizes = np.arange(len(h) - 1)
+    inr = h[:-1]
+    tot = int(inr.sum())
+    cum = np.cumsum(inr)
+
+    def pct(f):
+        return int(sizes[np.searchsorted(cum, f * tot)]) if tot else None
+
+    nz = np.nonzero(inr)[0]
+    return {"references": int(h.sum()), "overflow": int(h[-1]),
+            "below_k_minus_1": int(inr[:K - 1].sum()),
+            "median": pct(0.5), "p90": pct(0.9), "p99": pct(0.99),
+            "max": int(nz[-1]) if len(nz) else None,
+            "mean": round(float((sizes * inr).sum() / tot), 2) if tot else None,
+            "k_minus_1": K - 1}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -342,6 +370,9 @@ def main():
     psnr_bf16 = psnr_all()
     out_bf16 = [o.clone() for o in outs]
     fb = api.hts_batch_fallback_counts(p16, xs, outs, sig, ws16).cpu().numpy()
+    # shortlist sizes of the certified match (untimed diagnostic run)
+    slh = api.hts_batch_shortlist_histogram(p16, xs, ws16).cpu().numpy().astype(np.int64)
+    del ws16
     mpix = wl.mpix
     value = mpix / (ms / 1e3)
 
@@ -395,7 +426,7 @@ def main():
     achieved = freorg / (f_ms / 1e3) / 1e12
     roof = {"kernel": fk, "bound": "alu", "achieved": round(achieved, 3),
             "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-            "traffic": profiled(fk, "hbm_bytes"),
+            "traffic": profiled(fk, "hbm_bytes", tune),
             "avg_launch_ms": round(f_ms, 4), "launches": args.stage_steps,
             "flops_per_launch": freorg,
             "flops_model": "reorg: Eq. 18 projection once per valid patch position + per-group "
@@ -414,8 +445,8 @@ def main():
                   "flops_model": "2 * 64 per (reference, candidate of its truncated window), "
                                  "dot form with exact norms",
                   "candidates": cands, "references": n_refs,
-                  "mfma_util_pct": profiled(mk, "mfma_util_pct"),
-                  "traffic": profiled(mk, "hbm_bytes"),
+                  "mfma_util_pct": profiled(mk, "mfma_util_pct", tune),
+                  "traffic": profiled(mk, "hbm_bytes", tune),
                   "target_frac": 0.5}
     if stage32:
         match_roof["fp32_ssd_ms"] = round(stage32["match"], 4)
@@ -625,6 +656,7 @@ def main():
                      "staged_outputs_equal_graph": same16},
         "fallback_references": {"total": int(fb.sum()), "of": n_refs,
                                 "images_with_any": int((fb > 0).sum())},
+        "shortlist_sizes": shortlist_summary(slh, q.K),
         "large_image": large,
         "differentiable": diff,
         "extensions": ext or None,

@@ -42,10 +42,15 @@
  *    stream).  A returned status covers argument validation and launch
  *    errors; on any error nothing is launched.  Device faults surface at the
  *    caller's next synchronisation.  No C++ exception crosses this ABI.
- *  - Aggregation (Eq. 2) sums the estimates in 64-bit fixed point with 32
- *    fractional bits (each estimate is rounded down to a multiple of 2^-32;
- *    estimates beyond +-2^31 saturate).  Integer sums do not depend on the
- *    order of the additions.
+ *  - Aggregation (Eq. 2) sums the estimates as 64-bit integers, scaled by a
+ *    power of two set from the image's largest input magnitude M.  The
+ *    forward filters of C = 1, 3 with uniform weights round every estimate
+ *    to a multiple of at most 2^-23 M (estimates are at most
+ *    sqrt(64 K C) M <= 79 M, which that encoding holds without saturation);
+ *    the weighted aggregation, the frozen adjoints and the other band counts
+ *    keep 32 fractional bits below 2^11..2^12 = M (multiples of 2^-43 M;
+ *    hts_filter's float num path: 32 fractional bits of the image values).
+ *    Integer sums do not depend on the order of the additions.
  *  - Reproducibility: match indices, distances, threshold masks and the
  *    outputs of hts_denoise, hts_denoise_batch and hts_denoise_backward are
  *    bit-for-bit the same from run to run, for any launch schedule of the
@@ -304,6 +309,20 @@ hts_status hts_match_fallback_count(const hts_params* p, int32_t C, int32_t H, i
 hts_status hts_batch_fallback_counts(const hts_params* p, const hts_image* imgs, int32_t n,
                                      const void* ws, size_t ws_bytes, int32_t* counts,
                                      void* stream);
+
+/* Diagnostics of the certified match (Alg. 1 Step 1): the sizes of the
+ * shortlists it re-ranks.  Runs the batched quantisation, Eq. 10 and the
+ * match of hts_denoise_batch on these images (imgs[i].out and sigma are not
+ * used; the workspace is that of hts_denoise_batch, whose idx it
+ * overwrites) and writes counts (device int32[HTS_SHORTLIST_BINS]):
+ * counts[s], s <= 128, = references whose shortlist held s candidates;
+ * counts[129] = references whose shortlist overflowed (they take the exact
+ * window scan).  Synchronises `stream` once (descriptor upload).
+ * Errors: as hts_denoise_batch, HTS_ERR_INVALID for null counts. */
+#define HTS_SHORTLIST_BINS 130
+hts_status hts_batch_shortlist_histogram(const hts_params* p, const hts_image* imgs, int32_t n,
+                                         void* ws, size_t ws_bytes, int32_t* counts,
+                                         void* stream);
 
 /* Workspace bytes for hts_denoise_batch over these n images (host array). */
 hts_status hts_batch_workspace_size(const hts_params* p, const hts_image* imgs, int32_t n,

@@ -19,6 +19,7 @@ HTS_MATCH_BF16 = 0
 HTS_MATCH_FP32 = 1
 HTS_FLAG_WEIGHTED = 1
 HTS_FLAG_FOURIER_THRESHOLD = 2
+HTS_SHORTLIST_BINS = 130
 
 c_i32 = ctypes.c_int32
 c_f32 = ctypes.c_float
@@ -65,6 +66,8 @@ SIGNATURES = {
                                           c_vp]),
     "hts_batch_workspace_size": (c_i32, [P, ctypes.POINTER(HtsImage), c_i32,
                                          ctypes.POINTER(c_sz)]),
+    "hts_batch_shortlist_histogram": (c_i32, [P, ctypes.POINTER(HtsImage), c_i32, c_vp, c_sz,
+                                              c_vp, c_vp]),
     "hts_denoise_batch": (c_i32, [P, ctypes.POINTER(HtsImage), c_i32, c_vp, c_sz, c_vp]),
     "hts_denoise_batch_save": (c_i32, [P, ctypes.POINTER(HtsImage), ctypes.POINTER(HtsState),
                                        c_i32, c_vp, c_sz, c_vp]),

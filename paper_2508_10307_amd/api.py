@@ -243,6 +243,23 @@ def hts_batch_fallback_counts(p: Params, noisy, outs, sigmas, ws: torch.Tensor) 
     return out
 
 
+def hts_batch_shortlist_histogram(p: Params, noisy, ws: Optional[torch.Tensor] = None):
+    """Shortlist sizes of the certified match over a batch: a device int32
+    tensor [HTS_SHORTLIST_BINS]; entry s <= 128 counts the references whose
+    shortlist held s candidates, the last entry the overflows."""
+    xs = [_img(x) for x in noisy]
+    dev = xs[0].device
+    sig = [0.0] * len(xs)
+    if ws is None:
+        ws = torch.empty(batch_workspace_size(p, xs, xs, sig), dtype=torch.uint8, device=dev)
+    arr = _images(xs, xs, sig)
+    out = torch.empty(L.HTS_SHORTLIST_BINS, dtype=torch.int32, device=dev)
+    pc = p.c()
+    L.check("hts_batch_shortlist_histogram", L.load().hts_batch_shortlist_histogram(
+        ctypes.byref(pc), arr, len(xs), _ptr(ws), ws.numel(), _ptr(out), _stream(dev)))
+    return out
+
+
 def _images(noisy: Sequence[torch.Tensor], outs: Sequence[torch.Tensor], sigmas):
     arr = (L.HtsImage * len(noisy))()
     for i, (x, o, s) in enumerate(zip(noisy, outs, sigmas)):

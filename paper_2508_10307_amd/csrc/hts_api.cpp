@@ -911,6 +911,42 @@ hts_status hts_batch_fallback_counts(const hts_params* p, const hts_image* imgs,
   return HTS_OK;
 }
 
+hts_status hts_batch_shortlist_histogram(const hts_params* p, const hts_image* imgs, int32_t n,
+                                         void* ws, size_t ws_bytes, int32_t* counts,
+                                         void* stream) {
+  static_assert(HTS_SHORTLIST_BINS == SL_BINS, "shortlist bins");
+  if (!ws || !counts || !imgs || n < 1) return HTS_ERR_INVALID;
+  for (int i = 0; i < n; ++i)
+    if (!imgs[i].noisy) return HTS_ERR_INVALID;
+  std::vector<hts_image> im(imgs, imgs + n);   // out and sigma play no part
+  for (auto& m : im) {
+    m.out = nullptr;
+    m.sigma = 0.f;
+  }
+  BatchPlan plan;
+  hts_status st = plan_batch(p, im.data(), n, (char*)ws, false, plan);
+  if (st != HTS_OK) return st;
+  if (ws_bytes < plan.bytes) return HTS_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  const int C = imgs[0].C;
+  ImgDesc* table = (ImgDesc*)((char*)ws + plan.table_off);
+  HIPCHK(hipMemcpyAsync(table, plan.descs.data(), plan.descs.size() * sizeof(ImgDesc),
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));   // the upload reads pageable host memory
+  const int cus = device_cus();
+  auto LK = [&](int kind) {
+    return batch_launch(p, C, table, n, kind >= 0 ? plan.totals[kind] : 0, plan.sc);
+  };
+  HIPCHK(launch_fill((float*)counts, SL_BINS, 0.f, s));   // zero bits
+  HIPCHK(launch_reset_counters(LK(-1), s));
+  HIPCHK(launch_quant(LK(W_PIX), cus * 8, s));
+  HIPCHK(launch_gcp(LK(W_REF), cus * 8, s));
+  Launch Lm = LK(W_MATCH);
+  Lm.sl_hist = counts;
+  HIPCHK(launch_match(Lm, p->match_mode, plan.sc.terms, cus * 2, s));
+  return HTS_OK;
+}
+
 hts_status hts_batch_workspace_size(const hts_params* p, const hts_image* imgs, int32_t n,
                                     size_t* bytes) {
   if (!bytes) return HTS_ERR_INVALID;
@@ -1155,16 +1191,30 @@ hts_status hts_autotune(const hts_params* p, int32_t C, int32_t H, int32_t W,
   ImgDesc d = make_desc(g, &q, base, c, img, 25.f, base_sc.fty, base_sc.ftx);
   d.idx = idx;
   d.out = out;
+  // Candidates are timed in a fixed order, and the first one within
+  // kTieMargin of the fastest wins: measurements a few per cent apart are
+  // noise, and the order puts the preferred variant first (the hi/lo split,
+  // whose tighter bounds give shorter shortlists; larger filter tiles, which
+  // flush fewer tile borders and gather with more reuse).
+  constexpr float kTieMargin = 1.02f;
+  auto pick = [&](const std::vector<float>& t) {
+    float best = 1e30f;
+    for (float v : t) best = std::min(best, v);
+    for (size_t i = 0; i < t.size(); ++i)
+      if (t[i] <= best * kTieMargin) return (int)i;
+    return 0;
+  };
   // distance-tile variant (BF16 only: one product or hi/lo split)
   int best_terms = 3;
   if (p->match_mode == HTS_MATCH_BF16) {
-    float tb = 1e30f;
-    for (int terms : {3, 1}) {
+    const int cand[2] = {3, 1};
+    std::vector<float> times;
+    for (int terms : cand) {
       Schedule sc = base_sc;
       sc.terms = terms;
-      const float t = time_it([&] { return run_match(&q, C, sc, d, s); });
-      if (t < tb) { tb = t; best_terms = terms; }
+      times.push_back(time_it([&] { return run_match(&q, C, sc, d, s); }));
     }
+    best_terms = cand[pick(times)];
   }
   {
     Schedule sc = base_sc;
@@ -1174,8 +1224,8 @@ hts_status hts_autotune(const hts_params* p, int32_t C, int32_t H, int32_t W,
     if (st != HTS_OK) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return st; }
   }
   // filter implementation and tile shape
-  int best_shape = 0, best_valu = 0;
-  float tf = 1e30f;
+  std::vector<float> ftimes;
+  std::vector<std::pair<int, int>> fcand;   // (valu, shape)
   for (int valu = filter_mfma_supported(C, p->K) && !weighted(p) && !fourier(p, C) ? 0 : 1;
        valu <= 1; ++valu) {
     for (int i = 0; i < kNumShapes; ++i) {
@@ -1186,13 +1236,15 @@ hts_status hts_autotune(const hts_params* p, int32_t C, int32_t H, int32_t W,
       sc.ftx = kShapes[i].tx;
       ImgDesc di = d;
       fill_counts(g, &q, sc.fty, sc.ftx, di);
-      const float t = time_it([&] {
+      ftimes.push_back(time_it([&] {
         if (launch_zero_accum(make_launch(&q, C, di, W_PIX, sc.fty, sc.ftx), 0, s) != hipSuccess) return HTS_ERR_HIP;
         return run_filter(&q, C, sc, di, 0, s);
-      });
-      if (t < tf) { tf = t; best_shape = i; best_valu = valu; }
+      }));
+      fcand.push_back({valu, i});
     }
   }
+  const int fi = fcand.empty() ? -1 : pick(ftimes);
+  const int best_valu = fi < 0 ? 1 : fcand[fi].first, best_shape = fi < 0 ? 0 : fcand[fi].second;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   const int word = (best_shape + 1) | ((best_terms == 1 ? 1 : 2) << 4) | (best_valu << 6);

@@ -16,6 +16,7 @@ constexpr int MAX_WINDOW = 63;         // window-relative candidate index fits 1
 constexpr int MATCH_TY = 4;            // match tile: 4 x 4 references
 constexpr int MATCH_TX = 4;
 constexpr int SHORT_CAP = 128;         // certified shortlist capacity per reference
+constexpr int SL_BINS = SHORT_CAP + 2;  // shortlist sizes 0..SHORT_CAP, then overflows
 constexpr int PIX_CHUNK = 2048;        // pixels per work item of the element-wise stages
 // General band counts (c other than 1 and 3: the spectral tubes of HSI)
 constexpr int GEN_CMAX = 256;          // bands
@@ -123,6 +124,8 @@ struct Launch {
   int32_t gcp_num, gcp_den;
   int32_t flags;
   int32_t fty, ftx;        // filter tile shape (references)
+  int32_t* sl_hist;        // diagnostics: shortlist-size histogram [SL_BINS] of the
+                           // match (nullable; then no extra LDS)
   int32_t count_hist;      // 1: k_quant clears hist and the match adds every group's
                            // slot corners to it (the coverage histogram)
   int32_t batch_masks;     // batched filter launch: export the keep-masks (d.masks)

@@ -93,6 +93,11 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
   const int r = (L.window - 1) / 2;
   const int s = L.stride;
   const int K = L.K;
+  // diagnostics: shortlist sizes, counted per work group past the regular
+  // LDS (allocated only when asked for), added to L.sl_hist at the end
+  int* shist = (int*)(smem + G.bytes);
+  if (L.sl_hist)
+    for (int i = tid; i < SL_BINS; i += 256) shist[i] = 0;
 
   for_each_item_cd<W_MATCH>(L, [&](const auto& d, int item) __attribute__((always_inline)) {
     const int ntx = (d.nrx + MATCH_TX - 1) / MATCH_TX;
@@ -519,6 +524,7 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
         const int ref = ri[7];
         const int* gi = GI(slot((ri[0] >> 1) & 1));   // the reference's guide plane
         const int nsl = __builtin_amdgcn_readfirstlane(scount[t]);
+        if (L.sl_hist && lane == 0) atomicAdd(&shist[min(nsl, SHORT_CAP + 1)], 1);
         if (nsl > SHORT_CAP || nsl < K - 1) {
           if (lane == 0) d.fb_list[atomicAdd(d.fb_count, 1)] = ref;
           continue;
@@ -599,6 +605,11 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
       }
     }
   });
+  if (L.sl_hist) {
+    __syncthreads();
+    for (int i = tid; i < SL_BINS; i += 256)
+      if (shist[i]) atomicAdd(L.sl_hist + i, shist[i]);
+  }
 }
 
 // Exact scan of the whole window for references whose certified shortlist
@@ -710,7 +721,7 @@ hipError_t launch_match(const Launch& L, int mode, int terms, int grid, hipStrea
   const int g = xcd_grid(grid > 0 && grid < L.total ? grid : L.total);
   const int npl = match_planes(L.C, L.stride, L.window);
   const MatchGeom G = match_geom(L.stride, L.window, npl);
-  const size_t lds = (size_t)G.bytes;
+  const size_t lds = (size_t)G.bytes + (L.sl_hist ? SL_BINS * sizeof(int) : 0);
   const bool cache = ((G.ryc + 1) / 2 * (G.rxp / 8) + 3) / 4 <= MAXBW;
 #define HTS_KM(M, T)                                                                          \
   if (npl == 2) {                                                                             \

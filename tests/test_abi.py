@@ -167,6 +167,12 @@ def test_calls_reject_null_pointers_and_small_workspace(lib):
             assert fn(ctypes.byref(pf), imgs, states, 1, FAKE, 1 << 40,
                       None) == L.HTS_ERR_UNSUPPORTED
         assert fn(bp, imgs, states, 1, FAKE, 16, None) == L.HTS_ERR_WORKSPACE
+    # shortlist histogram: null counts or image, small workspace
+    sh = lib.hts_batch_shortlist_histogram
+    assert sh(bp, imgs, 1, FAKE, 1 << 40, None, None) == L.HTS_ERR_INVALID
+    noimg = (L.HtsImage * 1)(L.HtsImage(None, None, 3, 64, 64, 10.0))
+    assert sh(bp, noimg, 1, FAKE, 1 << 40, FAKE, None) == L.HTS_ERR_INVALID
+    assert sh(bp, imgs, 1, FAKE, 16, FAKE, None) == L.HTS_ERR_WORKSPACE
 
 
 def test_workspace_grows_with_image():

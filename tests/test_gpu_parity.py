@@ -156,6 +156,31 @@ def test_batch_with_overflowing_shortlists_equals_per_image():
     assert cb[0] > 0 and cb[2] > 0 and cb[3] > 0
 
 
+@pytest.mark.parametrize("mode", [0, 1], ids=["bf16", "fp32"])
+def test_shortlist_histogram_accounts_for_every_reference(mode):
+    """hts_batch_shortlist_histogram: every reference lands in one bin, and
+    the references routed to the exact window scan (overflowing shortlists,
+    or fewer than K-1 entries) are exactly the batch's fallback counts."""
+    p = P(stride=3, window=31, K=32, match_mode=mode)
+    imgs = [np.full((3, 48, 56), 120.0, np.float32), synth.tiny(33, 3, 64, 60, sigma=15.0),
+            _two_level(3, 40, 72), synth.tiny(34, 3, 50, 50, sigma=30.0)]
+    sig = [10.0, 15.0, 12.0, 30.0]
+    xs = [T(y) for y in imgs]
+    outs = [torch.empty_like(x) for x in xs]
+    wsb = torch.empty(api.batch_workspace_size(p, xs, outs, sig), dtype=torch.uint8,
+                      device=dev())
+    api.hts_denoise_batch(xs, sig, p, outs=outs, ws=wsb)
+    nfb = int(api.hts_batch_fallback_counts(p, xs, outs, sig, wsb).sum().item())
+    h = api.hts_batch_shortlist_histogram(p, xs).cpu().numpy()
+    n_ref = sum(int(np.prod(api.ref_grid(x.shape[1], x.shape[2], p))) for x in xs)
+    log("shortlist histogram", mode, "overflow", int(h[-1]), "fallback", nfb,
+        "nonzero bins", np.nonzero(h)[0].tolist()[:12])
+    assert h.shape == (130,) and (h >= 0).all()
+    assert int(h.sum()) == n_ref
+    assert int(h[-1]) + int(h[:p.K - 1].sum()) == nfb
+    assert int(h[p.K - 1:129].sum()) > 0
+
+
 def test_match_mixed_guide_planes_repeatable():
     # RGB tiles whose references mix the green and the R+G+B guide are
     # matched plane by plane; the references of the other plane must not

@@ -115,7 +115,7 @@ def match_kernel_name(C, s, w, mode, terms):
     """The instantiation launch_match picks (LDS geometry of a 4x4 reference
     tile: two guide-plane slots when they fit beside a second work group;
     lower bounds cached in registers for up to 36 blocks per wavefront)."""
-    def geom(npl):
+    def geom(npl, sbs):
         r = (w - 1) // 2
         ryc, rxc = 3 * s + 2 * r + 1, 3 * s + 2 * r + 1
         rxp = (rxc + 7) // 8 * 8
@@ -123,13 +123,17 @@ def match_kernel_name(C, s, w, mode, terms):
         pitch = rxp + 7
         pitch += ((8 - pitch) % 16 + 16) % 16
         rgn = (ry2 + 7) * pitch * 4
-        plane = 2 * rgn + 2 * ry2 * rxp * 4
+        plane = 2 * rgn + (2 if sbs else 1) * ry2 * rxp * 4
         return npl * plane + max(16 * 64 * 2 * 4, 16 * 128 * 4) + 768, ryc, rxp
-    npl = 2 if C == 3 and geom(2)[0] <= 80 * 1024 else 1
-    _, ryc, rxp = geom(npl)
+    npl, sbs = 1, 1
+    if C == 3 and geom(2, 1)[0] <= 80 * 1024:
+        npl = 2
+    elif C == 3 and geom(2, 0)[0] <= 80 * 1024:
+        npl, sbs = 2, 0
+    _, ryc, rxp = geom(npl, sbs)
     cache = 1 if ((ryc + 1) // 2 * (rxp // 8) + 3) // 4 <= 36 else 0
     m, t = (1, 1) if mode == 1 else (0, terms)
-    return f"void hts::k_match<{m}, {t}, {cache}, {npl}>(hts::Launch)"
+    return f"void hts::k_match<{m}, {t}, {cache}, {npl}, {sbs}>(hts::Launch)"
 
 
 # ---------------------------------------------------------------- counters
@@ -151,7 +155,7 @@ PROFILED = {
     "void hts::k_filter<3, 4, 0, 0, 1, 0, 0>(hts::Launch)":
         ("ed4c1481f56d5d896758f12106fd90d70f087e8241aabd17849c16d9b28329f0",
          {98: {"hbm_bytes": 9719447016}, 99: {"hbm_bytes": 20354210653}}),
-    "void hts::k_match<0, 3, 1, 2>(hts::Launch)":
+    "void hts::k_match<0, 3, 1, 2, 1>(hts::Launch)":
         ("ed4c1481f56d5d896758f12106fd90d70f087e8241aabd17849c16d9b28329f0",
          {98: {"hbm_bytes": 2064882162, "mfma_util_pct": 6.17},
           99: {"hbm_bytes": 2065055631, "mfma_util_pct": 6.17}}),

@@ -141,10 +141,11 @@ struct MatchGeom {
   int rgn, nbsz, plane_bytes;  // bytes of one staged region, of one norm array, of one plane slot
   int off_tl, off_misc, bytes;
 };
-// LDS of the match: npl plane slots of [gi][gb][|b|^2][|b|], then the
-// list values of pass 1, which the shortlist of pass 2 reuses (the lists
-// are dead once T is known), then per-reference data.
-__host__ __device__ inline MatchGeom match_geom(int s, int w, int npl) {
+// LDS of the match: npl plane slots of [gi][gb][|b|^2][|b|] (sbs = 0: no
+// |b| array, its square root is taken where it is used), then the list
+// values of pass 1, which the shortlist of pass 2 reuses (the lists are dead
+// once T is known), then per-reference data.
+__host__ __device__ inline MatchGeom match_geom(int s, int w, int npl, int sbs = 1) {
   MatchGeom g;
   int r = (w - 1) / 2;
   g.ryc = (MATCH_TY - 1) * s + 2 * r + 1;
@@ -158,7 +159,7 @@ __host__ __device__ inline MatchGeom match_geom(int s, int w, int npl) {
   g.rows = ry2 + PS - 1;
   g.rgn = g.rows * g.pitch * 4;
   g.nbsz = ry2 * g.rxp * 4;
-  g.plane_bytes = 2 * g.rgn + 2 * g.nbsz;
+  g.plane_bytes = 2 * g.rgn + (sbs ? 2 : 1) * g.nbsz;
   g.off_tl = npl * g.plane_bytes;
   const int lists = 16 * 64 * 2 * 4, shortlist = 16 * SHORT_CAP * 4;
   g.off_misc = g.off_tl + (lists > shortlist ? lists : shortlist);

@@ -65,11 +65,13 @@ constexpr int MAXBW = 36;
 // references use both planes runs the distance passes once (every reference
 // against its own plane: the A operand of a reference is zero in the
 // products of the other plane); NPL = 1 runs the planes one after the other
-// (windows too large for two plane slots in LDS).
-template <int MODE, int TERMS, int CACHE, int NPL>
+// (windows too large for two plane slots in LDS).  SBS = 0 keeps no |b|
+// array and takes the square root of |b|^2 where the bound needs it: the
+// smaller footprint that lets two plane slots fit for larger windows.
+template <int MODE, int TERMS, int CACHE, int NPL, int SBS>
 __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const MatchGeom G = match_geom(L.stride, L.window, NPL);
+  const MatchGeom G = match_geom(L.stride, L.window, NPL, SBS);
   // plane slot q: staged guide (int), its bf16 split or float form, |b|^2, |b|
   auto GI = [&](int q) __attribute__((always_inline)) { return (int*)(smem + q * G.plane_bytes); };
   auto GB = [&](int q) __attribute__((always_inline)) {
@@ -227,7 +229,7 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
               if (cy < RYc) {
                 const float f = (float)nn;
                 nbf[cy * RXP + cx] = f;
-                sbf[cy * RXP + cx] = sqrtf(f);
+                if (SBS) sbf[cy * RXP + cx] = sqrtf(f);
               }
               if (j < 7) nn += rs[j + 8] - rs[j];
             }
@@ -328,7 +330,7 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
               }
             }
             nbq[sq] = NB(sq)[cy * RXP + cx];
-            sbq[sq] = SB(sq)[cy * RXP + cx];
+            sbq[sq] = SBS ? SB(sq)[cy * RXP + cx] : sqrtf(nbq[sq]);
           }
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
@@ -711,25 +713,37 @@ __global__ __launch_bounds__(256) void k_match_fallback(Launch L) {
 size_t match_lds_bytes(int stride, int window) { return (size_t)match_geom(stride, window, 1).bytes; }
 
 // Two plane slots when the image has two guide planes and they fit beside
-// a second work group on the CU (160 KB of LDS).
-static int match_planes(int C, int stride, int window) {
-  return C == 3 && match_geom(stride, window, 2).bytes <= 80 * 1024 ? 2 : 1;
+// a second work group on the CU (160 KB of LDS), with the |b| arrays when
+// those fit too; else one plane slot.  *sbs: keep the |b| arrays.
+static int match_planes(int C, int stride, int window, int* sbs) {
+  *sbs = 1;
+  if (C != 3) return 1;
+  if (match_geom(stride, window, 2, 1).bytes <= 80 * 1024) return 2;
+  if (match_geom(stride, window, 2, 0).bytes <= 80 * 1024) {
+    *sbs = 0;
+    return 2;
+  }
+  return 1;
 }
 
 hipError_t launch_match(const Launch& L, int mode, int terms, int grid, hipStream_t s) {
   if (L.total <= 0) return hipSuccess;
   const int g = xcd_grid(grid > 0 && grid < L.total ? grid : L.total);
-  const int npl = match_planes(L.C, L.stride, L.window);
-  const MatchGeom G = match_geom(L.stride, L.window, npl);
+  int sbs = 1;
+  const int npl = match_planes(L.C, L.stride, L.window, &sbs);
+  const MatchGeom G = match_geom(L.stride, L.window, npl, sbs);
   const size_t lds = (size_t)G.bytes + (L.sl_hist ? SL_BINS * sizeof(int) : 0);
   const bool cache = ((G.ryc + 1) / 2 * (G.rxp / 8) + 3) / 4 <= MAXBW;
 #define HTS_KM(M, T)                                                                          \
-  if (npl == 2) {                                                                             \
-    if (cache) hipLaunchKernelGGL((k_match<M, T, 1, 2>), dim3(g), dim3(256), lds, s, L);      \
-    else hipLaunchKernelGGL((k_match<M, T, 0, 2>), dim3(g), dim3(256), lds, s, L);            \
+  if (npl == 2 && !sbs) {                                                                     \
+    if (cache) hipLaunchKernelGGL((k_match<M, T, 1, 2, 0>), dim3(g), dim3(256), lds, s, L);   \
+    else hipLaunchKernelGGL((k_match<M, T, 0, 2, 0>), dim3(g), dim3(256), lds, s, L);         \
+  } else if (npl == 2) {                                                                      \
+    if (cache) hipLaunchKernelGGL((k_match<M, T, 1, 2, 1>), dim3(g), dim3(256), lds, s, L);   \
+    else hipLaunchKernelGGL((k_match<M, T, 0, 2, 1>), dim3(g), dim3(256), lds, s, L);         \
   } else {                                                                                    \
-    if (cache) hipLaunchKernelGGL((k_match<M, T, 1, 1>), dim3(g), dim3(256), lds, s, L);      \
-    else hipLaunchKernelGGL((k_match<M, T, 0, 1>), dim3(g), dim3(256), lds, s, L);            \
+    if (cache) hipLaunchKernelGGL((k_match<M, T, 1, 1, 1>), dim3(g), dim3(256), lds, s, L);   \
+    else hipLaunchKernelGGL((k_match<M, T, 0, 1, 1>), dim3(g), dim3(256), lds, s, L);         \
   }
   if (mode == HTS_MATCH_FP32) {
     HTS_KM(1, 1)

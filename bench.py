@@ -153,12 +153,12 @@ PROFILE_SOURCES = ["paper_2508_10307_amd/csrc/k_filter.hip",
 # they were taken on (profiles/ has the summaries and commands).
 PROFILED = {
     "void hts::k_filter<3, 4, 0, 0, 1, 0, 0>(hts::Launch)":
-        ("ed4c1481f56d5d896758f12106fd90d70f087e8241aabd17849c16d9b28329f0",
-         {98: {"hbm_bytes": 9719447016}, 99: {"hbm_bytes": 20354210653}}),
+        ("b9a99083910e8be935a022eee1e7019d79d6d99437b4c8bb56b976afe448e7da",
+         {98: {"hbm_bytes": 9722924411}, 99: {"hbm_bytes": 20356628487}}),
     "void hts::k_match<0, 3, 1, 2, 1>(hts::Launch)":
-        ("ed4c1481f56d5d896758f12106fd90d70f087e8241aabd17849c16d9b28329f0",
-         {98: {"hbm_bytes": 2064882162, "mfma_util_pct": 6.17},
-          99: {"hbm_bytes": 2065055631, "mfma_util_pct": 6.17}}),
+        ("b9a99083910e8be935a022eee1e7019d79d6d99437b4c8bb56b976afe448e7da",
+         {98: {"hbm_bytes": 2064443789, "mfma_util_pct": 6.17},
+          99: {"hbm_bytes": 2064345933, "mfma_util_pct": 6.19}}),
 }
 
 

@@ -44,13 +44,14 @@
  *    caller's next synchronisation.  No C++ exception crosses this ABI.
  *  - Aggregation (Eq. 2) sums the estimates as 64-bit integers, scaled by a
  *    power of two set from the image's largest input magnitude M.  The
- *    forward filters of C = 1, 3 with uniform weights round every estimate
- *    to a multiple of at most 2^-23 M (estimates are at most
- *    sqrt(64 K C) M <= 79 M, which that encoding holds without saturation);
- *    the weighted aggregation, the frozen adjoints and the other band counts
- *    keep 32 fractional bits below 2^11..2^12 = M (multiples of 2^-43 M;
- *    hts_filter's float num path: 32 fractional bits of the image values).
- *    Integer sums do not depend on the order of the additions.
+ *    forward filters of C = 1, 3 with uniform weights (hts_denoise, the
+ *    batches, hts_filter, the video) round every estimate to a multiple of
+ *    at most 2^-23 M (estimates are at most sqrt(64 K C) M <= 79 M, which
+ *    that encoding holds without saturation); the weighted aggregation, the
+ *    frozen adjoints and the other band counts keep 32 fractional bits
+ *    below 2^11..2^12 = M (multiples of 2^-43 M; into hts_filter's float
+ *    num: 32 fractional bits of the image values).  Integer sums do not
+ *    depend on the order of the additions.
  *  - Reproducibility: match indices, distances, threshold masks and the
  *    outputs of hts_denoise, hts_denoise_batch and hts_denoise_backward are
  *    bit-for-bit the same from run to run, for any launch schedule of the

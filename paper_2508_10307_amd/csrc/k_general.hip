@@ -313,6 +313,7 @@ __global__ __launch_bounds__(64) void k_filter_gen(Launch L) {
         xr[u] = x0 + (((f0 + u) & 1) ? -xh : xh);
         m[u] = 0;
       }
+#pragma unroll 4
       for (int j = 1; j <= JH; ++j) {
         const float sj = Yb[j * 64 + lane], dj = Yb[(C - j) * 64 + lane];
 #pragma unroll
@@ -347,6 +348,7 @@ __global__ __launch_bounds__(64) void k_filter_gen(Launch L) {
     for (int j0 = 1; j0 <= JH; j0 += 4) {
       float A[4] = {0.f, 0.f, 0.f, 0.f}, B[4] = {0.f, 0.f, 0.f, 0.f};
       int m[4] = {0, 0, 0, 0};
+#pragma unroll 4
       for (int f = 1; f < NF; ++f) {
         const float w = 2 * f == C ? 1.f : 2.f;
         const float2 z = X[f * 64 + lane];

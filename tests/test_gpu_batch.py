@@ -349,3 +349,24 @@ def test_autograd_batch_equals_per_image_autograd():
         api.HaarTSVDBatch.apply(xb.detach()[0], sig, 2.7, p)
     with pytest.raises(ValueError):
         api.HaarTSVDBatch.apply(xb.detach(), sig[:3], 2.7, p)
+
+
+@pytest.mark.parametrize("K", [4, 16])
+def test_batch_save_and_backward_gray(K):
+    """Grey images (c = 1; K = 4 leaves slot lanes idle): the batched state
+    export and the batched adjoint give the per-image bits."""
+    p = api.Params(stride=2, window=11, K=K)
+    shapes = [(1, 40, 52), (1, 33, 30), (1, 64, 48)]
+    xs = [T(synth.tiny(800 + i, *sh, sigma=18.0)) for i, sh in enumerate(shapes)]
+    sig = [18.0, 12.0, 25.0]
+    outs, states = api.hts_denoise_batch_save(xs, sig, p)
+    rng = np.random.default_rng(K)
+    gs = [T(rng.normal(size=x.shape)) for x in xs]
+    gins = api.hts_denoise_batch_backward(gs, states, p)
+    torch.cuda.synchronize()
+    for i, (x, s) in enumerate(zip(xs, sig)):
+        o, st = api.hts_denoise(x, s, p, save=True)
+        assert torch.equal(outs[i], o)
+        _state_equal(states[i], st)
+        ref, _ = api.hts_denoise_backward(gs[i], st, p)
+        assert torch.equal(gins[i], ref)

@@ -163,7 +163,9 @@ __host__ __device__ inline MatchGeom match_geom(int s, int w, int npl, int sbs =
   g.off_tl = npl * g.plane_bytes;
   const int lists = 16 * 64 * 2 * 4, shortlist = 16 * SHORT_CAP * 4;
   g.off_misc = g.off_tl + (lists > shortlist ? lists : shortlist);
-  g.bytes = g.off_misc + 768;    // rinfo [16][8], rnorm [16][2], Tp [16], scount [16]
+  // rinfo [16][8], rnorm [16][2], Tp [16], scount [16], then the re-rank
+  // keys [4][64] (8 bytes each)
+  g.bytes = g.off_misc + 768 + 4 * 64 * 8;
   return g;
 }
 

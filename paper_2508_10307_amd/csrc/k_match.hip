@@ -57,6 +57,25 @@ __device__ inline unsigned split_pack(float v) {
   return bf16_bits(h) | (bf16_bits(l) << 16);
 }
 
+// The value of lane l ^ 32 (v_permlane32_swap exchanges the upper half of
+// its first operand with the lower half of its second); hi: lane >= 32.
+__device__ inline unsigned xor32_u32(unsigned v, bool hi) {
+  const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  return hi ? r[0] : r[1];
+}
+// Orders one wavefront's LDS writes before its later reads of other lanes'
+// slots (the hardware keeps a wavefront's LDS accesses in order; this keeps
+// the compiler from moving them).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+__device__ inline unsigned long long xor32_u64(unsigned long long v, bool hi) {
+  const unsigned lo = xor32_u32((unsigned)v, hi), up = xor32_u32((unsigned)(v >> 32), hi);
+  return ((unsigned long long)up << 32) | lo;
+}
+
 // Blocks per wavefront whose lower bounds stay in registers between the
 // two passes (CACHE = 1): 36 covers windows up to 39 at stride 2 or 3.
 constexpr int MAXBW = 36;
@@ -89,6 +108,7 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
   float* rnorm = (float*)(rinfo + 128);            // [16][2] |a|^2, |a|
   float* Tp = rnorm + 32;                          // [16]
   int* scount = (int*)(Tp + 16);                   // [16]
+  unsigned long long* keyb = (unsigned long long*)(smem + G.off_misc + 768);   // [4][64]
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int kq = lane >> 4, n = lane & 15;
@@ -168,70 +188,116 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
         for (int q = 0; q < 2; ++q)
           moff[q] = (part[4 * q] + part[4 * q + 1] + part[4 * q + 2] + part[4 * q + 3]) >> 8;
       }
+      // Each wavefront loads SROWS rows of both planes before it waits for
+      // any of them (addresses clamped into the image, values masked after).
+      constexpr int SROWS = 4;
+      for (int x0 = 0; x0 < cols; x0 += 64) {
+        const int x = x0 + lane;
+        const int xc = min(X0 + x, d.W - 1);
+        const bool in_img = X0 + x < d.W;
+        for (int y0 = wave; y0 < rows; y0 += 4 * SROWS) {
+          // (a plane this pass does not use reads plane 0 in its place: no
+          // branch between the loads)
+          int v[2][SROWS];
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        if (!((pm >> q) & 1)) continue;
-        const int* gsrc = d.gplanes + (size_t)q * d.H * d.W;
-        int* gi = GI(slot(q));
-        unsigned* gb = GB(slot(q));
-        for (int y = wave; y < rows; y += 4) {
-          const int* srow = gsrc + (Y0 + y) * d.W + X0;
-          for (int x = lane; x < cols; x += 64) {
-            const int v = X0 + x < d.W ? srow[x] - moff[q] : 0;
-            gi[y * pitch + x] = v;
-            gb[y * pitch + x] = MODE == 0 ? split_pack((float)v) : __float_as_uint((float)v);
+          for (int q = 0; q < 2; ++q) {
+            const int* src = d.gplanes + (size_t)((pm >> q) & 1 ? q : 0) * d.H * d.W + xc;
+#pragma unroll
+            for (int u = 0; u < SROWS; ++u)
+              v[q][u] = src[(size_t)(Y0 + min(y0 + 4 * u, rows - 1)) * d.W];
+          }
+          if (x >= cols) continue;
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            if (!((pm >> q) & 1)) continue;
+            int* gi = GI(slot(q));
+            unsigned* gb = GB(slot(q));
+#pragma unroll
+            for (int u = 0; u < SROWS; ++u) {
+              const int y = y0 + 4 * u;
+              if (y < rows) {
+                const int c = in_img ? v[q][u] - moff[q] : 0;
+                gi[y * pitch + x] = c;
+                gb[y * pitch + x] = MODE == 0 ? split_pack((float)c) : __float_as_uint((float)c);
+              }
+            }
           }
         }
-        // the row below the region, read by the last block row when RYc is
-        // odd (then it lies inside the allocation, which has rows for an
-        // even number of candidate rows)
-        if (RYc & 1)
+      }
+      // the row below the region, read by the last block row when RYc is
+      // odd (then it lies inside the allocation, which has rows for an even
+      // number of candidate rows)
+      if (RYc & 1) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          if (!((pm >> q) & 1)) continue;
           for (int x = tid; x < cols; x += 256) {
-            gi[rows * pitch + x] = 0;
-            gb[rows * pitch + x] = 0u;
+            GI(slot(q))[rows * pitch + x] = 0;
+            GB(slot(q))[rows * pitch + x] = 0u;
           }
+        }
       }
       __syncthreads();
 
       // ---- exact candidate norms |b|^2 (norm+dot form only) ----
-      // One task per (column, 8 rows): row sums of v^2 over 8 columns, then
-      // a sliding sum down the rows, in FP64 (exact: |v| < 2^22, sums < 2^50).
+      // One task per (plane, column pair, 8 rows): per row the squares of
+      // the 9 values under the pair's two windows, their two sums of 8 (the
+      // second by sliding the first), then sliding sums down the rows; all
+      // in FP64 (exact: |v| < 2^22, sums < 2^50, so the order of additions
+      // does not matter).  Rows past the region repeat its last row: their
+      // sums only reach the norms of candidate rows >= RYc, which are not
+      // stored.
       if (MODE == 0) {
         const int nseg = (RYc + 7) >> 3;
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          if (!((pm >> q) & 1)) continue;
+        const int ncp = RXP >> 1;
+        const int per_plane = ncp * nseg;
+        const int q0 = (pm & 1) ? 0 : 1;
+        const int ntask = per_plane * __builtin_popcount(pm);
+        for (int task = tid; task < ntask; task += 256) {
+          const int second = task >= per_plane;
+          const int q = second ? 1 : q0;
+          const int rem = task - (second ? per_plane : 0);
+          const int cx = 2 * (rem % ncp), c0 = (rem / ncp) * 8;
           const int* gi = GI(slot(q));
           float* nbf = NB(slot(q));
           float* sbf = SB(slot(q));
-          for (int task = tid; task < RXP * nseg; task += 256) {
-            const int cx = task % RXP, c0 = (task / RXP) * 8;
-            double rs[15];
+          double ra[15], rb[15];
 #pragma unroll
-            for (int j = 0; j < 15; ++j) {
-              const int y = c0 + j;
-              double a = 0.0;
-              if (y < rows) {
+          for (int jj = 0; jj < 15; ++jj) {
+            const int* row = gi + min(c0 + jj, rows - 1) * pitch + cx;
+            double sq[PS + 1];
 #pragma unroll
-                for (int b = 0; b < PS; ++b) {
-                  const double v = (double)gi[y * pitch + cx + b];
-                  a = fma(v, v, a);
-                }
-              }
-              rs[j] = a;
+            for (int b = 0; b <= PS; ++b) {
+              const double v = (double)row[b];
+              sq[b] = v * v;
             }
-            double nn = 0.0;
+            double a = 0.0;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) nn += rs[j];
+            for (int b = 0; b < PS; ++b) a += sq[b];
+            ra[jj] = a;
+            rb[jj] = a + (sq[PS] - sq[0]);
+          }
+          double na = 0.0, nb = 0.0;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-              const int cy = c0 + j;
-              if (cy < RYc) {
-                const float f = (float)nn;
-                nbf[cy * RXP + cx] = f;
-                if (SBS) sbf[cy * RXP + cx] = sqrtf(f);
+          for (int jj = 0; jj < 8; ++jj) {
+            na += ra[jj];
+            nb += rb[jj];
+          }
+#pragma unroll
+          for (int jj = 0; jj < 8; ++jj) {
+            const int cy = c0 + jj;
+            if (cy < RYc) {
+              const float fa = (float)na, fb = (float)nb;
+              nbf[cy * RXP + cx] = fa;
+              nbf[cy * RXP + cx + 1] = fb;
+              if (SBS) {
+                sbf[cy * RXP + cx] = sqrtf(fa);
+                sbf[cy * RXP + cx + 1] = sqrtf(fb);
               }
-              if (j < 7) nn += rs[j + 8] - rs[j];
+            }
+            if (jj < 7) {
+              na += ra[jj + 8] - ra[jj];
+              nb += rb[jj + 8] - rb[jj];
             }
           }
         }
@@ -532,37 +598,31 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
           continue;
         }
         const int py0 = ri[1], px0 = ri[2], ty0 = ri[3], tx0 = ri[5];
-        // keys of shortlist entries j[e] (entries past nsl read entry 0 and are dropped)
-        auto exact_keys = [&](auto& key, const int (&j)[sizeof(key) / 8])
-            __attribute__((always_inline)) {
-          constexpr int E = sizeof(key) / 8;
-          int cy[E], cx[E];
-          double dd[E];
+        // exact squared distance of shortlist entry pk over the patch rows
+        // [pb, pb + nr), in two FP64 accumulators (every partial sum is an
+        // exact integer, so the grouping leaves the result unchanged)
+        auto dist_rows = [&](unsigned pk, int pb, int nr) __attribute__((always_inline)) {
+          const int cy = (int)(pk >> 8), cx = (int)(pk & 255u);
+          double a0 = 0.0, a1 = 0.0;
+#pragma unroll 2
+          for (int r = 0; r < nr; ++r) {
+            const int* rr = gi + (py0 + pb + r) * pitch + px0;   // the reference's row
+            const int* cr = gi + (cy + pb + r) * pitch + cx;
 #pragma unroll
-          for (int e = 0; e < E; ++e) {
-            const unsigned pk = sl[t * SHORT_CAP + (j[e] < nsl ? j[e] : 0)];
-            cy[e] = (int)(pk >> 8);
-            cx[e] = (int)(pk & 255u);
-            dd[e] = 0.0;
+            for (int px = 0; px < PS; px += 2) {
+              const double u = (double)(rr[px] - cr[px]);
+              const double v = (double)(rr[px + 1] - cr[px + 1]);
+              a0 = fma(u, u, a0);
+              a1 = fma(v, v, a1);
+            }
           }
-#pragma unroll 1
-          for (int py = 0; py < PS; ++py) {
-            int rrow[PS];   // reference row (same address on every lane)
-#pragma unroll
-            for (int px = 0; px < PS; ++px) rrow[px] = gi[(py0 + py) * pitch + px0 + px];
-#pragma unroll
-            for (int e = 0; e < E; ++e)
-#pragma unroll
-              for (int px = 0; px < PS; ++px) {
-                const double df = (double)(rrow[px] - gi[(cy[e] + py) * pitch + cx[e] + px]);
-                dd[e] = fma(df, df, dd[e]);
-              }
-          }
-#pragma unroll
-          for (int e = 0; e < E; ++e)
-            key[e] = j[e] < nsl ? ((unsigned long long)dd[e] << 12) |
-                                      (unsigned)((cy[e] - ty0) * 64 + (cx[e] - tx0))
-                                : ~0ull;
+          return a0 + a1;
+        };
+        // key = distance << 12 | window index: distinct keys, so the rank of
+        // a key among the nsl keys is its slot (minus one)
+        auto make_key = [&](unsigned pk, double dd) __attribute__((always_inline)) {
+          const int cy = (int)(pk >> 8), cx = (int)(pk & 255u);
+          return ((unsigned long long)dd << 12) | (unsigned)((cy - ty0) * 64 + (cx - tx0));
         };
         auto emit = [&](int g, unsigned long long key) __attribute__((always_inline)) {
           const unsigned loc = (unsigned)(key & 0xFFFu);
@@ -571,25 +631,51 @@ __global__ __launch_bounds__(256, 2) void k_match(Launch L) {
           if (L.count_hist) atomicAdd(d.hist + cy * d.W + cx, 1);
           if (d.dist) d.dist[(size_t)ref * K + 1 + g] = (long long)(key >> 12);
         };
-        // Keys (distance << 12 | window index) are distinct: the rank of a
-        // key among the nsl keys is its slot (minus one); ranks are counted
-        // against every key, broadcast one by one.
-        auto bcast = [&](unsigned long long v, int src) __attribute__((always_inline)) {
-          const unsigned lo = __builtin_amdgcn_readlane((unsigned)v, src);
-          const unsigned hi = __builtin_amdgcn_readlane((unsigned)(v >> 32), src);
-          return ((unsigned long long)hi << 32) | lo;
-        };
-        if (nsl <= 64) {
-          unsigned long long key[1];
-          const int j[1] = {lane};
-          exact_keys(key, j);
+        // ranks are counted against every key: read back from this
+        // wavefront's LDS slots (one wavefront's LDS accesses complete in
+        // order), or broadcast lane by lane past 64 entries
+        unsigned long long* kb = keyb + wave * 64;
+        if (nsl <= 32) {
+          // lanes l and l + 32 share entry l % 32, each summing four patch
+          // rows and counting against half of the keys
+          const int e = lane & 31;
+          const bool hi = lane >= 32;
+          const unsigned pk = sl[t * SHORT_CAP + (e < nsl ? e : 0)];
+          double dd = dist_rows(pk, hi ? 4 : 0, 4);
+          dd += __longlong_as_double((long long)xor32_u64(
+              (unsigned long long)__double_as_longlong(dd), hi));
+          const unsigned long long key = e < nsl ? make_key(pk, dd) : ~0ull;
+          if (!hi) kb[e] = key;
+          wave_lds_sync();
           int rank = 0;
-          for (int o = 0; o < nsl; ++o) rank += bcast(key[0], o) < key[0] ? 1 : 0;
-          if (lane < nsl && rank < K - 1) emit(rank, key[0]);
+#pragma unroll
+          for (int o = 0; o < 16; ++o) rank += kb[(hi ? 16 : 0) + o] < key ? 1 : 0;
+          rank += (int)xor32_u32((unsigned)rank, hi);
+          if (!hi && e < nsl && rank < K - 1) emit(rank, key);
+        } else if (nsl <= 64) {
+          const unsigned pk = sl[t * SHORT_CAP + (lane < nsl ? lane : 0)];
+          const unsigned long long key = lane < nsl ? make_key(pk, dist_rows(pk, 0, PS)) : ~0ull;
+          kb[lane] = key;
+          wave_lds_sync();
+          int rank = 0;
+          for (int o0 = 0; o0 < nsl; o0 += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) rank += kb[o0 + u] < key ? 1 : 0;
+          }
+          if (lane < nsl && rank < K - 1) emit(rank, key);
         } else {
           unsigned long long key[2];
-          const int j[2] = {lane, 64 + lane};
-          exact_keys(key, j);
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int j = 64 * h + lane;
+            const unsigned pk = sl[t * SHORT_CAP + (j < nsl ? j : 0)];
+            key[h] = j < nsl ? make_key(pk, dist_rows(pk, 0, PS)) : ~0ull;
+          }
+          auto bcast = [&](unsigned long long v, int src) __attribute__((always_inline)) {
+            const unsigned lo = __builtin_amdgcn_readlane((unsigned)v, src);
+            const unsigned hi = __builtin_amdgcn_readlane((unsigned)(v >> 32), src);
+            return ((unsigned long long)hi << 32) | lo;
+          };
           int rank0 = 0, rank1 = 0;
           for (int o = 0; o < nsl; ++o) {
             const unsigned long long ko = bcast(o < 64 ? key[0] : key[1], o & 63);

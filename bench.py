@@ -153,12 +153,12 @@ PROFILE_SOURCES = ["paper_2508_10307_amd/csrc/k_filter.hip",
 # they were taken on (profiles/ has the summaries and commands).
 PROFILED = {
     "void hts::k_filter<3, 4, 0, 0, 1, 0, 0>(hts::Launch)":
-        ("b9a99083910e8be935a022eee1e7019d79d6d99437b4c8bb56b976afe448e7da",
-         {98: {"hbm_bytes": 9722924411}, 99: {"hbm_bytes": 20356628487}}),
+        ("159baa1bb7ec83d6d6261c52eba2af173a7732655887942335b43be326e330c7",
+         {98: {"hbm_bytes": 9713018538}, 99: {"hbm_bytes": 20358593578}}),
     "void hts::k_match<0, 3, 1, 2, 1>(hts::Launch)":
-        ("b9a99083910e8be935a022eee1e7019d79d6d99437b4c8bb56b976afe448e7da",
-         {98: {"hbm_bytes": 2064443789, "mfma_util_pct": 6.17},
-          99: {"hbm_bytes": 2064345933, "mfma_util_pct": 6.19}}),
+        ("159baa1bb7ec83d6d6261c52eba2af173a7732655887942335b43be326e330c7",
+         {98: {"hbm_bytes": 2069796530, "mfma_util_pct": 7.15},
+          99: {"hbm_bytes": 2069851140, "mfma_util_pct": 7.15}}),
 }
 
 

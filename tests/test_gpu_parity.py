@@ -181,6 +181,32 @@ def test_shortlist_histogram_accounts_for_every_reference(mode):
     assert int(h[p.K - 1:129].sum()) > 0
 
 
+@pytest.mark.parametrize("mode", [0, 1], ids=["bf16", "fp32"])
+@pytest.mark.parametrize("C", [1, 3])
+def test_rerank_branches_bit_exact(C, mode):
+    """The exact re-rank takes three forms by shortlist size (at most 32
+    entries: split over the two wavefront halves; 33..64: one entry per lane;
+    65..128: two per lane).  A textured band, a checkerboard band (half of a
+    window ties at distance 0) and a flat band (every candidate ties) give
+    references of all three sizes, which the histogram confirms; indices and
+    distances equal the oracle's."""
+    H, W = 40, 72
+    y = synth.tiny(71, C, H, W, sigma=25.0, n_blobs=6)
+    y[:, :, 24:48] = _two_level(C, H, 24)
+    y[:, :, 48:] = 90.0
+    p = P(stride=3, window=11, K=32, match_mode=mode)
+    h = api.hts_batch_shortlist_histogram(p, [T(y)]).cpu().numpy()
+    log("rerank branches", C, mode, "<=32:", int(h[:33].sum()), "33..64:", int(h[33:65].sum()),
+        "65..128:", int(h[65:129].sum()), "overflow:", int(h[129]))
+    assert int(h[:33].sum()) > 0 and int(h[33:65].sum()) > 0 and int(h[65:129].sum()) > 0
+    assert int(h[129]) == 0
+    idx_o, dist_o, _ = omatch.match(y, 8, p.stride, p.window, p.K)
+    idx, dist = api.hts_match(T(y), p, want_dist=True)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(idx.cpu().numpy(), idx_o)
+    np.testing.assert_array_equal(dist.cpu().numpy(), dist_o)
+
+
 def test_match_mixed_guide_planes_repeatable():
     # RGB tiles whose references mix the green and the R+G+B guide are
     # matched plane by plane; the references of the other plane must not

@@ -69,51 +69,67 @@ hipError_t launch_filter(const Launch& L, int ty, int tx, int adjoint, int grid,
 }
 
 // Row projections (the first product of the filter's t-SVD projection,
-// hoisted out of the group loop): one thread per (row y, column start x),
-// x < Wp.  The row's 8 pixels of every channel go through the channel DFT
-// and the products with the V slices in exactly the order the filter used
-// to apply them per slot, so every estimate keeps its bits.  A non-finite
-// pixel makes all 8 C values of every row window over it non-finite (each
-// V column has a non-zero entry), which the filter's poison check sees.
+// hoisted out of the group loop): one thread per output position (row y,
+// column start x < Wp), taken in the order of the [H][Wp] output.  The
+// row's 8 pixels of every channel go through the channel DFT and the
+// products with the V slices in exactly the order the filter used to apply
+// them per slot, so every estimate keeps its bits.  A non-finite pixel
+// makes all 8 C values of every row window over it non-finite (each V
+// column has a non-zero entry), which the filter's poison check sees.
+// A work group's 256 consecutive positions have one contiguous output
+// range: their values are staged in LDS and written out in 16-byte pieces
+// by consecutive lanes (written directly, each lane's 8 C values would
+// spread one store instruction over dozens of cache lines).
 template <int C>
 __global__ __launch_bounds__(256) void k_rowproj(Launch L) {
+  constexpr int NF = 8 * C;   // floats per position
+  __shared__ __align__(16) float stage[256 * NF];
   for_each_item<W_PIX>(L, [&](const ImgDesc& d, int item) __attribute__((always_inline)) {
     const int HW = d.H * d.W;
-    const int p0 = item * PIX_CHUNK;
-    const int p1 = min(HW, p0 + PIX_CHUNK);
+    const int NQ = d.H * d.Wp;
+    const int q0 = item * PIX_CHUNK;
+    const int q1 = min(NQ, q0 + PIX_CHUNK);
     const cfloat* fb = uniform_ptr(d.fbasis);
-    for (int p = p0 + (int)threadIdx.x; p < p1; p += blockDim.x) {
-      const int y = p / d.W, x = p - y * d.W;
-      if (x >= d.Wp) continue;
-      const float* src = d.img + (size_t)y * d.W + x;
-      float* dst = d.rowp + ((size_t)y * d.Wp + x) * (8 * C);
-      if (C == 1) {
-        float xr[8], yv[8];
+    for (int qb = q0; qb < q1; qb += blockDim.x) {
+      const int q = qb + (int)threadIdx.x;
+      if (q < q1) {
+        const int y = q / d.Wp, x = q - y * d.Wp;
+        const float* src = d.img + (size_t)y * d.W + x;
+        float* dst = stage + threadIdx.x * NF;
+        if (C == 1) {
+          float xr[8], yv[8];
 #pragma unroll
-        for (int b = 0; b < 8; ++b) xr[b] = src[b];
-        mv<false>(xr, fb, FB_V0T, 1.f, yv);   // y[b] = sum_t x[t] V[t][b]
+          for (int b = 0; b < 8; ++b) xr[b] = src[b];
+          mv<false>(xr, fb, FB_V0T, 1.f, yv);   // y[b] = sum_t x[t] V[t][b]
 #pragma unroll
-        for (int b = 0; b < 8; ++b) dst[b] = yv[b];
-      } else {
-        float f0[8], f1r[8], f1i[8];
+          for (int b = 0; b < 8; ++b) dst[b] = yv[b];
+        } else {
+          float f0[8], f1r[8], f1i[8];
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-          const float q0 = src[b], q1 = src[HW + b], q2 = src[2 * HW + b];
-          f0[b] = q0 + q1 + q2;
-          f1r[b] = q0 - 0.5f * (q1 + q2);
-          f1i[b] = HALF_SQRT3 * (q2 - q1);
-        }
-        float y0[8], y1r[8], y1i[8];
-        mv<false>(f0, fb, FB_V0T, 1.f, y0);
-        // y1 = V_F(1)^T P^(1) per row: (V1R + i V1I)^T (f1r + i f1i)
-        cmv(f1r, f1i, fb, FB_V1RT, FB_V1IT, 1.f, FB_V1PT, y1r, y1i);
+          for (int b = 0; b < 8; ++b) {
+            const float q0v = src[b], q1v = src[HW + b], q2v = src[2 * HW + b];
+            f0[b] = q0v + q1v + q2v;
+            f1r[b] = q0v - 0.5f * (q1v + q2v);
+            f1i[b] = HALF_SQRT3 * (q2v - q1v);
+          }
+          float y0[8], y1r[8], y1i[8];
+          mv<false>(f0, fb, FB_V0T, 1.f, y0);
+          // y1 = V_F(1)^T P^(1) per row: (V1R + i V1I)^T (f1r + i f1i)
+          cmv(f1r, f1i, fb, FB_V1RT, FB_V1IT, 1.f, FB_V1PT, y1r, y1i);
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-          dst[b] = y0[b];
-          dst[8 + b] = y1r[b];
-          dst[16 + b] = y1i[b];
+          for (int b = 0; b < 8; ++b) {
+            dst[b] = y0[b];
+            dst[8 + b] = y1r[b];
+            dst[16 + b] = y1i[b];
+          }
         }
       }
+      __syncthreads();
+      const int n4 = min((int)blockDim.x, q1 - qb) * (NF / 4);
+      const float4* s4 = (const float4*)stage;
+      float4* d4 = (float4*)(d.rowp + (size_t)qb * NF);
+      for (int i = threadIdx.x; i < n4; i += blockDim.x) d4[i] = s4[i];
+      __syncthreads();
     }
   });
 }

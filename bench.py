@@ -153,12 +153,12 @@ PROFILE_SOURCES = ["paper_2508_10307_amd/csrc/k_filter.hip",
 # they were taken on (profiles/ has the summaries and commands).
 PROFILED = {
     "void hts::k_filter<3, 4, 0, 0, 1, 0, 0>(hts::Launch)":
-        ("159baa1bb7ec83d6d6261c52eba2af173a7732655887942335b43be326e330c7",
-         {98: {"hbm_bytes": 9713018538}, 99: {"hbm_bytes": 20358593578}}),
+        ("eeca3b69d949b8ca88578c356866862c2805b21d41319b88492ce38c2a79e265",
+         {98: {"hbm_bytes": 9715732495}, 99: {"hbm_bytes": 20313362689}}),
     "void hts::k_match<0, 3, 1, 2, 1>(hts::Launch)":
-        ("159baa1bb7ec83d6d6261c52eba2af173a7732655887942335b43be326e330c7",
-         {98: {"hbm_bytes": 2069796530, "mfma_util_pct": 7.15},
-          99: {"hbm_bytes": 2069851140, "mfma_util_pct": 7.15}}),
+        ("eeca3b69d949b8ca88578c356866862c2805b21d41319b88492ce38c2a79e265",
+         {98: {"hbm_bytes": 2069823608, "mfma_util_pct": 7.15},
+          99: {"hbm_bytes": 2070013289, "mfma_util_pct": 7.16}}),
 }
 
 

@@ -57,9 +57,20 @@ __global__ __launch_bounds__(256) void k_cov(Launch L) {
     const int RW = ref_coord(ix0 + tx - 1, s, d.Wp) + PS - X0;
     const int RP = RH * RW;
     __syncthreads();   // the previous item's references still read px
-    for (int e = tid; e < L.C * RP; e += 256) {
-      const int ch = e / RP, rem = e - ch * RP, y = rem / RW, x = rem - y * RW;
-      px[e] = d.img[ch * HW + (Y0 + y) * d.W + X0 + x];
+    // eight loads per thread in flight before the first wait (indices past
+    // the region repeat its last element and are not stored)
+    const int NE = L.C * RP;
+    for (int e0 = tid; e0 < NE; e0 += 256 * 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = min(e0 + 256 * u, NE - 1);
+        const int ch = e / RP, rem = e - ch * RP, y = rem / RW, x = rem - y * RW;
+        v[u] = d.img[ch * HW + (Y0 + y) * d.W + X0 + x];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (e0 + 256 * u < NE) px[e0 + 256 * u] = v[u];
     }
     __syncthreads();
     d4 gu1 = {0.0, 0.0, 0.0, 0.0}, gv1 = gu1, gu0 = gu1, gv0 = gu1;

@@ -126,13 +126,23 @@ __device__ inline void transpose_cr(float* T, int kl, int a, float (&v)[8]) {
   wave_sync();
 }
 
-// Value of the lane with slot lane kl ^ m (lane ^ 8m): a DPP rotation by 8
-// within each 16-lane row for m = 1, ds_bpermute beyond.
-__device__ inline float xor_slot_lane(float v, int m) {
-  if (m == 1)
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128 /* row_ror:8 */,
-                                                      0xF, 0xF, false));
-  return __shfl_xor(v, 8 * m, 64);
+// One Haar butterfly across slot lanes kl and kl ^ m (lanes l and l ^ 8m):
+// the lower lane keeps x_lo + x_hi, the upper x_lo - x_hi (sg = +1 / -1).
+// m = 1: the partner by a DPP rotation by 8 within each 16-lane row.
+// m = 2, 4: v_permlane16_swap / v_permlane32_swap of the value with itself
+// leaves, in every lane of the pair, the lower lane's value in the first
+// result and the upper lane's in the second, with no trip through LDS.
+// Both lanes of a pair are active or inactive together.
+__device__ inline float haar_xlane(float x, int m, float sg) {
+  if (m == 1) {
+    const float o = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128 /* row_ror:8 */,
+                                                               0xF, 0xF, false));
+    return fmaf(sg, x, o);
+  }
+  const unsigned b = __float_as_uint(x);
+  const auto r = m == 2 ? __builtin_amdgcn_permlane16_swap(b, b, false, false)
+                        : __builtin_amdgcn_permlane32_swap(b, b, false, false);
+  return fmaf(sg, __uint_as_float(r[1]), __uint_as_float(r[0]));
 }
 
 // Haar row (Eq. 9 ordering) of the coefficient produced for group slot k.
@@ -344,7 +354,7 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
 #pragma unroll
           for (int ch = 0; ch < C; ++ch)
 #pragma unroll
-            for (int i = 0; i < 8; ++i) X[0][ch][i] = fmaf(sg, X[0][ch][i], xor_slot_lane(X[0][ch][i], m));
+            for (int i = 0; i < 8; ++i) X[0][ch][i] = haar_xlane(X[0][ch][i], m, sg);
         }
       }
 
@@ -427,7 +437,7 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
 #pragma unroll
           for (int ch = 0; ch < C; ++ch)
 #pragma unroll
-            for (int i = 0; i < 8; ++i) X[0][ch][i] = fmaf(sg, X[0][ch][i], xor_slot_lane(X[0][ch][i], m));
+            for (int i = 0; i < 8; ++i) X[0][ch][i] = haar_xlane(X[0][ch][i], m, sg);
         }
       }
 #pragma unroll

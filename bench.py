@@ -153,12 +153,12 @@ PROFILE_SOURCES = ["paper_2508_10307_amd/csrc/k_filter.hip",
 # they were taken on (profiles/ has the summaries and commands).
 PROFILED = {
     "void hts::k_filter<3, 4, 0, 0, 1, 0, 0>(hts::Launch)":
-        ("eeca3b69d949b8ca88578c356866862c2805b21d41319b88492ce38c2a79e265",
-         {98: {"hbm_bytes": 9715732495}, 99: {"hbm_bytes": 20313362689}}),
+        ("9bed67d05a65e91773f73074f0c8193f61d9f067ec1b50b5bafb3afcde438055",
+         {98: {"hbm_bytes": 9698717827}, 99: {"hbm_bytes": 19957666857}}),
     "void hts::k_match<0, 3, 1, 2, 1>(hts::Launch)":
-        ("eeca3b69d949b8ca88578c356866862c2805b21d41319b88492ce38c2a79e265",
-         {98: {"hbm_bytes": 2069823608, "mfma_util_pct": 7.15},
-          99: {"hbm_bytes": 2070013289, "mfma_util_pct": 7.16}}),
+        ("9bed67d05a65e91773f73074f0c8193f61d9f067ec1b50b5bafb3afcde438055",
+         {98: {"hbm_bytes": 2069826909, "mfma_util_pct": 7.18},
+          99: {"hbm_bytes": 2069849094, "mfma_util_pct": 7.17}}),
 }
 
 

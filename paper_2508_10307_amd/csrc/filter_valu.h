@@ -240,9 +240,27 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
     }
 
     const int ngroups = (iy1 - iy0 + 1) * (ix1 - ix0 + 1);
+    const int gw = ix1 - ix0 + 1;
+    auto group_of = [&](int gl) __attribute__((always_inline)) {
+      return (iy0 + gl / gw) * d.nrx + ix0 + gl % gw;
+    };
+    // the idx entries of the wavefront's next group are loaded one group
+    // ahead (inactive lanes, K < 8, read slot 0 and drop it)
+    auto load_pos = [&](int gl, int (&pos)[SPL]) __attribute__((always_inline)) {
+      const int gn = gl < ngroups ? group_of(gl) : -1;
+      const bool ok = gn >= d.ref_begin && gn < d.ref_begin + d.ref_count;
+#pragma unroll
+      for (int j = 0; j < SPL; ++j)
+        pos[j] = ok ? d.idx[(size_t)gn * K + (active ? kl * SPL + j : 0)] : 0;
+    };
+    int pos_next[SPL];
+    load_pos(wave, pos_next);
     for (int gl = wave; gl < ngroups; gl += 4) {
-      const int gw = ix1 - ix0 + 1;
-      const int g = (iy0 + gl / gw) * d.nrx + ix0 + gl % gw;
+      const int g = group_of(gl);
+      int pos_cur[SPL];
+#pragma unroll
+      for (int j = 0; j < SPL; ++j) pos_cur[j] = pos_next[j];
+      load_pos(gl + 4, pos_next);
       if (g < d.ref_begin || g >= d.ref_begin + d.ref_count) continue;
       const int grel = g - d.ref_begin;
 
@@ -258,11 +276,8 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
       int py[SPL], px[SPL];
 #pragma unroll
       for (int j = 0; j < SPL; ++j) {
-        const int k = kl * SPL + j;
-        // inactive lanes (K < 8) read slot 0 and drop it; loads stay unconditional
-        const int pos = d.idx[(size_t)g * K + (active ? k : 0)];
         // positions come from the caller's idx: clamp to valid patch corners
-        split_pos(pos, d.W, rW, py[j], px[j]);
+        split_pos(pos_cur[j], d.W, rW, py[j], px[j]);
         py[j] = min(max(py[j], 0), d.Hp - 1);
         px[j] = min(max(px[j], 0), d.Wp - 1);
         const float4* src =

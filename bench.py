@@ -153,12 +153,12 @@ PROFILE_SOURCES = ["paper_2508_10307_amd/csrc/k_filter.hip",
 # they were taken on (profiles/ has the summaries and commands).
 PROFILED = {
     "void hts::k_filter<3, 4, 0, 0, 1, 0, 0>(hts::Launch)":
-        ("9bed67d05a65e91773f73074f0c8193f61d9f067ec1b50b5bafb3afcde438055",
-         {98: {"hbm_bytes": 9698717827}, 99: {"hbm_bytes": 19957666857}}),
+        ("16b0763347fa37f9c01028df1b75f0a906c27b5a223a80eff5bd8aa59842ee8f",
+         {98: {"hbm_bytes": 10253780366}, 99: {"hbm_bytes": 21351831871}}),
     "void hts::k_match<0, 3, 1, 2, 1>(hts::Launch)":
-        ("9bed67d05a65e91773f73074f0c8193f61d9f067ec1b50b5bafb3afcde438055",
-         {98: {"hbm_bytes": 2069826909, "mfma_util_pct": 7.18},
-          99: {"hbm_bytes": 2069849094, "mfma_util_pct": 7.17}}),
+        ("16b0763347fa37f9c01028df1b75f0a906c27b5a223a80eff5bd8aa59842ee8f",
+         {98: {"hbm_bytes": 2069961434, "mfma_util_pct": 7.18},
+          99: {"hbm_bytes": 2069904375, "mfma_util_pct": 7.18}}),
 }
 
 

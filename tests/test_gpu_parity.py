@@ -59,6 +59,10 @@ MATCH_CASES = [
     ("gray70x53_w31", 1, 70, 53, 3, 31, 32),
     ("rgb64x61_s2_w39", 3, 64, 61, 2, 39, 32),
     ("gray40x40_w63", 1, 40, 40, 5, 63, 64),
+    # RGB with a window too large for two guide-plane slots in LDS (the
+    # planes run one after the other) and for the cached bounds (pass 2
+    # recomputes the tiles)
+    ("rgb48x44_w51_one_plane_slot", 3, 48, 44, 3, 51, 16),
 ]
 
 

@@ -153,12 +153,12 @@ PROFILE_SOURCES = ["paper_2508_10307_amd/csrc/k_filter.hip",
 # they were taken on (profiles/ has the summaries and commands).
 PROFILED = {
     "void hts::k_filter<3, 4, 0, 0, 1, 0, 0>(hts::Launch)":
-        ("16b0763347fa37f9c01028df1b75f0a906c27b5a223a80eff5bd8aa59842ee8f",
-         {98: {"hbm_bytes": 10253780366}, 99: {"hbm_bytes": 21351831871}}),
+        ("79c10ab9f9996dcaba7fbd2f198cb0565bf61e4538c33d6c2b2330ebde59b533",
+         {98: {"hbm_bytes": 10257854557}, 99: {"hbm_bytes": 21324466303}}),
     "void hts::k_match<0, 3, 1, 2, 1>(hts::Launch)":
-        ("16b0763347fa37f9c01028df1b75f0a906c27b5a223a80eff5bd8aa59842ee8f",
-         {98: {"hbm_bytes": 2069961434, "mfma_util_pct": 7.18},
-          99: {"hbm_bytes": 2069904375, "mfma_util_pct": 7.18}}),
+        ("79c10ab9f9996dcaba7fbd2f198cb0565bf61e4538c33d6c2b2330ebde59b533",
+         {98: {"hbm_bytes": 2070012514, "mfma_util_pct": 7.13},
+          99: {"hbm_bytes": 2069895960, "mfma_util_pct": 7.13}}),
 }
 
 

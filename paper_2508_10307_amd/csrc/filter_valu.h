@@ -297,7 +297,6 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
       // ---- t-SVD projection U^T * P * V per slot (Eq. 18, patch level) ----
 #pragma unroll
       for (int j = 0; j < SPL; ++j) {
-        __builtin_amdgcn_sched_barrier(0);  // keep one slot's temporaries live at a time
         if (C == 1) {
           // y = row a of P V (a non-finite pixel makes it non-finite)
           float y[8];
@@ -482,7 +481,6 @@ __global__ __launch_bounds__(256, 2) void k_filter(Launch L) {
       // write-back.
 #pragma unroll
       for (int j = 0; j < SPL; ++j) {
-        __builtin_amdgcn_sched_barrier(0);  // keep one slot's temporaries live at a time
         float out[C][8];
         if (C == 1) {
           float y[8];

@@ -124,7 +124,8 @@ def match_kernel_name(C, s, w, mode, terms):
         pitch += ((8 - pitch) % 16 + 16) % 16
         rgn = (ry2 + 7) * pitch * 4
         plane = 2 * rgn + (2 if sbs else 1) * ry2 * rxp * 4
-        return npl * plane + max(16 * 64 * 2 * 4, 16 * 128 * 4) + 768, ryc, rxp
+        # lists / shortlist, per-reference data, re-rank keys [4][64]
+        return npl * plane + max(16 * 64 * 2 * 4, 16 * 128 * 4) + 768 + 4 * 64 * 8, ryc, rxp
     npl, sbs = 1, 1
     if C == 3 and geom(2, 1)[0] <= 80 * 1024:
         npl = 2

@@ -175,6 +175,25 @@ def test_calls_reject_null_pointers_and_small_workspace(lib):
     assert sh(bp, imgs, 1, FAKE, 16, FAKE, None) == L.HTS_ERR_WORKSPACE
 
 
+def test_batch_plan_validation(lib):
+    """Batch sizing rejects an empty batch, a null image list, images of
+    different channel counts and an image smaller than one patch (no GPU
+    call is made)."""
+    p = api.Params().c()
+    bp = ctypes.byref(p)
+    n = L.c_sz()
+    one = (L.HtsImage * 1)(L.HtsImage(FAKE.value, FAKE.value, 3, 64, 64, 10.0))
+    assert lib.hts_batch_workspace_size(bp, one, 1, ctypes.byref(n)) == L.HTS_OK and n.value > 0
+    assert lib.hts_batch_workspace_size(bp, one, 0, ctypes.byref(n)) == L.HTS_ERR_INVALID
+    assert lib.hts_batch_workspace_size(bp, None, 1, ctypes.byref(n)) == L.HTS_ERR_INVALID
+    mixed = (L.HtsImage * 2)(L.HtsImage(FAKE.value, FAKE.value, 3, 64, 64, 10.0),
+                             L.HtsImage(FAKE.value, FAKE.value, 1, 64, 64, 10.0))
+    assert lib.hts_batch_workspace_size(bp, mixed, 2, ctypes.byref(n)) == L.HTS_ERR_INVALID
+    tiny = (L.HtsImage * 2)(L.HtsImage(FAKE.value, FAKE.value, 3, 64, 64, 10.0),
+                            L.HtsImage(FAKE.value, FAKE.value, 3, 7, 64, 10.0))
+    assert lib.hts_batch_workspace_size(bp, tiny, 2, ctypes.byref(n)) == L.HTS_ERR_INVALID
+
+
 def test_workspace_grows_with_image():
     p = api.Params(stride=3, window=31, K=32)
     a = api.workspace_size(p, 3, 256, 256)

@@ -370,3 +370,26 @@ def test_batch_save_and_backward_gray(K):
         _state_equal(states[i], st)
         ref, _ = api.hts_denoise_backward(gs[i], st, p)
         assert torch.equal(gins[i], ref)
+
+
+@pytest.mark.parametrize("C", [1, 3])
+def test_batch_with_degenerate_images(C):
+    """Images with a single row or column of patch positions, or a 2 x 2
+    position grid (every reference has exactly K candidates), batched with
+    an ordinary image: each output equals the per-image call bit for bit, and
+    the per-image match indices equal the oracle's."""
+    p = api.Params(stride=1, window=7, K=4)
+    shapes = [(C, 9, 9), (C, 8, 30), (C, 30, 8), (C, 40, 33)]
+    ys = [synth.tiny(900 + i, *sh, sigma=15.0, n_blobs=2) for i, sh in enumerate(shapes)]
+    sig = [15.0, 10.0, 20.0, 15.0]
+    xs = [T(y) for y in ys]
+    outs = api.hts_denoise_batch(xs, sig, p)
+    torch.cuda.synchronize()
+    for i, (y, s) in enumerate(zip(ys, sig)):
+        log("degenerate batch", C, shapes[i])
+        ref = api.hts_denoise(T(y), s, p)
+        assert torch.equal(outs[i], ref)
+        assert torch.isfinite(outs[i]).all()
+        idx_o, _, _ = omatch.match(y, 8, p.stride, p.window, p.K)
+        idx = api.hts_match(T(y), p)
+        np.testing.assert_array_equal(idx.cpu().numpy(), idx_o)
